@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the opsp SpGEMM hot path on one MI355X.
+
+One step = one full C = A*B through the C ABI (``opsp_spgemm``: setup,
+both binnings, symbolic, scan, allocation of C, numeric, release of C), on
+inputs already resident in HBM.  The default workload is the 3-D 27-point
+stencil on a 100^3 grid, values U[-1,1) from seed 27, C = A^2.
+
+Metric (OpSparse Section 6): GFLOPS = 2 * n_prod / time, FP64.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SpGEMM GFLOPS (2·nprod/s) C=A², FP64, + % HBM roofline; learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def numeric_bytes(M, nnzA, nprod, nnzC):
+    """Algorithmic HBM bytes of the numeric step (one launch over all rows):
+    A col+val 12 B/entry and B row bounds 16 B per A entry; B col+val 12 B per
+    intermediate product; C col+val 12 B per output; C.rpt 16 B and row id
+    8 B per row."""
+    return 12 * nprod + 28 * nnzA + 12 * nnzC + 24 * M
+
+
+def symbolic_bytes(M, nnzA, nprod):
+    """Symbolic step: A col 4 B + B row bounds 16 B per A entry, B col 4 B per
+    product, n_prod read + nnz written 16 B per row, row id 8 B per row."""
+    return 4 * nprod + 20 * nnzA + 24 * M
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="st27_100")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "row-panel design is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synthetic as syn
+    import paper_2206_07244_amd as ops
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    desc, builder = syn.WORKLOADS[args.workload]
+    t0 = time.time()
+    A = builder()
+    log(f"workload {args.workload}: {A.rows} rows, {A.nnz} nnz, generated in {time.time() - t0:.1f}s")
+    dA = ops.DeviceCSR.from_host(A, dev)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    Ac = dA._c_fast(A.nnz)
+
+    # warm-up (also fills the memory pool)
+    st = ops.Stats()
+    for _ in range(max(args.warmup, 1)):
+        Cc = ops.opsp_csr()
+        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), None,
+                                        ops.byref(st), sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_ex")
+        ops.free_raw(Cc, sh)
+    torch.cuda.synchronize()
+    nprod, nnzC = st.nprod, st.nnz
+    log(f"n_prod={nprod} nnz(C)={nnzC} CR={nprod / max(nnzC, 1):.3f} bins sym={list(st.sym_bin_rows)} "
+        f"num={list(st.num_bin_rows)}")
+
+    # timed region: K whole products
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        Cc = ops.spgemm_raw(Ac, Ac, sh)
+        ops.free_raw(Cc, sh)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms = (t2 - t1) * 1e3 / args.steps
+    gflops = 2.0 * nprod / (ms * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step, {gflops:.1f} GFLOPS")
+
+    # per-stage kernel durations: same calls, HIP events recorded on the call's
+    # stream between stages (stage 1 = symbolic kernels, 3 = numeric kernels)
+    cfg = ops.Config(stage_timing=1)
+    stage = np.zeros(8)
+    for _ in range(args.steps):
+        Cc = ops.opsp_csr()
+        s2 = ops.Stats()
+        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), ops.byref(cfg),
+                                        ops.byref(s2), sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_ex")
+        ops.free_raw(Cc, sh)
+        stage += np.array(list(s2.ms_stage))
+    torch.cuda.synchronize()
+    stage /= args.steps
+    log("stage ms (setup+bin, symbolic, numbin+scan, numeric, total):",
+        [round(x, 4) for x in stage[:5]])
+
+    M, nnzA = A.rows, A.nnz
+    nb = numeric_bytes(M, nnzA, nprod, nnzC)
+    sb = symbolic_bytes(M, nnzA, nprod)
+    num_ms, sym_ms = stage[3], stage[1]
+    if num_ms >= sym_ms:
+        kernel, bytes_, kms = "numeric", nb, num_ms
+    else:
+        kernel, bytes_, kms = "symbolic", sb, sym_ms
+    achieved = bytes_ / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 3),
+        "unit": "GFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "rows": M, "nnzA": nnzA,
+                   "nprod": nprod, "nnzC": nnzC, "path": "plain two-pass"},
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes": bytes_, "kernel_ms": round(kms, 4)},
+        "stage_ms": {"setup_bin": round(stage[0], 4), "symbolic": round(stage[1], 4),
+                     "numbin_scan_alloc": round(stage[2], 4), "numeric": round(stage[3], 4),
+                     "total": round(stage[4], 4)},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        reps, el = 0, 0.0
+        tc = time.perf_counter()
+        while reps == 0 or (el < args.cpu_seconds and reps < 3):
+            oracle.spgemm(A, A, with_scale=False)
+            reps += 1
+            el = time.perf_counter() - tc
+        cpu_gflops = 2.0 * nprod * reps / el / 1e9
+        out["cpu_baseline"] = {"value": round(cpu_gflops, 4), "unit": "GFLOPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"whole {args.workload} product, {reps} run(s), {el:.1f}s, "
+                                         "single-threaded C oracle (symbolic + numeric)"}
+        log(f"cpu oracle: {cpu_gflops:.3f} GFLOPS over {reps} run(s)")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * opsp - row-wise sparse general matrix multiplication C = A * B on AMD
+ * Instinct MI355X (gfx950), after OpSparse (Du et al., arXiv 2206.07244).
+ *
+ * C ABI.  No HIP or torch types appear in any signature: streams are passed
+ * as `void*` (a hipStream_t, NULL = the default stream) and every matrix
+ * array is a plain device pointer.
+ *
+ * Matrix format (Section 2.1.1, CSR): `rpt` int64[rows+1] holds absolute
+ * offsets into `col` int32[nnz] and `val` double[nnz]; rpt[0] need not be 0,
+ * so a range of rows of a matrix is itself a valid matrix (a zero-copy
+ * view).  Inputs must be canonical: column indices strictly ascending inside
+ * each row, all in [0, cols).  Outputs are canonical with rpt[0] == 0.
+ *
+ * Result definition (Section 2.1, Eq. 1 / Eq. 2): C_ij = sum_k A_ik * B_kj
+ * over the *structural* product, i.e. C holds every (i,j) for which some k
+ * has both A_ik and B_kj stored, even when the sum is exactly zero
+ * (the symbolic step of Section 2.2 sees indices only).  Values are FP64 and
+ * summed in an unspecified order (hash-table atomics), so they may differ
+ * from a sequential sum in the last bits; rows and columns are exact.
+ *
+ * Errors: every call returns an opsp_status; nothing throws across the ABI.
+ * On error no memory stays allocated by the call and *C is zeroed.
+ * Thread safety: calls on distinct streams may run concurrently from
+ * different host threads.
+ */
+#ifndef OPSP_H
+#define OPSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OPSP_OK = 0,
+    OPSP_ERR_INVALID = 1,   /* NULL pointer, negative size, bad argument, non-canonical input (validation mode) */
+    OPSP_ERR_SHAPE = 2,     /* A.cols != B.rows, or a size beyond the index types */
+    OPSP_ERR_ALLOC = 3,     /* device allocation failed */
+    OPSP_ERR_OVERFLOW = 4,  /* a count exceeds its index type (e.g. a row of C above 2^31-1 entries) */
+    OPSP_ERR_HIP = 5,       /* a HIP runtime call or kernel launch failed */
+    OPSP_ERR_INTERNAL = 6,  /* internal consistency check failed */
+    OPSP_ERR_NO_DEVICE = 7  /* no usable gfx950 device */
+} opsp_status;
+
+/* A CSR matrix in device memory (see the format note above). */
+typedef struct {
+    int64_t rows, cols, nnz;
+    int64_t *rpt;
+    int32_t *col;
+    double *val;
+} opsp_csr;
+
+/* Number of bins per step.  Symbolic: bins 0..7 use workgroup-local (LDS)
+ * hash tables, and rows of bin 7 whose count crosses the abort threshold are
+ * recomputed in global-memory tables ("bin 8").  Numeric: bins 0..6 use LDS
+ * tables, bin 7 global-memory tables (Section 5.6, Tables of kernel
+ * configuration). */
+#define OPSP_SYM_BINS 9
+#define OPSP_NUM_BINS 8
+
+/* Optional tuning / test controls.  Pass NULL for the defaults.
+ * Set `version` to OPSP_CONFIG_VERSION; zero-initialised fields take their
+ * defaults. */
+#define OPSP_CONFIG_VERSION 1
+typedef struct {
+    int32_t version;
+    /* Binning ratio (Section 5.7): a row goes to the first table whose size is
+     * at least `ratio` x its n_prod (symbolic) or nnz (numeric).
+     * 0 = defaults 1.2 (symbolic) and 2.0 (numeric).  Must be >= 1. */
+    double sym_ratio;
+    double num_ratio;
+    /* Route every row that fits bin b (value <= the bin's upper bound) to
+     * bin b instead of its natural bin; larger rows keep their natural bin.
+     * -1 = off.  Symbolic b in 0..8 (8 = global tables), numeric 0..7. */
+    int32_t force_sym_bin;
+    int32_t force_num_bin;
+    /* Fraction of the largest symbolic LDS table at which a row is abandoned
+     * and recomputed with a global table (Section 5.6.1: 0.8).  0 = default
+     * 0.8; a negative value means "abort every row of that bin". */
+    double sym_abort_fraction;
+    /* Lanes that stream one row of B (power of two 1..64); 0 = chosen from
+     * the mean row length of B. */
+    int32_t b_lanes;
+    /* Record per-stage times in opsp_stats.ms_stage (adds device syncs). */
+    int32_t stage_timing;
+    /* Run the (slow) device-side input validation first. */
+    int32_t validate;
+} opsp_config;
+
+/* Counters of one call (filled when a stats pointer is given). */
+typedef struct {
+    int64_t nprod;                         /* total intermediate products, sum_i n_prod_i */
+    int64_t nnz;                           /* nnz(C) */
+    int64_t max_row_nprod;
+    int64_t max_row_nnz;
+    int64_t sym_bin_rows[OPSP_SYM_BINS];   /* rows per symbolic bin; [8] = rows recomputed globally */
+    int64_t num_bin_rows[OPSP_NUM_BINS];
+    /* Stage times in ms when config.stage_timing != 0:
+     * 0 setup+binning, 1 symbolic, 2 numeric binning+scan+allocation,
+     * 3 numeric, 4 total */
+    float ms_stage[8];
+} opsp_stats;
+
+typedef struct opsp_plan opsp_plan;       /* opaque */
+
+/* Version string of the library. */
+const char *opsp_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *opsp_status_string(opsp_status s);
+
+/* C = A * B (two-phase method of Section 2.2 with the six steps of
+ * Section 5: setup, symbolic binning, symbolic, numeric binning + scan +
+ * allocation of C, numeric, cleanup).
+ *   A, B   : read-only device inputs, borrowed until the stream work ends.
+ *   C      : output; C->rpt/col/val are allocated by the library from its
+ *            stream-ordered memory pool and owned by the caller afterwards
+ *            (release with opsp_csr_free).  nnz(C) == 0 gives col = val =
+ *            NULL and a valid rpt of zeros.
+ *   stream : hipStream_t or NULL.  The host blocks twice (to read the
+ *            symbolic bin sizes and nnz(C)); C is complete once the stream
+ *            reaches the point of return. */
+opsp_status opsp_spgemm(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, void *stream);
+
+/* As opsp_spgemm, with tuning/test controls and counters (either may be
+ * NULL). */
+opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
+                           const opsp_config *config, opsp_stats *stats, void *stream);
+
+/* Symbolic phase only (Section 2.2): runs setup, symbolic binning, the
+ * symbolic step, numeric binning and the row-pointer scan.  Returns nnz(C)
+ * in *nnzC and a plan that keeps C's row pointer and the numeric bins.
+ * A and B must keep their structure (rpt/col) until the plan is destroyed. */
+opsp_status opsp_spgemm_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config *config,
+                                 opsp_plan **plan, int64_t *nnzC, void *stream);
+
+/* Numeric phase for a plan (Section 2.2): may be called repeatedly when A and
+ * B change values but not structure.  For each of C->rpt/col/val: NULL means
+ * "allocate it" (caller owns it afterwards); non-NULL means a caller device
+ * buffer of rows+1 / nnzC / nnzC elements that is filled in. */
+opsp_status opsp_spgemm_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B,
+                                opsp_csr *C, void *stream);
+
+/* Release a plan (stream-ordered on the plan's last stream). NULL is a no-op. */
+void opsp_plan_destroy(opsp_plan *plan);
+
+/* Release the arrays of a C produced by this library (stream-ordered) and
+ * zero *C.  NULL arrays are skipped. */
+opsp_status opsp_csr_free(opsp_csr *C, void *stream);
+
+/* Host-side helpers (no device work; usable without a GPU).
+ * Table sizes of the per-bin hash tables, in entries (-1 = global-memory
+ * table), for step 0 = symbolic (OPSP_SYM_BINS entries) or 1 = numeric
+ * (OPSP_NUM_BINS entries). */
+opsp_status opsp_table_sizes(int32_t step, int64_t *out, int32_t n);
+
+/* Inclusive upper bounds of bins 0..n-2 for table sizes `tsize[0..n-2]` and
+ * a ratio (Section 5.7): symbolic floor(t/ratio), numeric
+ * min(t, floor((t+1)/ratio)); the last bin is unbounded. */
+opsp_status opsp_bin_bounds(int32_t step, const int64_t *tsize, int32_t n, double ratio,
+                            int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPSP_H */

@@ -1,0 +1,313 @@
+"""opsp: row-wise SpGEMM (C = A*B, CSR, FP64) for AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI declared in ``include/opsp.h``.  It only
+marshals arguments: every step of the product runs in the HIP kernels of
+``libopsp.so``.  PyTorch supplies device memory and streams.  There is no
+CPU fallback: if the library is missing the import of a compute entry point
+raises.
+
+Matrices are :class:`DeviceCSR` objects holding three torch tensors on a
+GPU: ``rpt`` int64[rows+1], ``col`` int32[nnz], ``val`` float64[nnz].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_int64, c_void_p
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "DeviceCSR", "Plan", "OpspError", "Config", "Stats", "spgemm", "spgemm_symbolic",
+    "spgemm_numeric", "lib", "library_path", "exported_symbols", "table_sizes", "bin_bounds",
+    "SYM_BINS", "NUM_BINS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libopsp.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "opsp.h")
+
+SYM_BINS = 9
+NUM_BINS = 8
+CONFIG_VERSION = 1
+
+
+class opsp_csr(ctypes.Structure):
+    _fields_ = [("rows", c_int64), ("cols", c_int64), ("nnz", c_int64),
+                ("rpt", c_void_p), ("col", c_void_p), ("val", c_void_p)]
+
+
+class Config(ctypes.Structure):
+    """Mirror of ``opsp_config`` (zero fields = defaults)."""
+    _fields_ = [("version", c_int32), ("sym_ratio", c_double), ("num_ratio", c_double),
+                ("force_sym_bin", c_int32), ("force_num_bin", c_int32),
+                ("sym_abort_fraction", c_double), ("b_lanes", c_int32),
+                ("stage_timing", c_int32), ("validate", c_int32)]
+
+    def __init__(self, **kw):
+        super().__init__()
+        self.version = CONFIG_VERSION
+        self.force_sym_bin = -1
+        self.force_num_bin = -1
+        for k, v in kw.items():
+            setattr(self, k, v)
+
+
+class Stats(ctypes.Structure):
+    """Mirror of ``opsp_stats``."""
+    _fields_ = [("nprod", c_int64), ("nnz", c_int64), ("max_row_nprod", c_int64),
+                ("max_row_nnz", c_int64), ("sym_bin_rows", c_int64 * SYM_BINS),
+                ("num_bin_rows", c_int64 * NUM_BINS), ("ms_stage", ctypes.c_float * 8)]
+
+    def as_dict(self):
+        return {"nprod": self.nprod, "nnz": self.nnz, "max_row_nprod": self.max_row_nprod,
+                "max_row_nnz": self.max_row_nnz, "sym_bin_rows": list(self.sym_bin_rows),
+                "num_bin_rows": list(self.num_bin_rows), "ms_stage": list(self.ms_stage)[:5]}
+
+
+class OpspError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().opsp_status_string(code).decode()
+        super().__init__(f"{where}: {msg}")
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded ``libopsp.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: build it with `python -m paper_2206_07244_amd._build` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(_LIB_PATH)
+        P = c_void_p
+        csr_p = POINTER(opsp_csr)
+        L.opsp_version.restype = c_char_p
+        L.opsp_version.argtypes = []
+        L.opsp_status_string.restype = c_char_p
+        L.opsp_status_string.argtypes = [ctypes.c_int]
+        L.opsp_spgemm.restype = ctypes.c_int
+        L.opsp_spgemm.argtypes = [csr_p, csr_p, csr_p, P]
+        L.opsp_spgemm_ex.restype = ctypes.c_int
+        L.opsp_spgemm_ex.argtypes = [csr_p, csr_p, csr_p, POINTER(Config), POINTER(Stats), P]
+        L.opsp_spgemm_symbolic.restype = ctypes.c_int
+        L.opsp_spgemm_symbolic.argtypes = [csr_p, csr_p, POINTER(Config), POINTER(c_void_p),
+                                           POINTER(c_int64), P]
+        L.opsp_spgemm_numeric.restype = ctypes.c_int
+        L.opsp_spgemm_numeric.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
+        L.opsp_plan_destroy.restype = None
+        L.opsp_plan_destroy.argtypes = [c_void_p]
+        L.opsp_csr_free.restype = ctypes.c_int
+        L.opsp_csr_free.argtypes = [csr_p, P]
+        L.opsp_table_sizes.restype = ctypes.c_int
+        L.opsp_table_sizes.argtypes = [c_int32, POINTER(c_int64), c_int32]
+        L.opsp_bin_bounds.restype = ctypes.c_int
+        L.opsp_bin_bounds.argtypes = [c_int32, POINTER(c_int64), c_int32, c_double, POINTER(c_int64)]
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list:
+    """Function names declared in include/opsp.h."""
+    with open(_HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(opsp_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise OpspError(code, where)
+
+
+# ---------------------------------------------------------------------------
+# Host-side helpers (no GPU needed)
+# ---------------------------------------------------------------------------
+
+def table_sizes(step: int) -> list:
+    n = SYM_BINS if step == 0 else NUM_BINS
+    out = (c_int64 * n)()
+    _check(lib().opsp_table_sizes(step, out, n), "opsp_table_sizes")
+    return list(out)
+
+
+def bin_bounds(step: int, tsizes, ratio: float) -> list:
+    n = len(tsizes) + 1
+    ts = (c_int64 * len(tsizes))(*tsizes)
+    out = (c_int64 * max(n - 1, 1))()
+    _check(lib().opsp_bin_bounds(step, ts, n, float(ratio), out), "opsp_bin_bounds")
+    return list(out)[: n - 1]
+
+
+# ---------------------------------------------------------------------------
+# Device matrices
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+class _Owner:
+    """Frees library-allocated C arrays once every tensor view is gone."""
+
+    def __init__(self, c: opsp_csr, stream):
+        self.c = c
+        self.stream = stream
+
+    def __del__(self):
+        try:
+            if _lib is not None:
+                _lib.opsp_csr_free(byref(self.c), self.stream)
+        except Exception:
+            pass
+
+
+class _CudaArray:
+    def __init__(self, ptr: int, n: int, typestr: str, owner):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr,
+                                         "data": (ptr, False), "version": 2, "strides": None}
+        self._owner = owner
+
+
+def _wrap(ptr, n, dtype, owner, device):
+    torch = _torch()
+    if n == 0 or not ptr:
+        return torch.empty(0, dtype=dtype, device=device)
+    typestr = {torch.int64: "<i8", torch.int32: "<i4", torch.float64: "<f8"}[dtype]
+    t = torch.as_tensor(_CudaArray(int(ptr), int(n), typestr, owner), device=device)
+    assert t.data_ptr() == int(ptr)
+    return t
+
+
+class DeviceCSR:
+    """CSR matrix in device memory (torch tensors)."""
+
+    def __init__(self, rows: int, cols: int, rpt, col, val):
+        self.rows, self.cols = int(rows), int(cols)
+        self.rpt, self.col, self.val = rpt, col, val
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_host(cls, A, device="cuda") -> "DeviceCSR":
+        torch = _torch()
+        rpt = torch.from_numpy(np.ascontiguousarray(A.rpt, np.int64)).to(device)
+        col = torch.from_numpy(np.ascontiguousarray(A.col, np.int32)).to(device)
+        val = torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).to(device)
+        return cls(A.rows, A.cols, rpt, col, val)
+
+    def to_host(self):
+        return (self.rpt.cpu().numpy(), self.col.cpu().numpy(), self.val.cpu().numpy())
+
+    def _c(self) -> opsp_csr:
+        c = opsp_csr()
+        c.rows, c.cols = self.rows, self.cols
+        c.nnz = int(self.rpt[-1].item() - self.rpt[0].item()) if self.rows > 0 else 0
+        c.rpt = self.rpt.data_ptr()
+        c.col = self.col.data_ptr() if self.col.numel() else None
+        c.val = self.val.data_ptr() if self.val.numel() else None
+        return c
+
+    def _c_fast(self, nnz: int) -> opsp_csr:
+        c = opsp_csr()
+        c.rows, c.cols, c.nnz = self.rows, self.cols, nnz
+        c.rpt = self.rpt.data_ptr()
+        c.col = self.col.data_ptr() if self.col.numel() else None
+        c.val = self.val.data_ptr() if self.val.numel() else None
+        return c
+
+
+def _adopt(c: opsp_csr, stream, device) -> DeviceCSR:
+    torch = _torch()
+    owner = _Owner(c, stream)
+    rpt = _wrap(c.rpt, c.rows + 1, torch.int64, owner, device)
+    col = _wrap(c.col, c.nnz, torch.int32, owner, device)
+    val = _wrap(c.val, c.nnz, torch.float64, owner, device)
+    return DeviceCSR(c.rows, c.cols, rpt, col, val)
+
+
+def spgemm(A: DeviceCSR, B: DeviceCSR, config: Optional[Config] = None,
+           stats: Optional[Stats] = None, stream=None) -> DeviceCSR:
+    """C = A*B on the GPU (two-phase OpSparse pipeline); C is library-allocated."""
+    s = _stream_handle(stream)
+    Ac, Bc, Cc = A._c(), B._c(), opsp_csr()
+    code = lib().opsp_spgemm_ex(byref(Ac), byref(Bc), byref(Cc),
+                                byref(config) if config is not None else None,
+                                byref(stats) if stats is not None else None, s)
+    _check(code, "opsp_spgemm")
+    return _adopt(Cc, s, A.rpt.device)
+
+
+def spgemm_raw(Ac: opsp_csr, Bc: opsp_csr, stream_handle) -> opsp_csr:
+    """Lowest-overhead call used by the benchmark: returns the raw C struct
+    (release with ``free_raw``)."""
+    Cc = opsp_csr()
+    _check(lib().opsp_spgemm(byref(Ac), byref(Bc), byref(Cc), stream_handle), "opsp_spgemm")
+    return Cc
+
+
+def free_raw(Cc: opsp_csr, stream_handle):
+    _check(lib().opsp_csr_free(byref(Cc), stream_handle), "opsp_csr_free")
+
+
+class Plan:
+    """Result of the symbolic phase; reusable for numeric calls on matrices
+    with the same structure."""
+
+    def __init__(self, handle: int, nnz: int, rows: int, cols: int):
+        self.handle, self.nnz, self.rows, self.cols = handle, nnz, rows, cols
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.opsp_plan_destroy(self.handle)
+            self.handle = None
+
+
+def spgemm_symbolic(A: DeviceCSR, B: DeviceCSR, config: Optional[Config] = None,
+                    stream=None) -> Plan:
+    s = _stream_handle(stream)
+    Ac, Bc = A._c(), B._c()
+    h = c_void_p()
+    nnz = c_int64()
+    _check(lib().opsp_spgemm_symbolic(byref(Ac), byref(Bc),
+                                      byref(config) if config is not None else None,
+                                      byref(h), byref(nnz), s), "opsp_spgemm_symbolic")
+    return Plan(h.value, nnz.value, A.rows, B.cols)
+
+
+def spgemm_numeric(plan: Plan, A: DeviceCSR, B: DeviceCSR, out: Optional[DeviceCSR] = None,
+                   stream=None) -> DeviceCSR:
+    """Numeric phase.  With ``out`` (torch buffers of the right sizes) the
+    result is written there; otherwise the library allocates C."""
+    s = _stream_handle(stream)
+    Ac, Bc = A._c(), B._c()
+    Cc = opsp_csr()
+    if out is not None:
+        assert out.rpt.numel() == plan.rows + 1 and out.col.numel() == plan.nnz == out.val.numel()
+        Cc.rpt = out.rpt.data_ptr()
+        Cc.col = out.col.data_ptr() if plan.nnz else None
+        Cc.val = out.val.data_ptr() if plan.nnz else None
+    _check(lib().opsp_spgemm_numeric(plan.handle, byref(Ac), byref(Bc), byref(Cc), s),
+           "opsp_spgemm_numeric")
+    if out is not None:
+        return out
+    return _adopt(Cc, s, A.rpt.device)

@@ -1,0 +1,246 @@
+// Symbolic step (OpSparse Section 5.2 Alg. 4, Section 5.6.1 kernel
+// configuration): the number of distinct columns of every row of C, written
+// over n_prod in C.rpt.
+//
+// Hashing: one compare-and-swap per probe (the paper's "single access"):
+// the returned old value says whether the slot was empty (new key), held the
+// key (duplicate) or another key (probe the next slot).
+//
+// gfx950 mapping of the work of one row:
+//  * bin 0: 8 lanes per row, 32 rows per 256-lane workgroup; each lane takes
+//    every 8th entry of A's row and walks that B row alone (tiny rows);
+//  * bin 1: one wave per row (4 rows per workgroup, wave-level sync only);
+//  * bins 2-7: one workgroup per row;
+//  in bins 1-7 each entry of A's row is taken by a group of 2^log_g lanes that
+//  stream the referenced B row with coalesced loads.
+//  * bin 7 uses all 160 KB of LDS and abandons a row as soon as its distinct
+//    count passes the abort threshold (0.8 of the table, Section 5.6.1);
+//  * bin 8 recomputes abandoned rows with per-workgroup global-memory tables
+//    sized from the row's own bound min(n_prod, N), persistent workgroups.
+#include "opsp_internal.h"
+
+namespace opsp {
+
+// 1 = new key, 0 = key already present, -1 = no free slot after T probes
+// (cannot happen when the bin bounds hold; reported instead of spinning).
+__device__ __forceinline__ int sym_insert_lds(int *tab, uint32_t T, int key) {
+    uint32_t s = hslot(key, T);
+    for (uint32_t n = 0; n < T; ++n) {
+        const int old = atomicCAS(&tab[s], -1, key);
+        if (old == -1) return 1;
+        if (old == key) return 0;
+        s = next_slot(s, T);
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// bin 0: GL lanes per row
+// ---------------------------------------------------------------------------
+template <int GL, int T>
+__global__ __launch_bounds__(256) void k_sym_group(int64_t nrows, const int32_t *__restrict__ bins,
+                                                   int64_t bin_off, const int64_t *__restrict__ arpt,
+                                                   const int32_t *__restrict__ acol,
+                                                   const int64_t *__restrict__ brpt,
+                                                   const int32_t *__restrict__ bcol,
+                                                   int64_t *__restrict__ nnz,
+                                                   Counters *__restrict__ ctr) {
+    constexpr int RPW = 256 / GL;
+    __shared__ int tab[RPW * T];
+    const int slot = threadIdx.x / GL, g = threadIdx.x % GL;
+    const int64_t idx = (int64_t)blockIdx.x * RPW + slot;
+    const bool active = idx < nrows;
+    int *t = tab + slot * T;
+    for (int s = g; s < T; s += GL) t[s] = -1;
+    __syncthreads();
+    int cnt = 0;
+    int64_t row = 0;
+    if (active) {
+        row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
+        const int64_t a1 = arpt[row + 1];
+        for (int64_t p = arpt[row] + g; p < a1; p += GL) {
+            const int k = acol[p];
+            const int64_t b1 = brpt[k + 1];
+            for (int64_t q = brpt[k]; q < b1; ++q) {
+                const int r = sym_insert_lds(t, T, bcol[q]);
+                if (r < 0) atomicAdd(&ctr->error, 1u);
+                else cnt += r;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, GL);
+    if (active && g == 0) nnz[row] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// bins 1-7: one team (a wave for W == 64, else the workgroup) per row
+// ---------------------------------------------------------------------------
+template <int W, int T, bool ABORT>
+__global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
+    int64_t nrows, const int32_t *__restrict__ bins, int64_t bin_off,
+    const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
+    int log_g, int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list) {
+    constexpr bool WT = (W == 64);
+    constexpr int R = WT ? 4 : 1;
+    constexpr int NW = W / 64;  // waves per team
+    __shared__ int tab[R * T];
+    __shared__ int s_cnt[R];
+    __shared__ int s_abort[R];
+    __shared__ int red[NW];
+
+    const int team = threadIdx.x / W, t = threadIdx.x % W;
+    const int64_t idx = (int64_t)blockIdx.x * R + team;
+    const bool active = idx < nrows;
+    int *tb = tab + team * T;
+    for (int s = t; s < T; s += W) tb[s] = -1;
+    if (t == 0) { s_cnt[team] = 0; s_abort[team] = 0; }
+    team_sync<WT>();
+
+    int cnt = 0;
+    int64_t row = 0;
+    if (active) {
+        row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
+        const int G = 1 << log_g;
+        const int ngroups = W >> log_g;
+        const int gid = t >> log_g, gl = t & (G - 1);
+        const int64_t a1 = arpt[row + 1];
+        bool stop = false;
+        for (int64_t p = arpt[row] + gid; p < a1 && !stop; p += ngroups) {
+            const int k = acol[p];
+            const int64_t b1 = brpt[k + 1];
+            for (int64_t q = brpt[k] + gl; q < b1; q += G) {
+                int nw = sym_insert_lds(tb, T, bcol[q]);
+                if (nw < 0) { atomicAdd(&ctr->error, 1u); nw = 0; }
+                if (ABORT) {
+                    if (nw && atomicAdd(&s_cnt[team], 1) + 1 > abort_thr) s_abort[team] = 1;
+                    if (*(volatile int *)&s_abort[team]) { stop = true; break; }
+                } else {
+                    cnt += nw;
+                }
+            }
+        }
+    }
+    if (ABORT) {
+        team_sync<WT>();
+        if (active && t == 0) {
+            if (s_abort[team]) {
+                const unsigned f = atomicAdd(&ctr->fail, 1u);
+                fail_list[f] = (int32_t)row;
+            } else {
+                nnz[row] = s_cnt[team];
+            }
+        }
+    } else {
+        cnt = wave_sum(cnt);
+        if constexpr (WT) {
+            if (active && t == 0) nnz[row] = cnt;
+        } else {
+            if ((t & 63) == 0) red[t >> 6] = cnt;
+            __syncthreads();
+            if (active && t == 0) {
+                int sum = 0;
+                for (int i = 0; i < NW; ++i) sum += red[i];
+                nnz[row] = sum;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bin 8: global-memory tables, one slab per persistent workgroup
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_sym_global(
+    int64_t nrows_static, const unsigned int *__restrict__ count_dev,
+    const int32_t *__restrict__ rows, int64_t bin_off, const int64_t *__restrict__ arpt,
+    const int32_t *__restrict__ acol, const int64_t *__restrict__ brpt,
+    const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz, int64_t ncols, int *slabs,
+    int64_t slab_entries, int log_g, Counters *__restrict__ ctr) {
+    __shared__ int red[16];
+    int *tb = slabs + (int64_t)blockIdx.x * slab_entries;
+    const int64_t nrows = count_dev ? (int64_t)*count_dev : nrows_static;
+    const int t = threadIdx.x;
+    const int G = 1 << log_g;
+    const int ngroups = 1024 >> log_g;
+    const int gid = t >> log_g, gl = t & (G - 1);
+    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int64_t row = rows ? (int64_t)rows[bin_off + r] : bin_off + r;
+        // C.rpt[row] still holds n_prod for rows that reach this kernel
+        const int64_t np = nnz[row];
+        const int64_t bound = np < ncols ? np : ncols;
+        uint32_t T = pow2_at_least((uint64_t)(2 * bound > 64 ? 2 * bound : 64));
+        if ((int64_t)T > slab_entries) T = (uint32_t)slab_entries;
+        for (uint32_t s = t; s < T; s += 1024) tb[s] = -1;
+        __syncthreads();
+        int cnt = 0;
+        const int64_t a1 = arpt[row + 1];
+        for (int64_t p = arpt[row] + gid; p < a1; p += ngroups) {
+            const int k = acol[p];
+            const int64_t b1 = brpt[k + 1];
+            for (int64_t q = brpt[k] + gl; q < b1; q += G) {
+                const int key = bcol[q];
+                uint32_t s = hslot(key, T);
+                uint32_t n = 0;
+                for (; n < T; ++n) {
+                    const int old = atomicCAS(&tb[s], -1, key);
+                    if (old == -1) { ++cnt; break; }
+                    if (old == key) break;
+                    s = next_slot(s, T);
+                }
+                if (n == T) atomicAdd(&ctr->error, 1u);
+            }
+        }
+        cnt = wave_sum(cnt);
+        if ((t & 63) == 0) red[t >> 6] = cnt;
+        __syncthreads();
+        if (t == 0) {
+            int64_t sum = 0;
+            for (int i = 0; i < 16; ++i) sum += red[i];
+            nnz[row] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int W, int T, bool ABORT>
+static hipError_t go_row(const SymArgs &a, hipStream_t s) {
+    constexpr int R = (W == 64) ? 4 : 1;
+    const int64_t grid = (a.nrows + R - 1) / R;
+    hipLaunchKernelGGL((k_sym_row<W, T, ABORT>), dim3((unsigned)grid), dim3(W * R), 0, s, a.nrows,
+                       a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.log_g,
+                       a.abort_thr, a.ctr, a.fail_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
+    if (bin != SYM_GLOBAL_BIN && a.nrows == 0) return hipSuccess;
+    switch (bin) {
+        case 0: {
+            constexpr int RPW = 256 / SYM_GL;
+            const int64_t grid = (a.nrows + RPW - 1) / RPW;
+            hipLaunchKernelGGL((k_sym_group<SYM_GL, SYM_T[0]>), dim3((unsigned)grid), dim3(256), 0, s,
+                               a.nrows, a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz,
+                               a.ctr);
+            return hipGetLastError();
+        }
+        case 1: return go_row<SYM_W[1], SYM_T[1], false>(a, s);
+        case 2: return go_row<SYM_W[2], SYM_T[2], false>(a, s);
+        case 3: return go_row<SYM_W[3], SYM_T[3], false>(a, s);
+        case 4: return go_row<SYM_W[4], SYM_T[4], false>(a, s);
+        case 5: return go_row<SYM_W[5], SYM_T[5], false>(a, s);
+        case 6: return go_row<SYM_W[6], SYM_T[6], false>(a, s);
+        case 7: return go_row<SYM_W[7], SYM_T[7], true>(a, s);
+        case SYM_GLOBAL_BIN: {
+            if (a.grid <= 0) return hipSuccess;
+            hipLaunchKernelGGL(k_sym_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.nrows,
+                               a.count_dev, a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col,
+                               a.nnz, a.B.cols, a.slab, a.slab_entries, a.log_g, a.ctr);
+            return hipGetLastError();
+        }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace opsp

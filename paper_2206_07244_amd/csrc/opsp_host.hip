@@ -1,0 +1,610 @@
+// Host orchestration and the C ABI of opsp (see include/opsp.h).
+//
+// Flow of one product (OpSparse Section 5, six steps):
+//   1 setup      C.rpt allocated; n_prod per row written into it, fused with
+//                the first symbolic binning pass (Alg. 1); workspace
+//                allocation is stream-ordered and overlaps the kernel.
+//   2 sym. bins  one read-back of the 9 bin sizes (+ total, max) sizes the
+//                launches; second pass (Alg. 2) or the all-in-one-bin
+//                shortcut (Alg. 3: rows are their own ids, no list written).
+//   3 symbolic   per-bin kernels, biggest bins first (Section 5.5); bin 7
+//                aborts rows into the global-table kernel.
+//   4 num. bins  first pass over nnz with the nnz(C) total (Section 5.4);
+//                one read-back of nnz(C).
+//   5 alloc+scan C.col/C.val come from the stream-ordered pool while the
+//                scan + second pass run (Section 5.4); C.rpt is scanned in
+//                place (Section 5.3).
+//   6 numeric    per-bin kernels, global-table bin first.
+// Every allocation comes from the device's default memory pool with an
+// unbounded release threshold, so after warm-up allocation is a pool hit
+// and never synchronises the device.
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <string.h>
+
+#include "../../include/opsp.h"
+#include "opsp_internal.h"
+
+using namespace opsp;
+
+struct opsp_plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t M = 0, K = 0, N = 0;
+    int64_t nnzC = 0;
+    int64_t max_nnz = 0;
+    int64_t *crpt = nullptr;            // C row pointer (owned)
+    int32_t *bins = nullptr;            // numeric bins (owned; NULL = identity)
+    int64_t num_size[OPSP_NUM_BINS] = {};
+    int64_t num_off[OPSP_NUM_BINS] = {};
+    int identity_bin = -1;              // bin holding all rows when bins == NULL
+    int log_g = 0;
+    bool check = false;
+    Counters *ctr = nullptr;            // device counters (numeric step), owned
+    opsp_stats stats = {};
+};
+
+namespace {
+
+const char *kVersion = "opsp 0.1.0 (gfx950)";
+
+struct DeviceInfo {
+    bool ready = false;
+    int cus = 256;
+};
+std::mutex g_mu;
+DeviceInfo g_dev[64];
+
+opsp_status status_of(hipError_t e) {
+    if (e == hipSuccess) return OPSP_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return OPSP_ERR_ALLOC;
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return OPSP_ERR_NO_DEVICE;
+    return OPSP_ERR_HIP;
+}
+
+opsp_status init_device(int *dev_out, int *cus_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return status_of(e);
+    if (dev < 0 || dev >= 64) return OPSP_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_dev[dev].ready) {
+        hipMemPool_t pool;
+        e = hipDeviceGetDefaultMemPool(&pool, dev);
+        if (e != hipSuccess) return status_of(e);
+        uint64_t thr = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        if (e != hipSuccess) return status_of(e);
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return status_of(e);
+        g_dev[dev].cus = cus > 0 ? cus : 256;
+        g_dev[dev].ready = true;
+    }
+    *dev_out = dev;
+    *cus_out = g_dev[dev].cus;
+    return OPSP_OK;
+}
+
+// Stream-ordered allocations released on every exit path unless kept.
+struct Arena {
+    hipStream_t s;
+    void *p[16];
+    int n = 0;
+    explicit Arena(hipStream_t st) : s(st) {}
+    hipError_t alloc(void **out, size_t bytes) {
+        *out = nullptr;
+        if (bytes == 0) return hipSuccess;
+        hipError_t e = hipMallocAsync(out, bytes, s);
+        if (e == hipSuccess) p[n++] = *out;
+        return e;
+    }
+    void keep(void *q) {
+        for (int i = 0; i < n; ++i)
+            if (p[i] == q) p[i] = nullptr;
+    }
+    ~Arena() {
+        for (int i = 0; i < n; ++i)
+            if (p[i]) (void)hipFreeAsync(p[i], s);
+    }
+};
+
+#define CHK(x)                                  \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return status_of(e_); \
+    } while (0)
+
+bool csr_ok(const opsp_csr *X) {
+    if (!X) return false;
+    if (X->rows < 0 || X->cols < 0 || X->nnz < 0) return false;
+    if (!X->rpt) return false;
+    if (X->nnz > 0 && (!X->col || !X->val)) return false;
+    return true;
+}
+
+DevCSR dev_of(const opsp_csr *X) {
+    return DevCSR{X->rows, X->cols, X->rpt, X->col, X->val};
+}
+
+double sym_ratio(const opsp_config *c) { return (c && c->sym_ratio > 0) ? c->sym_ratio : 1.2; }
+double num_ratio(const opsp_config *c) { return (c && c->num_ratio > 0) ? c->num_ratio : 2.0; }
+
+// Upper bounds by the ratio rule of Section 5.7.
+int64_t bound_for(int step, int64_t t, double ratio) {
+    const double x = step == 0 ? (double)t : (double)(t + 1);
+    int64_t b = (int64_t)(x / ratio + 1e-9);
+    // guard against the division landing just above an integer
+    while (b > 0 && (double)b * ratio > x + 1e-9) --b;
+    if (step == 1 && b > t) b = t;
+    return b;
+}
+
+Bounds make_bounds(int step, double ratio, int force) {
+    Bounds b;
+    memset(&b, 0, sizeof(b));
+    if (step == 0) {
+        b.nb = SYM_NLDS;                    // bins 0..7 natural; 8 only by force
+        for (int j = 0; j < SYM_NLDS - 1; ++j) b.ub[j] = bound_for(0, SYM_T[j], ratio);
+        b.nslots = SYM_NLDS + 1;
+    } else {
+        b.nb = NUM_NLDS + 1;                // bins 0..6 LDS, 7 global
+        for (int j = 0; j < NUM_NLDS; ++j) b.ub[j] = bound_for(1, NUM_T[j], ratio);
+        b.nslots = NUM_NLDS + 1;
+    }
+    b.force = force;
+    return b;
+}
+
+int pick_log_g(const opsp_csr *B, const opsp_config *cfg) {
+    int g = 0;
+    if (cfg && cfg->b_lanes > 0) {
+        while ((1 << g) < cfg->b_lanes && g < 6) ++g;
+        return g;
+    }
+    const double mean = B->rows > 0 ? (double)B->nnz / (double)B->rows : 0.0;
+    while ((double)(1 << g) < mean && g < 6) ++g;
+    return g;
+}
+
+struct Timer {
+    bool on;
+    hipStream_t s;
+    hipEvent_t ev[8];
+    int n = 0;
+    Timer(bool enable, hipStream_t st) : on(enable), s(st) {}
+    void mark() {
+        if (!on || n >= 8) return;
+        if (hipEventCreate(&ev[n]) == hipSuccess) {
+            (void)hipEventRecord(ev[n], s);
+            ++n;
+        }
+    }
+    float between(int a, int b) {
+        float ms = 0.f;
+        if (on && a < n && b < n) (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+        return ms;
+    }
+    ~Timer() {
+        for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
+    }
+};
+
+// Steps 1-5: everything up to C's row pointer and the numeric bins.
+opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config *cfg,
+                         hipStream_t s, opsp_plan *plan, Timer &tm) {
+    int dev = 0, cus = 256;
+    opsp_status st = init_device(&dev, &cus);
+    if (st != OPSP_OK) return st;
+    const int64_t M = A->rows, N = B->cols;
+    plan->device = dev;
+    plan->stream = s;
+    plan->M = M;
+    plan->K = A->cols;
+    plan->N = N;
+    plan->log_g = pick_log_g(B, cfg);
+    plan->check = cfg && cfg->validate;
+
+    Arena ar(s);
+    void *p = nullptr;
+    CHK(ar.alloc(&p, sizeof(int64_t) * (size_t)(M + 1)));
+    int64_t *crpt = (int64_t *)p;
+    CHK(ar.alloc(&p, sizeof(Counters) * 2));
+    Counters *ctrS = (Counters *)p, *ctrN = ctrS + 1;
+    CHK(hipMemsetAsync(ctrS, 0, sizeof(Counters) * 2, s));
+    if (M == 0) {
+        CHK(hipMemsetAsync(crpt, 0, sizeof(int64_t), s));
+        ar.keep(crpt);
+        ar.keep(ctrS);
+        plan->crpt = crpt;
+        plan->ctr = ctrN;
+        return OPSP_OK;
+    }
+    const int64_t nblk = (M + 255) / 256;
+    CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M));
+    int32_t *bins = (int32_t *)p;
+    CHK(ar.alloc(&p, sizeof(unsigned long long) * (size_t)(nblk + 1)));
+    unsigned long long *blocksum = (unsigned long long *)p;
+
+    const int fs = cfg ? cfg->force_sym_bin : -1;
+    const int fn = cfg ? cfg->force_num_bin : -1;
+    if (fs < -1 || fs > SYM_GLOBAL_BIN || fn < -1 || fn > NUM_GLOBAL_BIN) return OPSP_ERR_INVALID;
+    const Bounds bs = make_bounds(0, sym_ratio(cfg), fs);
+    const Bounds bn = make_bounds(1, num_ratio(cfg), fn);
+    const DevCSR dA = dev_of(A), dB = dev_of(B);
+
+    // 1 setup + first symbolic binning pass
+    tm.mark();
+    CHK(launch_setup(dA, dB, crpt, bs, ctrS, nullptr, nullptr, s));
+    Counters hS;
+    CHK(hipMemcpyAsync(&hS, ctrS, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    plan->stats.nprod = (int64_t)hS.total;
+    plan->stats.max_row_nprod = (int64_t)hS.maxv;
+
+    // 2 second pass (or identity rows when one bin holds everything)
+    int64_t ssz[16] = {}, soff[16] = {};
+    int sym_identity = -1;
+    for (int j = 0; j < bs.nslots; ++j) {
+        ssz[j] = (int64_t)hS.size[j];
+        if (ssz[j] == M) sym_identity = j;
+        plan->stats.sym_bin_rows[j < OPSP_SYM_BINS ? j : OPSP_SYM_BINS - 1] = ssz[j];
+    }
+    for (int j = 1; j < bs.nslots; ++j) soff[j] = soff[j - 1] + ssz[j - 1];
+    if (sym_identity < 0) CHK(launch_scatter(M, crpt, bs, ctrS, bins, nullptr, false, s));
+    tm.mark();
+
+    // 3 symbolic, biggest bins first
+    SymArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.A = dA;
+    sa.B = dB;
+    sa.nnz = crpt;
+    sa.log_g = plan->log_g;
+    sa.ctr = ctrS;
+    int32_t *fail_list = nullptr;
+    const int64_t big = ssz[7] + ssz[SYM_GLOBAL_BIN];
+    int *slab = nullptr;
+    int64_t slab_entries = 0, sgrid = 0;
+    if (big > 0) {
+        if (ssz[7] > 0) {
+            CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)ssz[7]));
+            fail_list = (int32_t *)p;
+        }
+        const int64_t bound = (int64_t)hS.maxv < N ? (int64_t)hS.maxv : N;
+        slab_entries = pow2_host(2 * bound > 64 ? 2 * bound : 64);
+        sgrid = big < (int64_t)cus * SYM_GLOBAL_WG_PER_CU ? big : (int64_t)cus * SYM_GLOBAL_WG_PER_CU;
+    }
+    for (int b = 7; b >= 0; --b) {
+        if (ssz[b] == 0) continue;
+        sa.bins = (sym_identity == b) ? nullptr : bins;
+        sa.bin_off = (sym_identity == b) ? 0 : soff[b];
+        sa.nrows = ssz[b];
+        if (b == 7) {
+            const double frac = cfg && cfg->sym_abort_fraction != 0 ? cfg->sym_abort_fraction : 0.8;
+            int64_t thr = frac < 0 ? -1 : (int64_t)(frac * SYM_T[7]);
+            const int64_t cap = SYM_T[7] - SYM_W[7] - 1;
+            if (thr > cap) thr = cap;
+            sa.abort_thr = (int)thr;
+            sa.fail_list = fail_list;
+        }
+        CHK(launch_symbolic_bin(b, sa, s));
+        if (b == 7) {
+            // the global-table allocation overlaps the bin-7 kernel (Section 5.4)
+            CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
+            slab = (int *)p;
+            SymArgs g = sa;
+            g.bins = fail_list;
+            g.bin_off = 0;
+            g.nrows = ssz[7];
+            g.count_dev = &ctrS->fail;
+            g.slab = slab;
+            g.slab_entries = slab_entries;
+            g.grid = ssz[7] < sgrid ? ssz[7] : sgrid;
+            CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
+        }
+    }
+    if (ssz[SYM_GLOBAL_BIN] > 0) {
+        if (!slab) {
+            CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
+            slab = (int *)p;
+        }
+        SymArgs g = sa;
+        g.bins = (sym_identity == SYM_GLOBAL_BIN) ? nullptr : bins;
+        g.bin_off = (sym_identity == SYM_GLOBAL_BIN) ? 0 : soff[SYM_GLOBAL_BIN];
+        g.nrows = ssz[SYM_GLOBAL_BIN];
+        g.count_dev = nullptr;
+        g.slab = slab;
+        g.slab_entries = slab_entries;
+        g.grid = g.nrows < sgrid ? g.nrows : sgrid;
+        CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
+    }
+    tm.mark();
+
+    // 4 numeric binning, first pass with nnz(C)
+    CHK(launch_hist(M, crpt, bn, ctrN, blocksum, s));
+    Counters hc[2];
+    CHK(hipMemcpyAsync(hc, ctrS, sizeof(Counters) * 2, hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    const Counters &hN = hc[1];
+    plan->nnzC = (int64_t)hN.total;
+    plan->max_nnz = (int64_t)hN.maxv;
+    plan->stats.nnz = plan->nnzC;
+    plan->stats.max_row_nnz = plan->max_nnz;
+    if (plan->max_nnz > INT32_MAX) return OPSP_ERR_OVERFLOW;
+    plan->stats.sym_bin_rows[SYM_GLOBAL_BIN] += (int64_t)hc[0].fail;
+
+    // 5 scan C.rpt in place + numeric bins
+    int identity = -1;
+    for (int j = 0; j < bn.nslots; ++j) {
+        plan->num_size[j] = (int64_t)hN.size[j];
+        plan->stats.num_bin_rows[j] = plan->num_size[j];
+        if (plan->num_size[j] == M) identity = j;
+    }
+    for (int j = 1; j < bn.nslots; ++j) plan->num_off[j] = plan->num_off[j - 1] + plan->num_size[j - 1];
+    CHK(launch_scan_blocks(nblk, blocksum, crpt + M, s));
+    CHK(launch_scatter(M, crpt, bn, ctrN, identity >= 0 ? nullptr : bins, blocksum, true, s));
+    tm.mark();
+    ar.keep(crpt);
+    ar.keep(ctrS);
+    if (identity < 0) ar.keep(bins);
+    plan->identity_bin = identity;
+    plan->crpt = crpt;
+    plan->bins = identity >= 0 ? nullptr : bins;
+    plan->ctr = ctrN;
+    return OPSP_OK;
+}
+
+// Step 6 into caller-visible C arrays.
+opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, int32_t *ccol,
+                        double *cval, hipStream_t s) {
+    int dev = 0, cus = 256;
+    opsp_status st = init_device(&dev, &cus);
+    if (st != OPSP_OK) return st;
+    if (plan->M == 0 || plan->nnzC == 0) return OPSP_OK;
+    Arena ar(s);
+    NumArgs na;
+    memset(&na, 0, sizeof(na));
+    na.A = dev_of(A);
+    na.B = dev_of(B);
+    na.crpt = plan->crpt;
+    na.ccol = ccol;
+    na.cval = cval;
+    na.log_g = plan->log_g;
+    na.ctr = plan->ctr;
+    const int gb = NUM_GLOBAL_BIN;
+    bool first = true;
+    void *pk = nullptr, *pv = nullptr;
+    for (int b = gb; b >= 0; --b) {
+        const int64_t rows = plan->num_size[b];
+        if (rows == 0) continue;
+        na.bins = (plan->identity_bin == b) ? nullptr : plan->bins;
+        na.bin_off = (plan->identity_bin == b) ? 0 : plan->num_off[b];
+        na.nrows = rows;
+        if (b == gb) {
+            const int64_t entries = pow2_host(2 * plan->max_nnz > 64 ? 2 * plan->max_nnz : 64);
+            const int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
+            CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
+            CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));
+            na.slab_keys = (int *)pk;
+            na.slab_vals = (double *)pv;
+            na.slab_entries = entries;
+            na.grid = grid;
+        }
+        CHK(launch_numeric_bin(b, na, s));
+        first = false;
+    }
+    (void)first;
+    return OPSP_OK;
+}
+
+opsp_status check_errors(opsp_plan *plan, hipStream_t s) {
+    if (!plan->ctr) return OPSP_OK;
+    Counters h[2];   // symbolic and numeric counters share one allocation
+    CHK(hipMemcpyAsync(h, plan->ctr - 1, sizeof(Counters) * 2, hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    return (h[0].error || h[1].error) ? OPSP_ERR_INTERNAL : OPSP_OK;
+}
+
+void plan_release(opsp_plan *plan, hipStream_t s) {
+    if (!plan) return;
+    if (plan->crpt) (void)hipFreeAsync(plan->crpt, s);
+    if (plan->bins) (void)hipFreeAsync(plan->bins, s);
+    if (plan->ctr) (void)hipFreeAsync(plan->ctr - 1, s);  // both counters share one allocation
+    plan->crpt = nullptr;
+    plan->bins = nullptr;
+    plan->ctr = nullptr;
+}
+
+opsp_status check_inputs(const opsp_csr *A, const opsp_csr *B) {
+    if (!csr_ok(A) || !csr_ok(B)) return OPSP_ERR_INVALID;
+    if (A->cols != B->rows) return OPSP_ERR_SHAPE;
+    if (B->cols > INT32_MAX || A->cols > INT32_MAX) return OPSP_ERR_SHAPE;
+    return OPSP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *opsp_version(void) { return kVersion; }
+
+const char *opsp_status_string(opsp_status s) {
+    switch (s) {
+        case OPSP_OK: return "OPSP_OK";
+        case OPSP_ERR_INVALID: return "OPSP_ERR_INVALID: invalid argument";
+        case OPSP_ERR_SHAPE: return "OPSP_ERR_SHAPE: incompatible or oversized shapes";
+        case OPSP_ERR_ALLOC: return "OPSP_ERR_ALLOC: device allocation failed";
+        case OPSP_ERR_OVERFLOW: return "OPSP_ERR_OVERFLOW: count exceeds its index type";
+        case OPSP_ERR_HIP: return "OPSP_ERR_HIP: HIP runtime error";
+        case OPSP_ERR_INTERNAL: return "OPSP_ERR_INTERNAL: internal consistency check failed";
+        case OPSP_ERR_NO_DEVICE: return "OPSP_ERR_NO_DEVICE: no usable device";
+    }
+    return "unknown opsp status";
+}
+
+opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
+                           const opsp_config *config, opsp_stats *stats, void *stream) {
+    if (!C) return OPSP_ERR_INVALID;
+    memset(C, 0, sizeof(*C));
+    opsp_status st = check_inputs(A, B);
+    if (st != OPSP_OK) return st;
+    if (config && config->version != OPSP_CONFIG_VERSION) return OPSP_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    opsp_plan plan;
+    Timer tm(config && config->stage_timing, s);
+    st = run_symbolic(A, B, config, s, &plan, tm);
+    if (st != OPSP_OK) {
+        plan_release(&plan, s);
+        return st;
+    }
+    void *pc = nullptr, *pv = nullptr;
+    if (plan.nnzC > 0) {
+        hipError_t e = hipMallocAsync(&pc, sizeof(int32_t) * (size_t)plan.nnzC, s);
+        if (e == hipSuccess) e = hipMallocAsync(&pv, sizeof(double) * (size_t)plan.nnzC, s);
+        if (e != hipSuccess) {
+            if (pc) (void)hipFreeAsync(pc, s);
+            plan_release(&plan, s);
+            return status_of(e);
+        }
+    }
+    st = run_numeric(&plan, A, B, (int32_t *)pc, (double *)pv, s);
+    tm.mark();
+    if (st == OPSP_OK && plan.check) st = check_errors(&plan, s);
+    if (st != OPSP_OK) {
+        if (pc) (void)hipFreeAsync(pc, s);
+        if (pv) (void)hipFreeAsync(pv, s);
+        plan_release(&plan, s);
+        return st;
+    }
+    C->rows = A->rows;
+    C->cols = B->cols;
+    C->nnz = plan.nnzC;
+    C->rpt = plan.crpt;
+    C->col = (int32_t *)pc;
+    C->val = (double *)pv;
+    plan.crpt = nullptr;  // ownership moves to the caller
+    if (stats) {
+        *stats = plan.stats;
+        if (tm.on) {
+            (void)hipStreamSynchronize(s);
+            for (int k = 0; k < 4; ++k) stats->ms_stage[k] = tm.between(k, k + 1);
+            stats->ms_stage[4] = tm.between(0, 4);
+        }
+    }
+    plan_release(&plan, s);
+    return OPSP_OK;
+}
+
+opsp_status opsp_spgemm(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, void *stream) {
+    return opsp_spgemm_ex(A, B, C, nullptr, nullptr, stream);
+}
+
+opsp_status opsp_spgemm_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config *config,
+                                 opsp_plan **plan_out, int64_t *nnzC, void *stream) {
+    if (!plan_out || !nnzC) return OPSP_ERR_INVALID;
+    *plan_out = nullptr;
+    *nnzC = 0;
+    opsp_status st = check_inputs(A, B);
+    if (st != OPSP_OK) return st;
+    if (config && config->version != OPSP_CONFIG_VERSION) return OPSP_ERR_INVALID;
+    opsp_plan *plan = new (std::nothrow) opsp_plan();
+    if (!plan) return OPSP_ERR_ALLOC;
+    hipStream_t s = (hipStream_t)stream;
+    Timer tm(false, s);
+    st = run_symbolic(A, B, config, s, plan, tm);
+    if (st != OPSP_OK) {
+        plan_release(plan, s);
+        delete plan;
+        return st;
+    }
+    *plan_out = plan;
+    *nnzC = plan->nnzC;
+    return OPSP_OK;
+}
+
+opsp_status opsp_spgemm_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B,
+                                opsp_csr *C, void *stream) {
+    if (!plan || !C) return OPSP_ERR_INVALID;
+    opsp_status st = check_inputs(A, B);
+    if (st != OPSP_OK) return st;
+    if (A->rows != plan->M || A->cols != plan->K || B->cols != plan->N) return OPSP_ERR_SHAPE;
+    hipStream_t s = (hipStream_t)stream;
+    plan->stream = s;
+    const int64_t nnz = plan->nnzC;
+    void *pr = C->rpt, *pc = C->col, *pv = C->val;
+    const bool own_r = !pr, own_c = !pc && nnz > 0, own_v = !pv && nnz > 0;
+    hipError_t e = hipSuccess;
+    if (own_r) e = hipMallocAsync(&pr, sizeof(int64_t) * (size_t)(plan->M + 1), s);
+    if (e == hipSuccess && own_c) e = hipMallocAsync(&pc, sizeof(int32_t) * (size_t)nnz, s);
+    if (e == hipSuccess && own_v) e = hipMallocAsync(&pv, sizeof(double) * (size_t)nnz, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pr, plan->crpt, sizeof(int64_t) * (size_t)(plan->M + 1),
+                           hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        if (own_r && pr) (void)hipFreeAsync(pr, s);
+        if (own_c && pc) (void)hipFreeAsync(pc, s);
+        if (own_v && pv) (void)hipFreeAsync(pv, s);
+        return status_of(e);
+    }
+    st = run_numeric(plan, A, B, (int32_t *)pc, (double *)pv, s);
+    if (st == OPSP_OK && plan->check) st = check_errors(plan, s);
+    if (st != OPSP_OK) {
+        if (own_r) (void)hipFreeAsync(pr, s);
+        if (own_c) (void)hipFreeAsync(pc, s);
+        if (own_v) (void)hipFreeAsync(pv, s);
+        return st;
+    }
+    C->rows = plan->M;
+    C->cols = plan->N;
+    C->nnz = nnz;
+    C->rpt = (int64_t *)pr;
+    C->col = (int32_t *)pc;
+    C->val = (double *)pv;
+    return OPSP_OK;
+}
+
+void opsp_plan_destroy(opsp_plan *plan) {
+    if (!plan) return;
+    plan_release(plan, plan->stream);
+    delete plan;
+}
+
+opsp_status opsp_csr_free(opsp_csr *C, void *stream) {
+    if (!C) return OPSP_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess, e2;
+    if (C->rpt && (e2 = hipFreeAsync(C->rpt, s)) != hipSuccess) e = e2;
+    if (C->col && (e2 = hipFreeAsync(C->col, s)) != hipSuccess) e = e2;
+    if (C->val && (e2 = hipFreeAsync(C->val, s)) != hipSuccess) e = e2;
+    memset(C, 0, sizeof(*C));
+    return status_of(e);
+}
+
+opsp_status opsp_table_sizes(int32_t step, int64_t *out, int32_t n) {
+    if (!out) return OPSP_ERR_INVALID;
+    if (step == 0) {
+        if (n < OPSP_SYM_BINS) return OPSP_ERR_INVALID;
+        for (int j = 0; j < SYM_NLDS; ++j) out[j] = SYM_T[j];
+        out[SYM_GLOBAL_BIN] = -1;
+        return OPSP_OK;
+    }
+    if (step == 1) {
+        if (n < OPSP_NUM_BINS) return OPSP_ERR_INVALID;
+        for (int j = 0; j < NUM_NLDS; ++j) out[j] = NUM_T[j];
+        out[NUM_GLOBAL_BIN] = -1;
+        return OPSP_OK;
+    }
+    return OPSP_ERR_INVALID;
+}
+
+opsp_status opsp_bin_bounds(int32_t step, const int64_t *tsize, int32_t n, double ratio,
+                            int64_t *out) {
+    if (!tsize || !out || n < 1 || (step != 0 && step != 1) || !(ratio >= 1.0)) return OPSP_ERR_INVALID;
+    for (int j = 0; j < n - 1; ++j) out[j] = bound_for(step, tsize[j], ratio);
+    return OPSP_OK;
+}
+
+}  // extern "C"

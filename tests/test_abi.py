@@ -1,0 +1,73 @@
+"""CPU-side checks of the C ABI library: it loads without a GPU, exports every
+function that include/opsp.h declares, and its host-only helpers agree with
+the oracle's reading of the paper's binning-range rule."""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2206_07244_amd as ops
+
+
+def test_library_loads_and_exports_header_symbols():
+    L = ops.lib()
+    names = ops.exported_symbols()
+    assert "opsp_spgemm" in names and "opsp_spgemm_symbolic" in names
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", ops.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    dyn = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [n for n in names if n not in dyn]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    L = ops.lib()
+    assert b"gfx950" in L.opsp_version()
+    for code in range(8):
+        assert L.opsp_status_string(code).startswith(b"OPSP_")
+    assert b"unknown" in L.opsp_status_string(99)
+
+
+def test_table_sizes_fit_lds_budget():
+    sym = ops.table_sizes(0)
+    num = ops.table_sizes(1)
+    assert len(sym) == ops.SYM_BINS and sym[-1] == -1
+    assert len(num) == ops.NUM_BINS and num[-1] == -1
+    # strictly growing LDS tables; last LDS bins use (almost) all 160 KB
+    assert all(a < b for a, b in zip(sym[:-1], sym[1:-1]))
+    assert all(a < b for a, b in zip(num[:-1], num[1:-1]))
+    assert sym[7] * 4 <= 163840 and num[6] * 12 <= 163840
+    assert sym[7] * 4 > 160000 and num[6] * 12 > 160000
+
+
+@pytest.mark.parametrize("ratio", ["1", "1.2", "1.5", "2", "3"])
+def test_bin_bounds_match_oracle_rule(oracle_lib, ratio):
+    for step in (0, 1):
+        sizes = ops.table_sizes(step)[:-1]
+        got = ops.bin_bounds(step, sizes, float(ratio))
+        want = oracle_lib.bin_ranges(sizes, ratio, numeric=(step == 1))
+        assert got == want, (step, ratio)
+    # and on the paper's V100 table sizes
+    for step, sizes in ((0, [32, 512, 1024, 2048, 4096, 8192, 12287]),
+                        (1, [31, 255, 511, 1023, 2047, 4095, 8191])):
+        got = ops.bin_bounds(step, sizes, float(ratio))
+        assert got == oracle_lib.bin_ranges(sizes, ratio, numeric=(step == 1))
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = ops.lib()
+    out = (ctypes.c_int64 * 4)()
+    assert L.opsp_table_sizes(7, out, 4) == 1
+    assert L.opsp_table_sizes(0, out, 4) == 1
+    ts = (ctypes.c_int64 * 2)(10, 20)
+    assert L.opsp_bin_bounds(0, ts, 3, 0.5, out) == 1
+    # shape mismatch is caught before any device work
+    A = ops.opsp_csr(rows=3, cols=4, nnz=0, rpt=1, col=None, val=None)
+    B = ops.opsp_csr(rows=5, cols=2, nnz=0, rpt=1, col=None, val=None)
+    C = ops.opsp_csr()
+    assert L.opsp_spgemm(ctypes.byref(A), ctypes.byref(B), ctypes.byref(C), None) == 2
+    assert L.opsp_spgemm(None, ctypes.byref(B), ctypes.byref(C), None) == 1
+    assert L.opsp_spgemm(ctypes.byref(A), ctypes.byref(B), None, None) == 1

@@ -1,0 +1,184 @@
+"""GPU parity: the HIP pipeline against the CPU oracle, element by element.
+
+Row pointers and column indices must be identical; values must satisfy
+|c - c_ref| <= 1e-12 * S_ij with S_ij = sum_k |a_ik b_kj| (the summation order
+of the GPU's hash-table atomics differs from the oracle's sequential order,
+and S bounds the rounding difference of any order).  Integer-valued inputs
+are exact in any order and must match bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _ops():
+    import paper_2206_07244_amd as ops
+    return ops
+
+
+def gpu_product(A, B=None, cfg=None, stats=None):
+    import torch
+    ops = _ops()
+    dA = ops.DeviceCSR.from_host(A)
+    dB = dA if B is None else ops.DeviceCSR.from_host(B)
+    C = ops.spgemm(dA, dB, config=cfg, stats=stats)
+    torch.cuda.synchronize()
+    return C.to_host()
+
+
+def check(A, B=None, cfg=None, exact=False, stats=None):
+    Bm = A if B is None else B
+    if cfg is None:
+        cfg = _ops().Config(validate=1)
+    got = gpu_product(A, B, cfg, stats)
+    ref = oracle.spgemm(A, Bm)
+    info = oracle.compare(*got, ref, tol=TOL)
+    if exact:
+        assert info["bit_exact_values"], info
+    return info
+
+
+def test_lap5_64_bit_exact():
+    st = _ops().Stats()
+    info = check(syn.lap5(64), exact=True, stats=st)
+    assert st.nprod == 100104 and st.nnz == 51972
+
+
+@pytest.mark.parametrize("g", [1, 2, 5, 20])
+def test_stencil27_small(g):
+    check(syn.stencil27(g, seed=g))
+
+
+@pytest.mark.parametrize("scale", [10, 14])
+def test_rmat_all_bins(scale):
+    st = _ops().Stats()
+    check(syn.rmat(scale, 16, seed=scale), stats=st)
+    if scale == 14:
+        # every numeric bin, including the global-table bin, is exercised
+        assert all(x > 0 for x in st.num_bin_rows), list(st.num_bin_rows)
+
+
+def test_banded_and_poisson_rectangular():
+    check(syn.banded(20000, 64, 12, seed=3))
+    A = syn.poisson_uniform(3000, 5000, 6.0, seed=1)
+    B = syn.poisson_uniform(5000, 2000, 9.0, seed=2)
+    check(A, B)
+
+
+@pytest.mark.parametrize("m,k,n,d", [(1, 1, 1, 1.0), (7, 0, 5, 0.5), (0, 4, 4, 0.5),
+                                     (30, 40, 0, 0.5), (50, 60, 70, 0.0), (257, 300, 129, 0.05),
+                                     (100, 100, 100, 0.6)])
+def test_small_and_degenerate(m, k, n, d):
+    A = syn.random_csr(m, k, d, seed=m + k, values="int")
+    B = syn.random_csr(k, n, d, seed=n + k + 1, values="int")
+    check(A, B, exact=True)
+
+
+def test_identity_products_exact():
+    A = syn.random_csr(300, 200, 0.03, seed=4)
+    check(A, syn.identity(200), exact=True)
+    check(syn.identity(300), A, exact=True)
+
+
+def test_explicit_zero_kept():
+    A = syn.CSR(1, 2, np.array([0, 2]), np.array([0, 1], np.int32), np.array([1.0, 1.0]))
+    B = syn.CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([1.0, -1.0]))
+    rpt, col, val = gpu_product(A, B)
+    assert list(rpt) == [0, 1] and list(col) == [0] and val[0] == 0.0
+
+
+@pytest.mark.parametrize("b", list(range(9)))
+def test_forced_symbolic_bin(b):
+    ops = _ops()
+    cfg = ops.Config(force_sym_bin=b, validate=1)
+    st = ops.Stats()
+    check(syn.rmat(12, 16, seed=5), cfg=cfg, stats=st)
+    assert st.sym_bin_rows[b] > 0
+
+
+@pytest.mark.parametrize("b", list(range(8)))
+def test_forced_numeric_bin(b):
+    ops = _ops()
+    cfg = ops.Config(force_num_bin=b, validate=1)
+    st = ops.Stats()
+    check(syn.rmat(12, 16, seed=6), cfg=cfg, stats=st)
+    assert st.num_bin_rows[b] > 0
+
+
+def test_every_big_row_recomputed_globally():
+    ops = _ops()
+    cfg = ops.Config(sym_abort_fraction=-1.0, validate=1)
+    st = ops.Stats()
+    check(syn.rmat(14, 16, seed=7), cfg=cfg, stats=st)
+    assert st.sym_bin_rows[7] > 0 and st.sym_bin_rows[8] >= st.sym_bin_rows[7]
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 64])
+def test_b_lane_counts(lanes):
+    ops = _ops()
+    check(syn.rmat(11, 16, seed=8), cfg=ops.Config(b_lanes=lanes, validate=1))
+    check(syn.stencil27(9, seed=8), cfg=ops.Config(b_lanes=lanes, validate=1))
+
+
+@pytest.mark.parametrize("ratios", [(1.0, 1.0), (1.5, 3.0)])
+def test_other_binning_ratios(ratios):
+    ops = _ops()
+    check(syn.rmat(13, 16, seed=9), cfg=ops.Config(sym_ratio=ratios[0], num_ratio=ratios[1], validate=1))
+
+
+def test_symbolic_numeric_split_and_rerun():
+    import torch
+    ops = _ops()
+    A = syn.rmat(12, 16, seed=10)
+    dA = ops.DeviceCSR.from_host(A)
+    plan = ops.spgemm_symbolic(dA, dA)
+    ref = oracle.spgemm(A, A)
+    assert plan.nnz == ref[0][-1]
+    C1 = ops.spgemm_numeric(plan, dA, dA)
+    torch.cuda.synchronize()
+    oracle.compare(*C1.to_host(), ref)
+    # same structure, new values: the plan is reused
+    A2 = syn.CSR(A.rows, A.cols, A.rpt, A.col, np.random.default_rng(1).standard_normal(A.nnz))
+    dA2 = ops.DeviceCSR.from_host(A2)
+    out = ops.DeviceCSR(A.rows, A.cols, torch.empty(A.rows + 1, dtype=torch.int64, device="cuda"),
+                        torch.empty(plan.nnz, dtype=torch.int32, device="cuda"),
+                        torch.empty(plan.nnz, dtype=torch.float64, device="cuda"))
+    C2 = ops.spgemm_numeric(plan, dA2, dA2, out=out)
+    torch.cuda.synchronize()
+    oracle.compare(*C2.to_host(), oracle.spgemm(A2, A2))
+
+
+def test_row_range_view_of_A():
+    """rpt holds absolute offsets, so a slice of rows is a valid input."""
+    import torch
+    ops = _ops()
+    A = syn.rmat(11, 16, seed=11)
+    dA = ops.DeviceCSR.from_host(A)
+    lo, hi = 300, 1500
+    view = ops.DeviceCSR(hi - lo, A.cols, dA.rpt[lo:hi + 1], dA.col, dA.val)
+    C = ops.spgemm(view, dA)
+    torch.cuda.synchronize()
+    ref = oracle.spgemm(A, A, rows=np.arange(lo, hi))
+    oracle.compare(*C.to_host(), ref)
+
+
+def test_structure_deterministic_over_runs():
+    import torch
+    ops = _ops()
+    A = syn.rmat(12, 16, seed=12)
+    dA = ops.DeviceCSR.from_host(A)
+    first = None
+    for _ in range(10):
+        C = ops.spgemm(dA, dA)
+        torch.cuda.synchronize()
+        r, c, _v = C.to_host()
+        if first is None:
+            first = (r, c)
+        else:
+            assert np.array_equal(first[0], r) and np.array_equal(first[1], c)
