@@ -80,8 +80,8 @@ typedef struct {
      * and recomputed with a global table (Section 5.6.1: 0.8).  0 = default
      * 0.8; a negative value means "abort every row of that bin". */
     double sym_abort_fraction;
-    /* Lanes that stream one row of B (power of two 1..64); 0 = chosen from
-     * the mean row length of B. */
+    /* Reserved, must be 0 (the lane mapping of products is chosen per chunk
+     * of A entries from the lengths of the referenced B rows). */
     int32_t b_lanes;
     /* Record per-stage times in opsp_stats.ms_stage (adds device syncs). */
     int32_t stage_timing;
@@ -116,7 +116,7 @@ const char *opsp_status_string(opsp_status s);
  * allocation of C, numeric, cleanup).
  *   A, B   : read-only device inputs, borrowed until the stream work ends.
  *   C      : output; C->rpt/col/val are allocated by the library from its
- *            stream-ordered memory pool and owned by the caller afterwards
+ *            device-memory cache and owned by the caller afterwards
  *            (release with opsp_csr_free).  nnz(C) == 0 gives col = val =
  *            NULL and a valid rpt of zeros.
  *   stream : hipStream_t or NULL.  The host blocks twice (to read the
@@ -149,6 +149,17 @@ void opsp_plan_destroy(opsp_plan *plan);
 /* Release the arrays of a C produced by this library (stream-ordered) and
  * zero *C.  NULL arrays are skipped. */
 opsp_status opsp_csr_free(opsp_csr *C, void *stream);
+
+/* Device memory of the library (workspaces and C arrays) comes from a
+ * per-device cache: blocks released by the library or by opsp_csr_free are
+ * kept, per stream and size class, and handed out again to later calls on the
+ * same stream without any HIP allocation call (on this stack a pool
+ * allocation or release costs tens to hundreds of microseconds of host
+ * time).  opsp_cache_release() synchronises the current device and returns
+ * every cached block to HIP; opsp_cache_bytes() reports what is cached on the
+ * current device. */
+opsp_status opsp_cache_release(void);
+int64_t opsp_cache_bytes(void);
 
 /* Host-side helpers (no device work; usable without a GPU).
  * Table sizes of the per-bin hash tables, in entries (-1 = global-memory

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "DeviceCSR", "Plan", "OpspError", "Config", "Stats", "spgemm", "spgemm_symbolic",
     "spgemm_numeric", "lib", "library_path", "exported_symbols", "table_sizes", "bin_bounds",
-    "SYM_BINS", "NUM_BINS",
+    "SYM_BINS", "NUM_BINS", "cache_release", "cache_bytes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -109,6 +109,10 @@ def lib():
         L.opsp_plan_destroy.argtypes = [c_void_p]
         L.opsp_csr_free.restype = ctypes.c_int
         L.opsp_csr_free.argtypes = [csr_p, P]
+        L.opsp_cache_release.restype = ctypes.c_int
+        L.opsp_cache_release.argtypes = []
+        L.opsp_cache_bytes.restype = c_int64
+        L.opsp_cache_bytes.argtypes = []
         L.opsp_table_sizes.restype = ctypes.c_int
         L.opsp_table_sizes.argtypes = [c_int32, POINTER(c_int64), c_int32]
         L.opsp_bin_bounds.restype = ctypes.c_int
@@ -122,6 +126,15 @@ def exported_symbols() -> list:
     with open(_HEADER) as f:
         text = f.read()
     return sorted(set(re.findall(r"\b(opsp_[a-z_0-9]+)\s*\(", text)))
+
+
+def cache_release():
+    """Return every cached device block of the current device to HIP."""
+    _check(lib().opsp_cache_release(), "opsp_cache_release")
+
+
+def cache_bytes() -> int:
+    return int(lib().opsp_cache_bytes())
 
 
 def _check(code: int, where: str):

@@ -1,11 +1,14 @@
 // Setup step, the two binning passes and the row-pointer scan
 // (OpSparse Section 5, setup step; Section 5.1 Alg. 1-3; Section 5.3).
 //
-// gfx950 design: counting is done per wave with ballots (one LDS atomic per
-// wave per bin instead of one per lane), ranks inside a bin come from
-// mbcnt over the ballot mask, and each workgroup issues one global atomic
-// per bin.  The numeric second pass also performs the in-place exclusive
-// scan that turns per-row nnz (kept in C.rpt) into C's row pointer.
+// gfx950 design: every 256-row block counts its rows per bin with wave
+// ballots and LDS, and writes its counts, value total and value maximum to a
+// per-block record instead of issuing global atomics (thousands of blocks
+// hitting one counter serialise in L2).  One finalize workgroup turns the
+// records into bin sizes, per-block bin offsets (exclusive scans over blocks)
+// and, for the numeric step, per-block row-pointer offsets.  The second pass
+// then places every row with no global atomic at all: rows of a bin appear in
+// ascending order, so the bin lists are deterministic.
 #include "opsp_internal.h"
 
 namespace opsp {
@@ -21,17 +24,17 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
                                                const int32_t *__restrict__ acol,
                                                const int64_t *__restrict__ brpt,
                                                int64_t *__restrict__ nprod, Bounds bd,
-                                               Counters *__restrict__ ctr,
+                                               BlockParts parts,
                                                int32_t *__restrict__ f_alen,
                                                int32_t *__restrict__ f_bmax) {
     __shared__ int64_t rs[4][65];
     __shared__ unsigned long long acc[4][64];
     __shared__ unsigned int bmx[4][64];
-    __shared__ unsigned long long hist[16];
+    __shared__ unsigned int hist[BIN_SLOTS];
     __shared__ unsigned long long s_tot, s_max;
 
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (threadIdx.x < 16) hist[threadIdx.x] = 0;
+    if (threadIdx.x < BIN_SLOTS) hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) { s_tot = 0; s_max = 0; }
     const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 64;
     const int nrows = (int)(M - r0 < 0 ? 0 : (M - r0 > 64 ? 64 : M - r0));
@@ -45,17 +48,28 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
 
     if (nrows > 0) {
         const int64_t e0 = rs[w][0], e1 = rs[w][64];
-        for (int64_t e = e0 + l; e < e1; e += 64) {
-            const int k = acol[e];
-            const int64_t len = brpt[k + 1] - brpt[k];
-            // largest r in [0, nrows) with rs[r] <= e (rows may be empty)
-            int lo = 0, hi = nrows - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rs[w][mid] <= e) lo = mid; else hi = mid - 1;
+        // four entries per lane per step so that their gathers overlap
+        for (int64_t eb = e0 + l; eb < e1; eb += 256) {
+            int64_t len[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t e = eb + 64 * u;
+                const int k = e < e1 ? acol[e] : -1;
+                len[u] = k >= 0 ? brpt[k + 1] - brpt[k] : -1;
             }
-            atomicAdd(&acc[w][lo], (unsigned long long)len);
-            atomicMax(&bmx[w][lo], (unsigned)(len > 0xffffffffll ? 0xffffffffll : len));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t e = eb + 64 * u;
+                if (len[u] < 0) continue;
+                // largest r in [0, nrows) with rs[r] <= e (rows may be empty)
+                int lo = 0, hi = nrows - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (rs[w][mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                atomicAdd(&acc[w][lo], (unsigned long long)len[u]);
+                atomicMax(&bmx[w][lo], (unsigned)(len[u] > 0xffffffffll ? 0xffffffffll : len[u]));
+            }
         }
     }
     __syncthreads();
@@ -71,7 +85,7 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     const int b = valid ? bin_of((int64_t)v, bd) : -1;
     for (int j = 0; j < bd.nslots; ++j) {
         const unsigned long long m = __ballot(b == j);
-        if (l == 0 && m) atomicAdd(&hist[j], (unsigned long long)__popcll(m));
+        if (l == 0 && m) atomicAdd(&hist[j], (unsigned)__popcll(m));
     }
     const unsigned long long ws = wave_sum(v), wm = wave_max(v);
     if (l == 0) {
@@ -79,26 +93,23 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
         atomicMax(&s_max, wm);
     }
     __syncthreads();
-    if ((int)threadIdx.x < bd.nslots && hist[threadIdx.x])
-        atomicAdd(&ctr->size[threadIdx.x], hist[threadIdx.x]);
+    if ((int)threadIdx.x < BIN_SLOTS) parts.hist[(int64_t)blockIdx.x * BIN_SLOTS + threadIdx.x] = hist[threadIdx.x];
     if (threadIdx.x == 0) {
-        atomicAdd(&ctr->total, s_tot);
-        atomicMax(&ctr->maxv, s_max);
+        parts.tot[blockIdx.x] = s_tot;
+        parts.mx[blockIdx.x] = s_max;
     }
 }
 
 // ---------------------------------------------------------------------------
-// First binning pass over existing values (Alg. 1), plus the total
-// (Section 5.4: nnz(C) is summed inside the numeric binning's first pass)
-// and 256-row block sums for the row-pointer scan.
+// First binning pass over existing values (Alg. 1), with the per-block total
+// (Section 5.4 sums nnz(C) inside the numeric binning's first pass).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_hist(int64_t M, const int64_t *__restrict__ v, Bounds bd,
-                                              Counters *__restrict__ ctr,
-                                              unsigned long long *__restrict__ blocksum) {
-    __shared__ unsigned long long hist[16];
+                                              BlockParts parts) {
+    __shared__ unsigned int hist[BIN_SLOTS];
     __shared__ unsigned long long s_tot, s_max;
     const int l = threadIdx.x & 63;
-    if (threadIdx.x < 16) hist[threadIdx.x] = 0;
+    if (threadIdx.x < BIN_SLOTS) hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) { s_tot = 0; s_max = 0; }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -107,7 +118,7 @@ __global__ __launch_bounds__(256) void k_hist(int64_t M, const int64_t *__restri
     const int b = valid ? bin_of((int64_t)x, bd) : -1;
     for (int j = 0; j < bd.nslots; ++j) {
         const unsigned long long m = __ballot(b == j);
-        if (l == 0 && m) atomicAdd(&hist[j], (unsigned long long)__popcll(m));
+        if (l == 0 && m) atomicAdd(&hist[j], (unsigned)__popcll(m));
     }
     const unsigned long long ws = wave_sum(x), wm = wave_max(x);
     if (l == 0) {
@@ -115,59 +126,115 @@ __global__ __launch_bounds__(256) void k_hist(int64_t M, const int64_t *__restri
         atomicMax(&s_max, wm);
     }
     __syncthreads();
-    if ((int)threadIdx.x < bd.nslots && hist[threadIdx.x])
-        atomicAdd(&ctr->size[threadIdx.x], hist[threadIdx.x]);
+    if ((int)threadIdx.x < BIN_SLOTS) parts.hist[(int64_t)blockIdx.x * BIN_SLOTS + threadIdx.x] = hist[threadIdx.x];
     if (threadIdx.x == 0) {
-        atomicAdd(&ctr->total, s_tot);
-        atomicMax(&ctr->maxv, s_max);
-        if (blocksum) blocksum[blockIdx.x] = s_tot;
+        parts.tot[blockIdx.x] = s_tot;
+        parts.mx[blockIdx.x] = s_max;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of the block sums (one workgroup, chunks of 1024 with a
-// running carry).  The grand total is nnz(C) = C.rpt[M].
+// Finalize (one workgroup of 1024 threads): blocks are taken 1024 at a time,
+// one per thread.  Each thread loads its block's record (16 bin counts with
+// four 16-byte loads, the total and the maximum); the workgroup scans every
+// bin slot and the totals (wave scans, per-wave sums in LDS, a running carry
+// across chunks) and writes the exclusive offsets back in place: per bin slot
+// the block's offset inside the bin, and with SCAN the block's row-pointer
+// offset.  Bin sizes, grand total and maximum go to `ctr`.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t nblk,
-                                                      unsigned long long *__restrict__ bs,
-                                                      int64_t *__restrict__ total_out) {
-    __shared__ unsigned long long wtot[16];
-    __shared__ unsigned long long carry;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (threadIdx.x == 0) carry = 0;
+template <bool SCAN>
+__global__ __launch_bounds__(1024) void k_finalize(int64_t nblk, int nslots, BlockParts parts,
+                                                   Counters *__restrict__ ctr,
+                                                   int64_t *__restrict__ total_out) {
+    constexpr int NV = BIN_SLOTS + 1;               // bin slots + totals
+    __shared__ unsigned long long wred[NV][16];
+    __shared__ unsigned long long carry[NV];
+    __shared__ unsigned long long wmx[16];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    // this step's failure / error counters start from zero
+    if (t == 0) {
+        ctr->fail = 0u;
+        ctr->error = 0u;
+    }
+    if (t < NV) carry[t] = 0;
+    unsigned long long mx = 0;
     __syncthreads();
     for (int64_t c = 0; c < nblk; c += 1024) {
-        const int64_t i = c + threadIdx.x;
-        const unsigned long long x = i < nblk ? bs[i] : 0ull;
-        const unsigned long long incl = wave_incl_scan(x);
-        if (l == 63) wtot[w] = incl;
+        const int64_t b = c + t;
+        const bool ok = b < nblk;
+        unsigned int h[BIN_SLOTS];
+        if (ok) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(parts.hist + b * BIN_SLOTS);
+#pragma unroll
+            for (int q = 0; q < BIN_SLOTS / 4; ++q) {
+                const uint4 v4 = src[q];
+                h[4 * q] = v4.x; h[4 * q + 1] = v4.y; h[4 * q + 2] = v4.z; h[4 * q + 3] = v4.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < BIN_SLOTS; ++j) h[j] = 0u;
+        }
+        const unsigned long long tt = ok ? parts.tot[b] : 0ull;
+        const unsigned long long m = ok ? parts.mx[b] : 0ull;
+        mx = m > mx ? m : mx;
+        unsigned long long incl[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const unsigned long long x = j < BIN_SLOTS ? (unsigned long long)h[j] : tt;
+            incl[j] = (j < nslots || j == BIN_SLOTS) ? wave_incl_scan(x) : 0ull;
+            if (l == 63) wred[j][w] = incl[j];
+        }
         __syncthreads();
-        unsigned long long pre = carry;
-        for (int ww = 0; ww < w; ++ww) pre += wtot[ww];
-        if (i < nblk) bs[i] = pre + incl - x;
+        unsigned long long outv[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const unsigned long long x = j < BIN_SLOTS ? (unsigned long long)h[j] : tt;
+            unsigned long long pre = carry[j];
+            for (int ww = 0; ww < w; ++ww) pre += wred[j][ww];
+            outv[j] = pre + incl[j] - x;
+        }
+        if (ok) {
+            uint4 *dst = reinterpret_cast<uint4 *>(parts.hist + b * BIN_SLOTS);
+#pragma unroll
+            for (int q = 0; q < BIN_SLOTS / 4; ++q)
+                dst[q] = make_uint4((unsigned)outv[4 * q], (unsigned)outv[4 * q + 1],
+                                    (unsigned)outv[4 * q + 2], (unsigned)outv[4 * q + 3]);
+            if (SCAN) parts.tot[b] = outv[BIN_SLOTS];
+        }
         __syncthreads();
-        if (threadIdx.x == 1023) carry = pre + incl;
+        if (t < NV) {
+            unsigned long long sum = 0;
+            for (int ww = 0; ww < 16; ++ww) sum += wred[t][ww];
+            carry[t] += sum;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total_out = (int64_t)carry;
+    mx = wave_max(mx);
+    if (l == 0) wmx[w] = mx;
+    __syncthreads();
+    if (t < nslots) ctr->size[t] = carry[t];
+    if (t == 0) {
+        unsigned long long mm = 0;
+        for (int i = 0; i < 16; ++i) mm = wmx[i] > mm ? wmx[i] : mm;
+        ctr->maxv = mm;
+        ctr->total = carry[BIN_SLOTS];
+        if (total_out) *total_out = (int64_t)carry[BIN_SLOTS];
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Second binning pass (Alg. 2): each row id is written to its bin's segment
-// of `bins`.  A wave ballots per bin, lanes take their rank from mbcnt, the
-// workgroup reserves one slice per bin with a single global atomic, and the
-// bin's start offset is the exclusive sum of the (complete) bin sizes.
+// Second binning pass (Alg. 2): row i goes to position
+//   start(bin) + offset of its block inside the bin + rank inside the block,
+// where the rank comes from per-wave ballots (mbcnt) and per-wave counts.
 // With SCAN, v[] (per-row nnz in C.rpt) becomes C's row pointer in place:
-// every row is read and written by the same thread, so no other thread can
-// observe a half-updated value.
+// every row is read and written by the same thread.
 // ---------------------------------------------------------------------------
 template <bool SCAN>
 __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *__restrict__ v, Bounds bd,
-                                                 Counters *__restrict__ ctr,
-                                                 int32_t *__restrict__ bins,
-                                                 const unsigned long long *__restrict__ blockbase) {
-    __shared__ unsigned int wcnt[4][16];
-    __shared__ unsigned long long base[16];
+                                                 const Counters *__restrict__ ctr,
+                                                 int32_t *__restrict__ bins, BlockParts parts) {
+    __shared__ unsigned int wcnt[4][BIN_SLOTS];
+    __shared__ unsigned long long base[BIN_SLOTS];
     __shared__ unsigned long long wsum[4];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -175,23 +242,23 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *__restrict_
     const int64_t x = valid ? v[i] : 0;
     const int b = valid ? bin_of(x, bd) : -1;
     int rank = 0;
-    for (int j = 0; j < bd.nslots; ++j) {
-        const unsigned long long m = __ballot(b == j);
-        if (b == j) rank = mbcnt(m);
-        if (l == 0) wcnt[w][j] = (unsigned)__popcll(m);
+    if (bins) {
+        for (int j = 0; j < bd.nslots; ++j) {
+            const unsigned long long m = __ballot(b == j);
+            if (b == j) rank = mbcnt(m);
+            if (l == 0) wcnt[w][j] = (unsigned)__popcll(m);
+        }
     }
     unsigned long long incl = 0;
     if (SCAN) {
         incl = wave_incl_scan((unsigned long long)x);
         if (l == 63) wsum[w] = incl;
     }
-    __syncthreads();
     if (bins && (int)threadIdx.x < bd.nslots) {
         const int j = threadIdx.x;
-        const unsigned long long tot = (unsigned long long)wcnt[0][j] + wcnt[1][j] + wcnt[2][j] + wcnt[3][j];
         unsigned long long off = 0;
         for (int jj = 0; jj < j; ++jj) off += ctr->size[jj];
-        base[j] = off + (tot ? atomicAdd(&ctr->fill[j], tot) : 0ull);
+        base[j] = off + parts.hist[(int64_t)blockIdx.x * BIN_SLOTS + j];
     }
     __syncthreads();
     if (valid && bins) {
@@ -200,7 +267,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *__restrict_
         bins[pos + rank] = (int32_t)i;
     }
     if (SCAN && valid) {
-        unsigned long long pre = blockbase[blockIdx.x];
+        unsigned long long pre = parts.tot[blockIdx.x];
         for (int ww = 0; ww < w; ++ww) pre += wsum[ww];
         v[i] = (int64_t)(pre + incl - (unsigned long long)x);
     }
@@ -208,38 +275,44 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *__restrict_
 
 // ---------------------------------------------------------------------------
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
-                        Counters *ctr, int32_t *f_alen, int32_t *f_bmax, hipStream_t s) {
+                        const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s) {
     if (A.rows == 0) return hipSuccess;
     const int64_t grid = (A.rows + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)grid), dim3(256), 0, s, A.rows, A.rpt, A.col, B.rpt,
-                       nprod, bd, ctr, f_alen, f_bmax);
+                       nprod, bd, parts, f_alen, f_bmax);
     return hipGetLastError();
 }
 
-hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, Counters *ctr,
-                       unsigned long long *blocksum, hipStream_t s) {
+hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, const BlockParts &parts,
+                       hipStream_t s) {
     if (M == 0) return hipSuccess;
     const int64_t grid = (M + 255) / 256;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr, blocksum);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, parts);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_blocks(int64_t nblk, unsigned long long *blocksum, int64_t *total_out,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, nblk, blocksum, total_out);
+hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Counters *ctr,
+                           int64_t *total_out, bool scan, hipStream_t s) {
+    const int64_t nblk = (M + 255) / 256;
+    if (scan)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(1), dim3(1024), 0, s, nblk, nslots, parts, ctr,
+                           total_out);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(1024), 0, s, nblk, nslots, parts, ctr,
+                           total_out);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, Counters *ctr, int32_t *bins,
-                          const unsigned long long *blockbase, bool scan, hipStream_t s) {
+hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
+                          int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s) {
     if (M == 0) return hipSuccess;
     const int64_t grid = (M + 255) / 256;
     if (scan)
         hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, blockbase);
+                           bins, parts);
     else
         hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, blockbase);
+                           bins, parts);
     return hipGetLastError();
 }
 

@@ -39,6 +39,30 @@ __device__ __forceinline__ bool num_insert_lds(int *keys, double *vals, uint32_t
     return false;
 }
 
+// Accumulate one product per lane (lanes with ok == false take part without
+// one): compare-and-swap the key, then add the product to the slot holding it
+// (Alg. 5).  The probe loop is uniform over the wave and bounded by T
+// iterations with a scalar counter.
+template <class KeyT, class ValT, class AddF>
+__device__ __forceinline__ void num_insert_wave(KeyT *keys, ValT *vals, uint32_t T, bool ok, int key,
+                                                double v, unsigned int *err, AddF &&add) {
+    bool pend = ok;
+    uint32_t s = ok ? hslot(key, T) : 0u;
+    for (uint32_t it = 0; __ballot(pend); ++it) {
+        if (it >= T) {
+            if (pend) atomicAdd(err, 1u);
+            break;
+        }
+        if (pend) {
+            const int old = atomicCAS(&keys[s], -1, key);
+            const bool hit = (old == -1) | (old == key);
+            if (hit) add(&vals[s], v);
+            pend = !hit;
+            s = hit ? s : next_slot(s, T);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // bin 0: GL lanes per row; rank counting over the packed keys
 // ---------------------------------------------------------------------------
@@ -119,46 +143,114 @@ __global__ __launch_bounds__(256) void k_num_group(
     }
 }
 
-// Ascending bitonic sort of keys[0..n) with their values (mirrored first
-// comparator per merge; positions >= n are virtual +inf and never touched).
-template <int NT, bool WT>
-__device__ __forceinline__ void team_bitonic(int *keys, double *vals, int n, int t) {
+// Ascending bitonic sort of keys[0..n) carrying an int payload (mirrored
+// first comparator per merge; positions >= n are virtual +inf and never
+// touched).  All index arithmetic is shifts and masks.
+template <int NT, bool WT, class P>
+__device__ __forceinline__ void team_bitonic(int *keys, P *pay, int n, int t) {
     if (n < 2) return;
-    const int P = (int)pow2_at_least((uint64_t)n);
-    for (int k = 2; k <= P; k <<= 1) {
-        const int h = k >> 1;
-        for (int c = t; c < (P >> 1); c += NT) {
-            const int blk = c / h, off = c - blk * h;
-            const int i = blk * k + off, j = blk * k + k - 1 - off;
-            if (j < n) {
-                const int ki = keys[i], kj = keys[j];
-                if (ki > kj) {
-                    keys[i] = kj; keys[j] = ki;
-                    const double vi = vals[i];
-                    vals[i] = vals[j]; vals[j] = vi;
-                }
+    int lgP = 0;
+    while ((1 << lgP) < n) ++lgP;
+    const int half = 1 << (lgP - 1);
+    auto ce = [&](int i, int j) {
+        if (j < n) {
+            const int ki = keys[i], kj = keys[j];
+            if (ki > kj) {
+                keys[i] = kj;
+                keys[j] = ki;
+                const P pi = pay[i];
+                pay[i] = pay[j];
+                pay[j] = pi;
             }
         }
+    };
+    for (int lk = 1; lk <= lgP; ++lk) {
+        const int lh = lk - 1;
+        const int hmask = (1 << lh) - 1;
+        for (int c = t; c < half; c += NT) {
+            const int blk = c >> lh, off = c & hmask;
+            const int i = (blk << lk) + off;
+            const int j = (blk << lk) + (1 << lk) - 1 - off;
+            ce(i, j);
+        }
         team_sync<WT>();
-        for (int d = h >> 1; d > 0; d >>= 1) {
-            for (int c = t; c < (P >> 1); c += NT) {
-                const int i = 2 * d * (c / d) + (c % d), j = i + d;
-                if (j < n) {
-                    const int ki = keys[i], kj = keys[j];
-                    if (ki > kj) {
-                        keys[i] = kj; keys[j] = ki;
-                        const double vi = vals[i];
-                        vals[i] = vals[j]; vals[j] = vi;
-                    }
-                }
+        for (int ld = lh - 1; ld >= 0; --ld) {
+            const int dmask = (1 << ld) - 1;
+            for (int c = t; c < half; c += NT) {
+                const int i = ((c >> ld) << (ld + 1)) + (c & dmask);
+                ce(i, i + (1 << ld));
             }
             team_sync<WT>();
         }
     }
 }
 
+// Reductions over a team (a wave, or the NW waves of a workgroup through the
+// LDS scratch `red`, which holds at least 3*NW ints).
+template <bool WT, int NW>
+__device__ __forceinline__ void team_min_max_sum(int &mn, int &mx, int &sum, int *red) {
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    sum = wave_sum(sum);
+    if constexpr (!WT) {
+        const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+        if (l == 0) {
+            red[wv] = mn;
+            red[NW + wv] = mx;
+            red[2 * NW + wv] = sum;
+        }
+        __syncthreads();
+        mn = red[0];
+        mx = red[NW];
+        sum = red[2 * NW];
+        for (int i = 1; i < NW; ++i) {
+            mn = red[i] < mn ? red[i] : mn;
+            mx = red[NW + i] > mx ? red[NW + i] : mx;
+            sum += red[2 * NW + i];
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive prefix of one int per lane over the team, plus the team total.
+template <bool WT, int NW>
+__device__ __forceinline__ int team_excl_scan(int x, int &total, int *red) {
+    const int incl = wave_incl_scan(x);
+    if constexpr (WT) {
+        total = __builtin_amdgcn_readlane(incl, 63);
+        return incl - x;
+    } else {
+        const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+        if (l == 63) red[wv] = incl;
+        __syncthreads();
+        int pre = 0;
+        total = 0;
+        for (int i = 0; i < NW; ++i) {
+            const int y = red[i];
+            if (i < wv) pre += y;
+            total += y;
+        }
+        __syncthreads();
+        return pre + incl - x;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // bins 1-6: one team (wave for W == 64, else the workgroup) per row
+//
+// Ordering after hashing.  The occupied slots are packed into (key, slot)
+// pairs at the front of the key array, and each lane then holds the pairs
+// e = t, t + W, ...  An entry's rank is computed with a two-level bitmap of
+// the row's column range [kmin, kmax], built in the freed key array:
+//   level 1: one bit per block of 32 columns, with u16 popcount prefixes per
+//            word, numbers the non-empty blocks;
+//   level 0: one 32-bit word per non-empty block (at most n), with u16
+//            prefixes, holds the columns themselves;
+// rank = prefix0[block number] + popcount of the block word below the column.
+// Values stay in the hash table and are read through the slot.  Rows whose
+// range does not fit the level-1 bitmap sort the pairs with the bitonic
+// network instead; with binning ratios below 1.5 pairs may not fit at all and
+// entries are ranked by counting over the table.
 // ---------------------------------------------------------------------------
 template <int W, int T>
 __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
@@ -167,17 +259,19 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    int log_g, Counters *__restrict__ ctr) {
+    Counters *__restrict__ ctr) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;
     constexpr int ITEMS = (T + W - 1) / W;
+    constexpr int NPACK = (4 * T) / 6;               // pairs that fit the key array
+    constexpr int EMAX = (NPACK + W - 1) / W;         // packed pairs per lane
     __shared__ double vals[R * T];
     __shared__ int keys[R * T];
-    __shared__ int wtot[R * NW];
+    __shared__ int red[3 * NW];
 
     const int team = threadIdx.x / W, t = threadIdx.x % W;
-    const int wv = t >> 6, l = t & 63;
+    const int wv = t >> 6;
     const int64_t idx = (int64_t)blockIdx.x * R + team;
     const bool active = idx < nrows;
     int *tk = keys + team * T;
@@ -188,70 +282,160 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     int64_t row = 0;
     if (active) {
         row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
-        const int G = 1 << log_g;
-        const int ngroups = W >> log_g;
-        const int gid = t >> log_g, gl = t & (G - 1);
-        const int64_t a1 = arpt[row + 1];
-        for (int64_t p = arpt[row] + gid; p < a1; p += ngroups) {
-            const int k = acol[p];
-            const double a = aval[p];
-            const int64_t b1 = brpt[k + 1];
-            for (int64_t q = brpt[k] + gl; q < b1; q += G)
-                if (!num_insert_lds(tk, tv, T, bcol[q], a * bval[q])) atomicAdd(&ctr->error, 1u);
-        }
+        auto ins = [&](bool ok, int key, double v) {
+            num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
+                            [](double *p, double x) { atomicAdd(p, x); });
+        };
+        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, NW, ins,
+                           [] { return false; });
     }
     team_sync<WT>();
 
-    // condense into registers, then pack to the front of the table
+    // count, range and keys of this lane's slots (s = t + m*W)
     int rk[ITEMS];
-    double rv[ITEMS];
-    int c = 0;
+    int c = 0, kmin = INT_MAX, kmax = -1;
 #pragma unroll
     for (int m = 0; m < ITEMS; ++m) {
         const int s = t + m * W;
-        rk[m] = -1;
-        rv[m] = 0.0;
-        if (s < T) {
-            rk[m] = tk[s];
-            if (rk[m] >= 0) { rv[m] = tv[s]; ++c; }
+        rk[m] = s < T ? tk[s] : -1;
+        if (rk[m] >= 0) {
+            ++c;
+            kmin = rk[m] < kmin ? rk[m] : kmin;
+            kmax = rk[m] > kmax ? rk[m] : kmax;
         }
     }
-    const int incl = wave_incl_scan(c);
-    int n, pos;
-    if constexpr (WT) {
-        n = __shfl(incl, 63);
-        pos = incl - c;
-    } else {
-        if (l == 63) wtot[wv] = incl;
-        __syncthreads();
-        int pre = 0;
-        n = 0;
-        for (int i = 0; i < NW; ++i) {
-            const int x = wtot[i];
-            if (i < wv) pre += x;
-            n += x;
+    int n = c;
+    team_min_max_sum<WT, NW>(kmin, kmax, n, red);
+    const int64_t base = active ? crpt[row] : 0;
+    const int64_t cap = active ? crpt[row + 1] - base : 0;
+    if (active && t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+    if (n == 0) return;   // uniform over the team
+
+    if (n > NPACK) {
+        // rank by counting against the intact table
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < ITEMS; ++m) {
+                if (rk[m] >= 0) {
+                    int rank = 0;
+                    for (int s2 = 0; s2 < T; ++s2) {
+                        const int k2 = tk[s2];
+                        rank += (k2 >= 0) & (k2 < rk[m]);
+                    }
+                    if (rank < cap) {
+                        ccol[base + rank] = rk[m];
+                        cval[base + rank] = tv[t + m * W];
+                    }
+                }
+            }
         }
-        pos = pre + incl - c;
+        return;
     }
-    team_sync<WT>();
+
+    // pack (key, slot) pairs: keys in tk[0..n), u16 slots after them
+    int tot;
+    int pos = team_excl_scan<WT, NW>(c, tot, red);
+    team_sync<WT>();   // every lane has read its slots
+    unsigned short *ps = reinterpret_cast<unsigned short *>(tk + n);
 #pragma unroll
     for (int m = 0; m < ITEMS; ++m) {
         if (rk[m] >= 0) {
             tk[pos] = rk[m];
-            tv[pos] = rv[m];
+            ps[pos] = (unsigned short)(t + m * W);
             ++pos;
         }
     }
     team_sync<WT>();
-    team_bitonic<W, WT>(tk, tv, n, t);
+
+    // level-1 words (even count keeps level 0 4-byte aligned)
+    const int span = kmax - kmin + 1;
+    const int nblk1 = (int)(((int64_t)span + 31) >> 5);
+    int l1w = (nblk1 + 31) >> 5;
+    l1w += l1w & 1;
+    const bool two_level = 6 * l1w + 6 * n <= 4 * T;
+    if (!two_level) {
+        team_bitonic<W, WT>(tk, ps, n, t);
+        if (active) {
+            const int nw = cap < n ? (int)cap : n;
+            for (int e = t; e < nw; e += W) {
+                ccol[base + e] = tk[e];
+                cval[base + e] = tv[ps[e]];
+            }
+        }
+        return;
+    }
+
+    int ek[EMAX], es[EMAX];
+#pragma unroll
+    for (int j = 0; j < EMAX; ++j) {
+        const int e = t + j * W;
+        ek[j] = e < n ? tk[e] : -1;
+        es[j] = e < n ? (int)ps[e] : 0;
+    }
+    team_sync<WT>();   // the pairs are in registers; the key array is free
+
+    unsigned int *L1 = reinterpret_cast<unsigned int *>(tk);
+    unsigned short *P1 = reinterpret_cast<unsigned short *>(L1 + l1w);
+    unsigned int *L0 = reinterpret_cast<unsigned int *>(P1 + l1w);
+    unsigned short *P0 = reinterpret_cast<unsigned short *>(L0 + n);
+    for (int w = t; w < l1w; w += W) L1[w] = 0u;
+    for (int w = t; w < n; w += W) L0[w] = 0u;
+    team_sync<WT>();
+    int eb[EMAX];
+#pragma unroll
+    for (int j = 0; j < EMAX; ++j) {
+        eb[j] = (ek[j] - kmin) >> 5;
+        if (ek[j] >= 0) atomicOr(&L1[eb[j] >> 5], 1u << (eb[j] & 31));
+    }
+    team_sync<WT>();
+    // level-1 prefixes: lane t owns words [t*q1, t*q1 + q1)
+    {
+        const int q1 = (l1w + W - 1) / W;
+        const int w0 = t * q1, w1 = w0 + q1 < l1w ? w0 + q1 : l1w;
+        int sum = 0;
+        for (int w = w0; w < w1; ++w) sum += __popc(L1[w]);
+        int nb;
+        int pre = team_excl_scan<WT, NW>(sum, nb, red);
+        for (int w = w0; w < w1; ++w) {
+            P1[w] = (unsigned short)pre;
+            pre += __popc(L1[w]);
+        }
+    }
+    team_sync<WT>();
+#pragma unroll
+    for (int j = 0; j < EMAX; ++j) {
+        if (ek[j] >= 0) {
+            const int b = eb[j];
+            eb[j] = P1[b >> 5] + __popc(L1[b >> 5] & ((1u << (b & 31)) - 1u));
+            atomicOr(&L0[eb[j]], 1u << ((ek[j] - kmin) & 31));
+        }
+    }
+    team_sync<WT>();
+    // level-0 prefixes over the non-empty blocks (at most n words)
+    {
+        const int q0 = (n + W - 1) / W;
+        const int w0 = t * q0, w1 = w0 + q0 < n ? w0 + q0 : n;
+        int sum = 0;
+        for (int w = w0; w < w1; ++w) sum += __popc(L0[w]);
+        int nn;
+        int pre = team_excl_scan<WT, NW>(sum, nn, red);
+        for (int w = w0; w < w1; ++w) {
+            P0[w] = (unsigned short)pre;
+            pre += __popc(L0[w]);
+        }
+    }
+    team_sync<WT>();
     if (active) {
-        const int64_t base = crpt[row];
-        const int64_t cap = crpt[row + 1] - base;
-        if (t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
-        const int nw = cap < n ? (int)cap : n;
-        for (int e = t; e < nw; e += W) {
-            ccol[base + e] = tk[e];
-            cval[base + e] = tv[e];
+#pragma unroll
+        for (int j = 0; j < EMAX; ++j) {
+            if (ek[j] >= 0) {
+                const int bit = (ek[j] - kmin) & 31;
+                const int rank = P0[eb[j]] + __popc(L0[eb[j]] & ((1u << bit) - 1u));
+                if (rank < cap) {
+                    ccol[base + rank] = ek[j];
+                    cval[base + rank] = tv[es[j]];
+                }
+            }
         }
     }
 }
@@ -266,8 +450,7 @@ __global__ __launch_bounds__(1024) void k_num_global(
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    int *slab_keys, double *slab_vals, int64_t slab_entries, int log_g,
-    Counters *__restrict__ ctr) {
+    int *slab_keys, double *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr) {
     constexpr int CW = NUM_GLOBAL_CHUNK_WORDS;
     constexpr int CBITS = CW * 32;
     constexpr int WPT = CW / 1024;  // bitmap words per thread
@@ -279,9 +462,6 @@ __global__ __launch_bounds__(1024) void k_num_global(
     int *tk = slab_keys + (int64_t)blockIdx.x * slab_entries;
     double *tv = slab_vals + (int64_t)blockIdx.x * slab_entries;
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
-    const int G = 1 << log_g;
-    const int ngroups = 1024 >> log_g;
-    const int gid = t >> log_g, gl = t & (G - 1);
 
     for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
         const int64_t row = bins ? (int64_t)bins[bin_off + r] : bin_off + r;
@@ -294,28 +474,16 @@ __global__ __launch_bounds__(1024) void k_num_global(
         __syncthreads();
 
         int kmin = INT_MAX, kmax = -1;
-        const int64_t a1 = arpt[row + 1];
-        for (int64_t p = arpt[row] + gid; p < a1; p += ngroups) {
-            const int k = acol[p];
-            const double a = aval[p];
-            const int64_t b1 = brpt[k + 1];
-            for (int64_t q = brpt[k] + gl; q < b1; q += G) {
-                const int key = bcol[q];
+        auto ins = [&](bool ok, int key, double v) {
+            if (ok) {
                 kmin = key < kmin ? key : kmin;
                 kmax = key > kmax ? key : kmax;
-                uint32_t s = hslot(key, T);
-                uint32_t pr = 0;
-                for (; pr < T; ++pr) {
-                    const int old = atomicCAS(&tk[s], -1, key);
-                    if (old == -1 || old == key) {
-                        unsafeAtomicAdd(&tv[s], a * bval[q]);
-                        break;
-                    }
-                    s = next_slot(s, T);
-                }
-                if (pr == T) atomicAdd(&ctr->error, 1u);
             }
-        }
+            num_insert_wave(tk, tv, T, ok, key, v, &ctr->error,
+                            [](double *p, double x) { unsafeAtomicAdd(p, x); });
+        };
+        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, 16, ins,
+                           [] { return false; });
         kmin = wave_min(kmin);
         kmax = wave_max(kmax);
         if (l == 0) {
@@ -383,7 +551,7 @@ static hipError_t go_row(const NumArgs &a, hipStream_t s) {
     const int64_t grid = (a.nrows + R - 1) / R;
     hipLaunchKernelGGL((k_num_row<W, T>), dim3((unsigned)grid), dim3(W * R), 0, s, a.nrows, a.bins,
                        a.bin_off, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt,
-                       a.ccol, a.cval, a.log_g, a.ctr);
+                       a.ccol, a.cval, a.ctr);
     return hipGetLastError();
 }
 
@@ -409,7 +577,7 @@ hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(k_num_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.nrows,
                                a.bins, a.bin_off, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
                                a.B.val, a.crpt, a.ccol, a.cval, a.slab_keys, a.slab_vals,
-                               a.slab_entries, a.log_g, a.ctr);
+                               a.slab_entries, a.ctr);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

@@ -11,8 +11,9 @@
 //    every 8th entry of A's row and walks that B row alone (tiny rows);
 //  * bin 1: one wave per row (4 rows per workgroup, wave-level sync only);
 //  * bins 2-7: one workgroup per row;
-//  in bins 1-7 each entry of A's row is taken by a group of 2^log_g lanes that
-//  stream the referenced B row with coalesced loads.
+//  in bins 1-8 the products of the row are enumerated flat (row_products):
+//  every lane handles one product per 64-product window, whatever the
+//  lengths of the B rows.
 //  * bin 7 uses all 160 KB of LDS and abandons a row as soon as its distinct
 //    count passes the abort threshold (0.8 of the table, Section 5.6.1);
 //  * bin 8 recomputes abandoned rows with per-workgroup global-memory tables
@@ -32,6 +33,32 @@ __device__ __forceinline__ int sym_insert_lds(int *tab, uint32_t T, int key) {
         s = next_slot(s, T);
     }
     return -1;
+}
+
+// Insert one key per lane (lanes with ok == false take part without a key).
+// The probe loop is uniform over the wave and bounded by T iterations with a
+// scalar counter; every probe is a single compare-and-swap (Alg. 4).
+// Returns 1 when this lane's key was new.
+template <class Tab>
+__device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, int key,
+                                               unsigned int *err) {
+    bool pend = ok;
+    int isnew = 0;
+    uint32_t s = ok ? hslot(key, T) : 0u;
+    for (uint32_t it = 0; __ballot(pend); ++it) {
+        if (it >= T) {
+            if (pend) atomicAdd(err, 1u);
+            break;
+        }
+        if (pend) {
+            const int old = atomicCAS(&tab[s], -1, key);
+            const bool hit = (old == -1) | (old == key);
+            isnew = old == -1;
+            pend = !hit;
+            s = hit ? s : next_slot(s, T);
+        }
+    }
+    return isnew;
 }
 
 // ---------------------------------------------------------------------------
@@ -81,7 +108,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     int64_t nrows, const int32_t *__restrict__ bins, int64_t bin_off,
     const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
-    int log_g, int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list) {
+    int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;  // waves per team
@@ -102,25 +129,24 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     int64_t row = 0;
     if (active) {
         row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
-        const int G = 1 << log_g;
-        const int ngroups = W >> log_g;
-        const int gid = t >> log_g, gl = t & (G - 1);
-        const int64_t a1 = arpt[row + 1];
-        bool stop = false;
-        for (int64_t p = arpt[row] + gid; p < a1 && !stop; p += ngroups) {
-            const int k = acol[p];
-            const int64_t b1 = brpt[k + 1];
-            for (int64_t q = brpt[k] + gl; q < b1; q += G) {
-                int nw = sym_insert_lds(tb, T, bcol[q]);
-                if (nw < 0) { atomicAdd(&ctr->error, 1u); nw = 0; }
-                if (ABORT) {
-                    if (nw && atomicAdd(&s_cnt[team], 1) + 1 > abort_thr) s_abort[team] = 1;
-                    if (*(volatile int *)&s_abort[team]) { stop = true; break; }
-                } else {
-                    cnt += nw;
+        auto ins = [&](bool ok, int key) {
+            const int nw = sym_insert_wave(tb, (uint32_t)T, ok, key, &ctr->error);
+            if constexpr (ABORT) {
+                const unsigned long long m = __ballot(nw);
+                const int nm = (int)__popcll(m);
+                if (nm && lane_id() == 0) {
+                    if (atomicAdd(&s_cnt[team], nm) + nm > abort_thr) s_abort[team] = 1;
                 }
+            } else {
+                cnt += nw;
             }
-        }
+        };
+        auto stop = [&]() -> bool {
+            if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
+            else return false;
+        };
+        row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6, NW,
+                            ins, stop);
     }
     if (ABORT) {
         team_sync<WT>();
@@ -156,14 +182,11 @@ __global__ __launch_bounds__(1024) void k_sym_global(
     const int32_t *__restrict__ rows, int64_t bin_off, const int64_t *__restrict__ arpt,
     const int32_t *__restrict__ acol, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz, int64_t ncols, int *slabs,
-    int64_t slab_entries, int log_g, Counters *__restrict__ ctr) {
+    int64_t slab_entries, Counters *__restrict__ ctr) {
     __shared__ int red[16];
     int *tb = slabs + (int64_t)blockIdx.x * slab_entries;
     const int64_t nrows = count_dev ? (int64_t)*count_dev : nrows_static;
     const int t = threadIdx.x;
-    const int G = 1 << log_g;
-    const int ngroups = 1024 >> log_g;
-    const int gid = t >> log_g, gl = t & (G - 1);
     for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
         const int64_t row = rows ? (int64_t)rows[bin_off + r] : bin_off + r;
         // C.rpt[row] still holds n_prod for rows that reach this kernel
@@ -174,23 +197,9 @@ __global__ __launch_bounds__(1024) void k_sym_global(
         for (uint32_t s = t; s < T; s += 1024) tb[s] = -1;
         __syncthreads();
         int cnt = 0;
-        const int64_t a1 = arpt[row + 1];
-        for (int64_t p = arpt[row] + gid; p < a1; p += ngroups) {
-            const int k = acol[p];
-            const int64_t b1 = brpt[k + 1];
-            for (int64_t q = brpt[k] + gl; q < b1; q += G) {
-                const int key = bcol[q];
-                uint32_t s = hslot(key, T);
-                uint32_t n = 0;
-                for (; n < T; ++n) {
-                    const int old = atomicCAS(&tb[s], -1, key);
-                    if (old == -1) { ++cnt; break; }
-                    if (old == key) break;
-                    s = next_slot(s, T);
-                }
-                if (n == T) atomicAdd(&ctr->error, 1u);
-            }
-        }
+        auto ins = [&](bool ok, int key) { cnt += sym_insert_wave(tb, T, ok, key, &ctr->error); };
+        row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6, 16,
+                            ins, [] { return false; });
         cnt = wave_sum(cnt);
         if ((t & 63) == 0) red[t >> 6] = cnt;
         __syncthreads();
@@ -209,8 +218,8 @@ static hipError_t go_row(const SymArgs &a, hipStream_t s) {
     constexpr int R = (W == 64) ? 4 : 1;
     const int64_t grid = (a.nrows + R - 1) / R;
     hipLaunchKernelGGL((k_sym_row<W, T, ABORT>), dim3((unsigned)grid), dim3(W * R), 0, s, a.nrows,
-                       a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.log_g,
-                       a.abort_thr, a.ctr, a.fail_list);
+                       a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr,
+                       a.ctr, a.fail_list);
     return hipGetLastError();
 }
 
@@ -236,7 +245,7 @@ hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
             if (a.grid <= 0) return hipSuccess;
             hipLaunchKernelGGL(k_sym_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.nrows,
                                a.count_dev, a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col,
-                               a.nnz, a.B.cols, a.slab, a.slab_entries, a.log_g, a.ctr);
+                               a.nnz, a.B.cols, a.slab, a.slab_entries, a.ctr);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

@@ -132,3 +132,162 @@ __device__ __forceinline__ double ld_coherent(const double *p) {
 }
 
 }  // namespace opsp
+
+namespace opsp {
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int s) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint64_t)v, s);
+    const int hi = __builtin_amdgcn_readlane((int)((uint64_t)v >> 32), s);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int s) {
+    return __longlong_as_double(readlane64(__double_as_longlong(v), s));
+}
+
+__device__ __forceinline__ int bpermute(int v, int src_lane) {
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+
+__device__ __forceinline__ int64_t bpermute64(int64_t v, int src_lane) {
+    const int lo = bpermute((int)(uint64_t)v, src_lane);
+    const int hi = bpermute((int)((uint64_t)v >> 32), src_lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Enumeration of the intermediate products of one row of C = A*B
+// (Eq. 2: C_i* = sum over k in A_i* of A_ik * B_k*), spread over `nwaves`
+// waves of which the caller is wave `wv`.
+//
+// A's row is taken in chunks of 64 entries; every wave loads the chunk (lane j
+// holds entry j's B-row start, length and value a_j).  Each chunk is then
+// walked in 64-lane windows in one of two ways, whichever issues fewer
+// instructions for that chunk:
+//  * grouped: when every referenced B row has at most G <= 64 entries, a
+//    window gives 64/G consecutive entries a group of G lanes each; lane
+//    (g, r) handles entry e0+g, position r.  The entry's start, length and
+//    value arrive with one ds_bpermute per 32-bit field.
+//  * flat: lanes take 64 consecutive products of the chunk; a lane finds its
+//    entry by walking (with scalar readlanes) the entries that start inside
+//    the window, after taking the entry that covers the window's first
+//    product.  Used for long or irregular B rows.
+// Windows go round-robin to the waves.  B loads of the next window are issued
+// before the current window's products are handed to `f(ok, key, a * b)`
+// (`f(ok, key)` for the symbolic step); every lane calls f once per window,
+// `ok` says whether it holds a product.  `stop()` is polled once per window
+// and ends the enumeration for the whole wave.
+template <bool NUMERIC, class F, class Stop>
+__device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32_t *__restrict__ acol,
+                                             const double *__restrict__ aval,
+                                             const int64_t *__restrict__ brpt,
+                                             const int32_t *__restrict__ bcol,
+                                             const double *__restrict__ bval, int wv, int nwaves,
+                                             F &&f, Stop &&stop) {
+    const int l = lane_id();
+    for (int64_t c0 = a0; c0 < a1; c0 += 64) {
+        const int64_t j = c0 + l;
+        const bool v = j < a1;
+        int k = 0;
+        double av = 0.0;
+        if (v) {
+            k = acol[j];
+            if constexpr (NUMERIC) av = aval[j];
+        }
+        const int64_t b0 = v ? brpt[k] : 0;
+        const int len = v ? (int)(brpt[k + 1] - b0) : 0;
+        const int nent = (int)(a1 - c0 < 64 ? a1 - c0 : 64);
+        const int lmax = wave_max(len);
+        const int64_t total = (int64_t)wave_sum((long long)len);
+        if (total == 0) continue;
+        int lg = 0;
+        while ((1 << lg) < lmax) ++lg;
+        const int per = 64 >> lg;                         // entries per window
+        const int64_t win_grouped = (nent + per - 1) / per;
+        const int64_t win_flat = (total + 63) / 64;
+        // a flat window costs about twice a grouped one (entry walk)
+        const bool grouped = lg <= 6 && win_grouped <= 2 * win_flat;
+
+        if (grouped) {
+            const int g = l >> lg, r = l & ((1 << lg) - 1);
+            auto fetch = [&](int64_t w, int &key, double &bv, double &a, bool &ok) {
+                const int e = (int)w * per + g;
+                const int src = e < 64 ? e : 63;
+                const int64_t eb0 = bpermute64(b0, src);
+                const int elen = bpermute(len, src);
+                if constexpr (NUMERIC) a = __longlong_as_double(bpermute64(__double_as_longlong(av), src));
+                ok = e < nent && r < elen;
+                key = ok ? bcol[eb0 + r] : -1;
+                if constexpr (NUMERIC) bv = ok ? bval[eb0 + r] : 0.0;
+            };
+            int64_t w = wv;
+            if (w >= win_grouped) continue;
+            int key, key1;
+            double bv = 0.0, bv1 = 0.0, a = 0.0, a1v = 0.0;
+            bool ok, ok1;
+            fetch(w, key, bv, a, ok);
+            while (true) {
+                const int64_t wn = w + nwaves;
+                const bool more = wn < win_grouped;
+                if (more) fetch(wn, key1, bv1, a1v, ok1);
+                if constexpr (NUMERIC) f(ok, key, a * bv);
+                else f(ok, key);
+                if (!more || stop()) break;
+                w = wn;
+                key = key1;
+                bv = bv1;
+                a = a1v;
+                ok = ok1;
+            }
+        } else {
+            const int64_t incl = wave_incl_scan((int64_t)len);
+            const int64_t off = incl - len;
+            const int64_t base = b0 - off;
+            const bool starts = len > 0;
+            auto fetch = [&](int64_t w0, int &key, double &bv, double &a, bool &ok) {
+                const unsigned long long cov = __ballot(starts && off <= w0);
+                int s = 63 - __clzll((long long)cov);
+                int64_t cb = readlane64(base, s);
+                double ca = 0.0;
+                if constexpr (NUMERIC) ca = readlane_f64(av, s);
+                unsigned long long in = __ballot(starts && off > w0 && off < w0 + 64);
+                const int64_t p = w0 + l;
+                while (in) {
+                    s = __ffsll((long long)in) - 1;
+                    in &= in - 1;
+                    const int64_t os = readlane64(off, s);
+                    if (p >= os) {
+                        cb = readlane64(base, s);
+                        if constexpr (NUMERIC) ca = readlane_f64(av, s);
+                    }
+                }
+                ok = p < total;
+                key = ok ? bcol[cb + p] : -1;
+                if constexpr (NUMERIC) bv = ok ? bval[cb + p] : 0.0;
+                a = ca;
+            };
+            const int64_t stride = (int64_t)nwaves * 64;
+            int64_t w0 = (int64_t)wv * 64;
+            if (w0 >= total) continue;
+            int key, key1;
+            double bv = 0.0, bv1 = 0.0, a = 0.0, a1v = 0.0;
+            bool ok, ok1;
+            fetch(w0, key, bv, a, ok);
+            while (true) {
+                const int64_t wn = w0 + stride;
+                const bool more = wn < total;
+                if (more) fetch(wn, key1, bv1, a1v, ok1);
+                if constexpr (NUMERIC) f(ok, key, a * bv);
+                else f(ok, key);
+                if (!more || stop()) break;
+                w0 = wn;
+                key = key1;
+                bv = bv1;
+                a = a1v;
+                ok = ok1;
+            }
+        }
+        if (stop()) break;
+    }
+}
+
+}  // namespace opsp

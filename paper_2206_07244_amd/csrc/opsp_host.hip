@@ -23,7 +23,7 @@
 #include <new>
 #include <string.h>
 
-#include "../../include/opsp.h"
+#include "opsp.h"
 #include "opsp_internal.h"
 
 using namespace opsp;
@@ -39,7 +39,6 @@ struct opsp_plan {
     int64_t num_size[OPSP_NUM_BINS] = {};
     int64_t num_off[OPSP_NUM_BINS] = {};
     int identity_bin = -1;              // bin holding all rows when bins == NULL
-    int log_g = 0;
     bool check = false;
     Counters *ctr = nullptr;            // device counters (numeric step), owned
     opsp_stats stats = {};
@@ -96,7 +95,7 @@ struct Arena {
     hipError_t alloc(void **out, size_t bytes) {
         *out = nullptr;
         if (bytes == 0) return hipSuccess;
-        hipError_t e = hipMallocAsync(out, bytes, s);
+        hipError_t e = cache_alloc(out, bytes, s);
         if (e == hipSuccess) p[n++] = *out;
         return e;
     }
@@ -106,7 +105,7 @@ struct Arena {
     }
     ~Arena() {
         for (int i = 0; i < n; ++i)
-            if (p[i]) (void)hipFreeAsync(p[i], s);
+            if (p[i]) (void)cache_free(p[i], s);
     }
 };
 
@@ -157,15 +156,31 @@ Bounds make_bounds(int step, double ratio, int force) {
     return b;
 }
 
-int pick_log_g(const opsp_csr *B, const opsp_config *cfg) {
-    int g = 0;
-    if (cfg && cfg->b_lanes > 0) {
-        while ((1 << g) < cfg->b_lanes && g < 6) ++g;
-        return g;
+// Per-thread pinned host buffer for the small counter read-backs.
+struct PinnedCounters {
+    Counters *h = nullptr;
+    Counters *get() {
+        if (!h && hipHostMalloc((void **)&h, sizeof(Counters) * 2, hipHostMallocDefault) != hipSuccess)
+            h = nullptr;
+        return h;
     }
-    const double mean = B->rows > 0 ? (double)B->nnz / (double)B->rows : 0.0;
-    while ((double)(1 << g) < mean && g < 6) ++g;
-    return g;
+    ~PinnedCounters() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+thread_local PinnedCounters t_pinned;
+
+hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipStream_t s) {
+    Counters *pin = t_pinned.get();
+    if (!pin) {
+        hipError_t e = hipMemcpyAsync(dst, src, sizeof(Counters) * count, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    }
+    hipError_t e = hipMemcpyAsync(pin, src, sizeof(Counters) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) memcpy(dst, pin, sizeof(Counters) * count);
+    return e;
 }
 
 struct Timer {
@@ -203,7 +218,6 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     plan->M = M;
     plan->K = A->cols;
     plan->N = N;
-    plan->log_g = pick_log_g(B, cfg);
     plan->check = cfg && cfg->validate;
 
     Arena ar(s);
@@ -212,8 +226,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     int64_t *crpt = (int64_t *)p;
     CHK(ar.alloc(&p, sizeof(Counters) * 2));
     Counters *ctrS = (Counters *)p, *ctrN = ctrS + 1;
-    CHK(hipMemsetAsync(ctrS, 0, sizeof(Counters) * 2, s));
     if (M == 0) {
+        CHK(hipMemsetAsync(ctrS, 0, sizeof(Counters) * 2, s));
         CHK(hipMemsetAsync(crpt, 0, sizeof(int64_t), s));
         ar.keep(crpt);
         ar.keep(ctrS);
@@ -224,8 +238,11 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     const int64_t nblk = (M + 255) / 256;
     CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M));
     int32_t *bins = (int32_t *)p;
-    CHK(ar.alloc(&p, sizeof(unsigned long long) * (size_t)(nblk + 1)));
-    unsigned long long *blocksum = (unsigned long long *)p;
+    CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
+    BlockParts parts;
+    parts.tot = (unsigned long long *)p;
+    parts.mx = parts.tot + nblk;
+    parts.hist = (unsigned int *)(parts.mx + nblk);
 
     const int fs = cfg ? cfg->force_sym_bin : -1;
     const int fn = cfg ? cfg->force_num_bin : -1;
@@ -236,10 +253,10 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 
     // 1 setup + first symbolic binning pass
     tm.mark();
-    CHK(launch_setup(dA, dB, crpt, bs, ctrS, nullptr, nullptr, s));
+    CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s));
+    CHK(launch_finalize(M, bs.nslots, parts, ctrS, nullptr, false, s));
     Counters hS;
-    CHK(hipMemcpyAsync(&hS, ctrS, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    CHK(hipStreamSynchronize(s));
+    CHK(read_counters(&hS, ctrS, 1, s));
     plan->stats.nprod = (int64_t)hS.total;
     plan->stats.max_row_nprod = (int64_t)hS.maxv;
 
@@ -252,7 +269,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
         plan->stats.sym_bin_rows[j < OPSP_SYM_BINS ? j : OPSP_SYM_BINS - 1] = ssz[j];
     }
     for (int j = 1; j < bs.nslots; ++j) soff[j] = soff[j - 1] + ssz[j - 1];
-    if (sym_identity < 0) CHK(launch_scatter(M, crpt, bs, ctrS, bins, nullptr, false, s));
+    if (sym_identity < 0) CHK(launch_scatter(M, crpt, bs, ctrS, bins, parts, false, s));
     tm.mark();
 
     // 3 symbolic, biggest bins first
@@ -261,7 +278,6 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.A = dA;
     sa.B = dB;
     sa.nnz = crpt;
-    sa.log_g = plan->log_g;
     sa.ctr = ctrS;
     int32_t *fail_list = nullptr;
     const int64_t big = ssz[7] + ssz[SYM_GLOBAL_BIN];
@@ -323,10 +339,10 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     tm.mark();
 
     // 4 numeric binning, first pass with nnz(C)
-    CHK(launch_hist(M, crpt, bn, ctrN, blocksum, s));
+    CHK(launch_hist(M, crpt, bn, parts, s));
+    CHK(launch_finalize(M, bn.nslots, parts, ctrN, crpt + M, true, s));
     Counters hc[2];
-    CHK(hipMemcpyAsync(hc, ctrS, sizeof(Counters) * 2, hipMemcpyDeviceToHost, s));
-    CHK(hipStreamSynchronize(s));
+    CHK(read_counters(hc, ctrS, 2, s));
     const Counters &hN = hc[1];
     plan->nnzC = (int64_t)hN.total;
     plan->max_nnz = (int64_t)hN.maxv;
@@ -343,8 +359,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
         if (plan->num_size[j] == M) identity = j;
     }
     for (int j = 1; j < bn.nslots; ++j) plan->num_off[j] = plan->num_off[j - 1] + plan->num_size[j - 1];
-    CHK(launch_scan_blocks(nblk, blocksum, crpt + M, s));
-    CHK(launch_scatter(M, crpt, bn, ctrN, identity >= 0 ? nullptr : bins, blocksum, true, s));
+    CHK(launch_scatter(M, crpt, bn, ctrN, identity >= 0 ? nullptr : bins, parts, true, s));
     tm.mark();
     ar.keep(crpt);
     ar.keep(ctrS);
@@ -371,7 +386,6 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     na.crpt = plan->crpt;
     na.ccol = ccol;
     na.cval = cval;
-    na.log_g = plan->log_g;
     na.ctr = plan->ctr;
     const int gb = NUM_GLOBAL_BIN;
     bool first = true;
@@ -402,16 +416,15 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
 opsp_status check_errors(opsp_plan *plan, hipStream_t s) {
     if (!plan->ctr) return OPSP_OK;
     Counters h[2];   // symbolic and numeric counters share one allocation
-    CHK(hipMemcpyAsync(h, plan->ctr - 1, sizeof(Counters) * 2, hipMemcpyDeviceToHost, s));
-    CHK(hipStreamSynchronize(s));
+    CHK(read_counters(h, plan->ctr - 1, 2, s));
     return (h[0].error || h[1].error) ? OPSP_ERR_INTERNAL : OPSP_OK;
 }
 
 void plan_release(opsp_plan *plan, hipStream_t s) {
     if (!plan) return;
-    if (plan->crpt) (void)hipFreeAsync(plan->crpt, s);
-    if (plan->bins) (void)hipFreeAsync(plan->bins, s);
-    if (plan->ctr) (void)hipFreeAsync(plan->ctr - 1, s);  // both counters share one allocation
+    if (plan->crpt) (void)cache_free(plan->crpt, s);
+    if (plan->bins) (void)cache_free(plan->bins, s);
+    if (plan->ctr) (void)cache_free(plan->ctr - 1, s);  // both counters share one allocation
     plan->crpt = nullptr;
     plan->bins = nullptr;
     plan->ctr = nullptr;
@@ -462,10 +475,10 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
     }
     void *pc = nullptr, *pv = nullptr;
     if (plan.nnzC > 0) {
-        hipError_t e = hipMallocAsync(&pc, sizeof(int32_t) * (size_t)plan.nnzC, s);
-        if (e == hipSuccess) e = hipMallocAsync(&pv, sizeof(double) * (size_t)plan.nnzC, s);
+        hipError_t e = cache_alloc(&pc, sizeof(int32_t) * (size_t)plan.nnzC, s);
+        if (e == hipSuccess) e = cache_alloc(&pv, sizeof(double) * (size_t)plan.nnzC, s);
         if (e != hipSuccess) {
-            if (pc) (void)hipFreeAsync(pc, s);
+            if (pc) (void)cache_free(pc, s);
             plan_release(&plan, s);
             return status_of(e);
         }
@@ -474,8 +487,8 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
     tm.mark();
     if (st == OPSP_OK && plan.check) st = check_errors(&plan, s);
     if (st != OPSP_OK) {
-        if (pc) (void)hipFreeAsync(pc, s);
-        if (pv) (void)hipFreeAsync(pv, s);
+        if (pc) (void)cache_free(pc, s);
+        if (pv) (void)cache_free(pv, s);
         plan_release(&plan, s);
         return st;
     }
@@ -537,24 +550,24 @@ opsp_status opsp_spgemm_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_c
     void *pr = C->rpt, *pc = C->col, *pv = C->val;
     const bool own_r = !pr, own_c = !pc && nnz > 0, own_v = !pv && nnz > 0;
     hipError_t e = hipSuccess;
-    if (own_r) e = hipMallocAsync(&pr, sizeof(int64_t) * (size_t)(plan->M + 1), s);
-    if (e == hipSuccess && own_c) e = hipMallocAsync(&pc, sizeof(int32_t) * (size_t)nnz, s);
-    if (e == hipSuccess && own_v) e = hipMallocAsync(&pv, sizeof(double) * (size_t)nnz, s);
+    if (own_r) e = cache_alloc(&pr, sizeof(int64_t) * (size_t)(plan->M + 1), s);
+    if (e == hipSuccess && own_c) e = cache_alloc(&pc, sizeof(int32_t) * (size_t)nnz, s);
+    if (e == hipSuccess && own_v) e = cache_alloc(&pv, sizeof(double) * (size_t)nnz, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pr, plan->crpt, sizeof(int64_t) * (size_t)(plan->M + 1),
                            hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) {
-        if (own_r && pr) (void)hipFreeAsync(pr, s);
-        if (own_c && pc) (void)hipFreeAsync(pc, s);
-        if (own_v && pv) (void)hipFreeAsync(pv, s);
+        if (own_r && pr) (void)cache_free(pr, s);
+        if (own_c && pc) (void)cache_free(pc, s);
+        if (own_v && pv) (void)cache_free(pv, s);
         return status_of(e);
     }
     st = run_numeric(plan, A, B, (int32_t *)pc, (double *)pv, s);
     if (st == OPSP_OK && plan->check) st = check_errors(plan, s);
     if (st != OPSP_OK) {
-        if (own_r) (void)hipFreeAsync(pr, s);
-        if (own_c) (void)hipFreeAsync(pc, s);
-        if (own_v) (void)hipFreeAsync(pv, s);
+        if (own_r) (void)cache_free(pr, s);
+        if (own_c) (void)cache_free(pc, s);
+        if (own_v) (void)cache_free(pv, s);
         return st;
     }
     C->rows = plan->M;
@@ -576,9 +589,9 @@ opsp_status opsp_csr_free(opsp_csr *C, void *stream) {
     if (!C) return OPSP_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess, e2;
-    if (C->rpt && (e2 = hipFreeAsync(C->rpt, s)) != hipSuccess) e = e2;
-    if (C->col && (e2 = hipFreeAsync(C->col, s)) != hipSuccess) e = e2;
-    if (C->val && (e2 = hipFreeAsync(C->val, s)) != hipSuccess) e = e2;
+    if (C->rpt && (e2 = cache_free(C->rpt, s)) != hipSuccess) e = e2;
+    if (C->col && (e2 = cache_free(C->col, s)) != hipSuccess) e = e2;
+    if (C->val && (e2 = cache_free(C->val, s)) != hipSuccess) e = e2;
     memset(C, 0, sizeof(*C));
     return status_of(e);
 }

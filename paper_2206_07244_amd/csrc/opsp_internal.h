@@ -15,6 +15,11 @@ inline int64_t pow2_host(int64_t x) {
     return p;
 }
 
+// Device-memory cache (opsp_alloc.hip): stream-ordered reuse of blocks
+// without HIP calls on the hot path.
+hipError_t cache_alloc(void **out, size_t bytes, hipStream_t s);
+hipError_t cache_free(void *p, hipStream_t s);
+
 struct DevCSR {
     int64_t rows, cols;
     const int64_t *rpt;
@@ -23,21 +28,32 @@ struct DevCSR {
 };
 
 // ---- binning / setup / scan (kernels_bin.hip) -----------------------------
+// Histogram slots per 256-row block (>= the bins of either step).
+constexpr int BIN_SLOTS = 16;
+
+// Per-block records of the first binning pass (256 rows per block).
+struct BlockParts {
+    unsigned int *hist;          // [nblk][BIN_SLOTS] rows per bin; exclusive over blocks after finalize
+    unsigned long long *tot;     // [nblk] sum of row values; exclusive scan after a scanning finalize
+    unsigned long long *mx;      // [nblk] max row value
+};
+
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
-// per-bin row counts, total and max into `ctr`; optional per-row features.
+// per-block bin counts / totals / maxima into `parts`; optional features.
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
-                        Counters *ctr, int32_t *f_alen, int32_t *f_bmax, hipStream_t s);
-// First binning pass over existing row values (numeric step): counts, total,
-// max and per-256-row block sums (for the scan).
-hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, Counters *ctr,
-                       unsigned long long *blocksum, hipStream_t s);
-// Exclusive scan of the block sums; writes the grand total to *total_out.
-hipError_t launch_scan_blocks(int64_t nblk, unsigned long long *blocksum, int64_t *total_out,
-                              hipStream_t s);
+                        const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s);
+// First binning pass over existing row values (numeric step).
+hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, const BlockParts &parts,
+                       hipStream_t s);
+// Reduce the block records into bin sizes, total and max (ctr); scan the
+// per-block bin counts; with `scan`, also scan the block totals and write the
+// grand total to *total_out.
+hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Counters *ctr,
+                           int64_t *total_out, bool scan, hipStream_t s);
 // Second binning pass: scatter row ids into `bins` (may be NULL when no
 // bins are needed); with `scan`, also turn v[] into exclusive offsets.
-hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, Counters *ctr, int32_t *bins,
-                          const unsigned long long *blockbase, bool scan, hipStream_t s);
+hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
+                          int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s);
 
 // ---- symbolic step (kernels_sym.hip) ---------------------------------------
 struct SymArgs {
@@ -46,7 +62,6 @@ struct SymArgs {
     const int32_t *bins;     // row list of the bin (NULL = identity rows bin_off..)
     int64_t bin_off;         // offset of the bin in `bins`
     int64_t nrows;           // rows in the bin
-    int log_g;               // lanes streaming one B row = 1 << log_g
     int abort_thr;           // bin 7: abandon a row above this many keys
     Counters *ctr;           // fail counter
     int32_t *fail_list;      // abandoned rows (bin 7)
@@ -66,7 +81,6 @@ struct NumArgs {
     const int32_t *bins;
     int64_t bin_off;
     int64_t nrows;
-    int log_g;
     Counters *ctr;           // error counter
     int *slab_keys;          // global tables (bin 7)
     double *slab_vals;

@@ -27,7 +27,7 @@ constexpr int SYM_GLOBAL_BIN = 8;
 // ---- numeric step: (int32 key, double value) entries ----------------------
 constexpr int NUM_GL = 8;
 constexpr int NUM_NLDS = 7;
-constexpr int NUM_T[NUM_NLDS] = {39, 425, 848, 1700, 3408, 6820, 13640};
+constexpr int NUM_T[NUM_NLDS] = {39, 425, 848, 1700, 3408, 6816, 13632};
 constexpr int NUM_W[NUM_NLDS] = {NUM_GL, 64, 128, 256, 512, 1024, 1024};
 constexpr int NUM_GLOBAL_BIN = 7;
 

@@ -119,11 +119,13 @@ def test_every_big_row_recomputed_globally():
     assert st.sym_bin_rows[7] > 0 and st.sym_bin_rows[8] >= st.sym_bin_rows[7]
 
 
-@pytest.mark.parametrize("lanes", [1, 4, 64])
-def test_b_lane_counts(lanes):
-    ops = _ops()
-    check(syn.rmat(11, 16, seed=8), cfg=ops.Config(b_lanes=lanes, validate=1))
-    check(syn.stencil27(9, seed=8), cfg=ops.Config(b_lanes=lanes, validate=1))
+@pytest.mark.parametrize("rowlen", [1, 3, 8, 20, 40, 70, 300])
+def test_b_row_lengths(rowlen):
+    """Uniform B rows of many lengths drive both product mappings (grouped
+    lanes for B rows up to 64 entries, flat windows beyond)."""
+    A = syn.poisson_uniform(700, 900, 6.0, seed=rowlen)
+    B = syn.poisson_uniform(900, 5000, float(rowlen), seed=rowlen + 1)
+    check(A, B)
 
 
 @pytest.mark.parametrize("ratios", [(1.0, 1.0), (1.5, 3.0)])
