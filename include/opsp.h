@@ -85,8 +85,14 @@ typedef struct {
     int32_t b_lanes;
     /* Record per-stage times in opsp_stats.ms_stage (adds device syncs). */
     int32_t stage_timing;
-    /* Run the (slow) device-side input validation first. */
+    /* Check the internal consistency counters after the call (adds a
+     * device sync). */
     int32_t validate;
+    /* Testing: > 0 launches the symbolic bin kernels (and numeric bin 0)
+     * with this fixed grid, the workgroups walking the bin's rows with a
+     * grid-stride loop (the launch form that captured graphs use for the
+     * symbolic step); 0 = one team per row. */
+    int32_t fixed_grid;
 } opsp_config;
 
 /* Counters of one call (filled when a stats pointer is given). */

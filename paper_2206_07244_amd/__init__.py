@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
     _fields_ = [("version", c_int32), ("sym_ratio", c_double), ("num_ratio", c_double),
                 ("force_sym_bin", c_int32), ("force_num_bin", c_int32),
                 ("sym_abort_fraction", c_double), ("b_lanes", c_int32),
-                ("stage_timing", c_int32), ("validate", c_int32)]
+                ("stage_timing", c_int32), ("validate", c_int32), ("fixed_grid", c_int32)]
 
     def __init__(self, **kw):
         super().__init__()

@@ -68,8 +68,7 @@ __device__ __forceinline__ void num_insert_wave(KeyT *keys, ValT *vals, uint32_t
 // ---------------------------------------------------------------------------
 template <int GL, int T>
 __global__ __launch_bounds__(256) void k_num_group(
-    int64_t nrows, const int32_t *__restrict__ bins, int64_t bin_off,
-    const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
@@ -79,67 +78,71 @@ __global__ __launch_bounds__(256) void k_num_group(
     __shared__ double vals[RPW * T];
     __shared__ int keys[RPW * T];
     __shared__ int ck[RPW * T];
+    src.resolve();
     const int slot = threadIdx.x / GL, g = threadIdx.x % GL;
-    const int64_t idx = (int64_t)blockIdx.x * RPW + slot;
-    const bool active = idx < nrows;
     int *tk = keys + slot * T;
     double *tv = vals + slot * T;
     int *pk = ck + slot * T;
-    for (int s = g; s < T; s += GL) { tk[s] = -1; tv[s] = 0.0; }
-    __syncthreads();
-    int64_t row = 0;
-    if (active) {
-        row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
-        const int64_t a1 = arpt[row + 1];
-        for (int64_t p = arpt[row] + g; p < a1; p += GL) {
-            const int k = acol[p];
-            const double a = aval[p];
-            const int64_t b1 = brpt[k + 1];
-            for (int64_t q = brpt[k]; q < b1; ++q)
-                if (!num_insert_lds(tk, tv, T, bcol[q], a * bval[q])) atomicAdd(&ctr->error, 1u);
+    for (int64_t b0 = (int64_t)blockIdx.x * RPW; b0 < src.nrows; b0 += (int64_t)gridDim.x * RPW) {
+        const int64_t idx = b0 + slot;
+        const bool active = idx < src.nrows;
+        for (int s = g; s < T; s += GL) { tk[s] = -1; tv[s] = 0.0; }
+        __syncthreads();
+        int64_t row = 0;
+        if (active) {
+            row = src.row(idx);
+            const int64_t a1 = arpt[row + 1];
+            for (int64_t p = arpt[row] + g; p < a1; p += GL) {
+                const int k = acol[p];
+                const double a = aval[p];
+                const int64_t b1 = brpt[k + 1];
+                for (int64_t q = brpt[k]; q < b1; ++q)
+                    if (!num_insert_lds(tk, tv, T, bcol[q], a * bval[q])) atomicAdd(&ctr->error, 1u);
+            }
         }
-    }
-    __syncthreads();
-    // pack keys: lane g owns slots g, g+GL, ...
-    int c = 0;
-#pragma unroll
-    for (int m = 0; m < ITEMS; ++m) {
-        const int s = g + m * GL;
-        if (s < T && tk[s] >= 0) ++c;
-    }
-    int incl = c;
-#pragma unroll
-    for (int o = 1; o < GL; o <<= 1) {
-        const int y = __shfl_up(incl, o, GL);
-        if (g >= o) incl += y;
-    }
-    const int n = __shfl(incl, GL - 1, GL);
-    int pos = incl - c;
-#pragma unroll
-    for (int m = 0; m < ITEMS; ++m) {
-        const int s = g + m * GL;
-        if (s < T && tk[s] >= 0) pk[pos++] = tk[s];
-    }
-    __syncthreads();
-    if (active) {
-        const int64_t base = crpt[row];
-        const int64_t cap = crpt[row + 1] - base;
-        if (g == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+        __syncthreads();
+        // pack keys: lane g owns slots g, g+GL, ...
+        int c = 0;
 #pragma unroll
         for (int m = 0; m < ITEMS; ++m) {
             const int s = g + m * GL;
-            if (s < T) {
-                const int key = tk[s];
-                if (key >= 0) {
-                    int rank = 0;
-                    for (int j = 0; j < n; ++j) rank += pk[j] < key;
-                    if (rank < cap) {
-                        ccol[base + rank] = key;
-                        cval[base + rank] = tv[s];
+            if (s < T && tk[s] >= 0) ++c;
+        }
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < GL; o <<= 1) {
+            const int y = __shfl_up(incl, o, GL);
+            if (g >= o) incl += y;
+        }
+        const int n = __shfl(incl, GL - 1, GL);
+        int pos = incl - c;
+#pragma unroll
+        for (int m = 0; m < ITEMS; ++m) {
+            const int s = g + m * GL;
+            if (s < T && tk[s] >= 0) pk[pos++] = tk[s];
+        }
+        __syncthreads();
+        if (active) {
+            const int64_t base = crpt[row];
+            const int64_t cap = crpt[row + 1] - base;
+            if (g == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+#pragma unroll
+            for (int m = 0; m < ITEMS; ++m) {
+                const int s = g + m * GL;
+                if (s < T) {
+                    const int key = tk[s];
+                    if (key >= 0) {
+                        int rank = 0;
+                        for (int j = 0; j < n; ++j) rank += pk[j] < key;
+                        if (rank < cap) {
+                            ccol[base + rank] = key;
+                            cval[base + rank] = tv[s];
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -254,8 +257,7 @@ __device__ __forceinline__ int team_excl_scan(int x, int &total, int *red) {
 // ---------------------------------------------------------------------------
 template <int W, int T>
 __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
-    int64_t nrows, const int32_t *__restrict__ bins, int64_t bin_off,
-    const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
@@ -270,18 +272,23 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     __shared__ int keys[R * T];
     __shared__ int red[3 * NW];
 
+    src.resolve();
     const int team = threadIdx.x / W, t = threadIdx.x % W;
     const int wv = t >> 6;
-    const int64_t idx = (int64_t)blockIdx.x * R + team;
-    const bool active = idx < nrows;
     int *tk = keys + team * T;
     double *tv = vals + team * T;
+    // one team per row (grids are sized from the numeric bin counts, which
+    // are always read back before this step); every lane of the team makes
+    // the same early returns
+    auto do_row = [&](const int64_t idx) {
+    const bool active = idx < src.nrows;
+    team_sync<WT>();   // the previous row of this team is done with the table
     for (int s = t; s < T; s += W) { tk[s] = -1; tv[s] = 0.0; }
     team_sync<WT>();
 
     int64_t row = 0;
     if (active) {
-        row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
+        row = src.row(idx);
         auto ins = [&](bool ok, int key, double v) {
             num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
                             [](double *p, double x) { atomicAdd(p, x); });
@@ -438,6 +445,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
             }
         }
     }
+    };
+    do_row((int64_t)blockIdx.x * R + team);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,8 +454,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
 // through LDS bitmaps of 2^19 columns at a time.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_num_global(
-    int64_t nrows, const int32_t *__restrict__ bins, int64_t bin_off,
-    const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
@@ -459,12 +467,13 @@ __global__ __launch_bounds__(1024) void k_num_global(
     __shared__ unsigned int red[16];
     __shared__ int s_min, s_max;
 
+    src.resolve();
     int *tk = slab_keys + (int64_t)blockIdx.x * slab_entries;
     double *tv = slab_vals + (int64_t)blockIdx.x * slab_entries;
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
 
-    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int64_t row = bins ? (int64_t)bins[bin_off + r] : bin_off + r;
+    for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
+        const int64_t row = src.row(r);
         const int64_t base = crpt[row];
         const int64_t n = crpt[row + 1] - base;
         uint32_t T = pow2_at_least((uint64_t)(2 * n > 64 ? 2 * n : 64));
@@ -545,25 +554,31 @@ __global__ __launch_bounds__(1024) void k_num_global(
 }
 
 // ---------------------------------------------------------------------------
+static int64_t grid_for(const NumArgs &a, int64_t per_wg) {
+    if (a.grid > 0) return a.grid;
+    return (a.src.nrows + per_wg - 1) / per_wg;
+}
+
 template <int W, int T>
 static hipError_t go_row(const NumArgs &a, hipStream_t s) {
     constexpr int R = (W == 64) ? 4 : 1;
-    const int64_t grid = (a.nrows + R - 1) / R;
-    hipLaunchKernelGGL((k_num_row<W, T>), dim3((unsigned)grid), dim3(W * R), 0, s, a.nrows, a.bins,
-                       a.bin_off, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt,
-                       a.ccol, a.cval, a.ctr);
+    const int64_t grid = (a.src.nrows + R - 1) / R;   // one team per row
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_num_row<W, T>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src, a.A.rpt,
+                       a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
-    if (a.nrows == 0) return hipSuccess;
+    if (!a.src.dctr && !a.src.count && a.src.nrows == 0) return hipSuccess;
     switch (bin) {
         case 0: {
             constexpr int RPW = 256 / NUM_GL;
-            const int64_t grid = (a.nrows + RPW - 1) / RPW;
+            const int64_t grid = grid_for(a, RPW);
+            if (grid <= 0) return hipSuccess;
             hipLaunchKernelGGL((k_num_group<NUM_GL, NUM_T[0]>), dim3((unsigned)grid), dim3(256), 0, s,
-                               a.nrows, a.bins, a.bin_off, a.A.rpt, a.A.col, a.A.val, a.B.rpt,
-                               a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.ctr);
+                               a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt,
+                               a.ccol, a.cval, a.ctr);
             return hipGetLastError();
         }
         case 1: return go_row<NUM_W[1], NUM_T[1]>(a, s);
@@ -574,10 +589,9 @@ hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
         case 6: return go_row<NUM_W[6], NUM_T[6]>(a, s);
         case NUM_GLOBAL_BIN: {
             if (a.grid <= 0) return hipSuccess;
-            hipLaunchKernelGGL(k_num_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.nrows,
-                               a.bins, a.bin_off, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
-                               a.B.val, a.crpt, a.ccol, a.cval, a.slab_keys, a.slab_vals,
-                               a.slab_entries, a.ctr);
+            hipLaunchKernelGGL(k_num_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
+                               a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval,
+                               a.slab_keys, a.slab_vals, a.slab_entries, a.ctr);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

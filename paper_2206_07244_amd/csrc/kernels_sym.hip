@@ -65,8 +65,7 @@ __device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, in
 // bin 0: GL lanes per row
 // ---------------------------------------------------------------------------
 template <int GL, int T>
-__global__ __launch_bounds__(256) void k_sym_group(int64_t nrows, const int32_t *__restrict__ bins,
-                                                   int64_t bin_off, const int64_t *__restrict__ arpt,
+__global__ __launch_bounds__(256) void k_sym_group(RowSrc src, const int64_t *__restrict__ arpt,
                                                    const int32_t *__restrict__ acol,
                                                    const int64_t *__restrict__ brpt,
                                                    const int32_t *__restrict__ bcol,
@@ -74,39 +73,42 @@ __global__ __launch_bounds__(256) void k_sym_group(int64_t nrows, const int32_t 
                                                    Counters *__restrict__ ctr) {
     constexpr int RPW = 256 / GL;
     __shared__ int tab[RPW * T];
+    src.resolve();
     const int slot = threadIdx.x / GL, g = threadIdx.x % GL;
-    const int64_t idx = (int64_t)blockIdx.x * RPW + slot;
-    const bool active = idx < nrows;
     int *t = tab + slot * T;
-    for (int s = g; s < T; s += GL) t[s] = -1;
-    __syncthreads();
-    int cnt = 0;
-    int64_t row = 0;
-    if (active) {
-        row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
-        const int64_t a1 = arpt[row + 1];
-        for (int64_t p = arpt[row] + g; p < a1; p += GL) {
-            const int k = acol[p];
-            const int64_t b1 = brpt[k + 1];
-            for (int64_t q = brpt[k]; q < b1; ++q) {
-                const int r = sym_insert_lds(t, T, bcol[q]);
-                if (r < 0) atomicAdd(&ctr->error, 1u);
-                else cnt += r;
+    for (int64_t b0 = (int64_t)blockIdx.x * RPW; b0 < src.nrows; b0 += (int64_t)gridDim.x * RPW) {
+        const int64_t idx = b0 + slot;
+        const bool active = idx < src.nrows;
+        for (int s = g; s < T; s += GL) t[s] = -1;
+        __syncthreads();
+        int cnt = 0;
+        int64_t row = 0;
+        if (active) {
+            row = src.row(idx);
+            const int64_t a1 = arpt[row + 1];
+            for (int64_t p = arpt[row] + g; p < a1; p += GL) {
+                const int k = acol[p];
+                const int64_t b1 = brpt[k + 1];
+                for (int64_t q = brpt[k]; q < b1; ++q) {
+                    const int r = sym_insert_lds(t, T, bcol[q]);
+                    if (r < 0) atomicAdd(&ctr->error, 1u);
+                    else cnt += r;
+                }
             }
         }
-    }
 #pragma unroll
-    for (int o = GL / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, GL);
-    if (active && g == 0) nnz[row] = cnt;
+        for (int o = GL / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, GL);
+        if (active && g == 0) nnz[row] = cnt;
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
 // bins 1-7: one team (a wave for W == 64, else the workgroup) per row
 // ---------------------------------------------------------------------------
-template <int W, int T, bool ABORT>
+template <int W, int T, bool ABORT, bool PERSIST>
 __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
-    int64_t nrows, const int32_t *__restrict__ bins, int64_t bin_off,
-    const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list) {
     constexpr bool WT = (W == 64);
@@ -116,59 +118,64 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     __shared__ int s_cnt[R];
     __shared__ int s_abort[R];
     __shared__ int red[NW];
+    src.resolve();
 
     const int team = threadIdx.x / W, t = threadIdx.x % W;
-    const int64_t idx = (int64_t)blockIdx.x * R + team;
-    const bool active = idx < nrows;
     int *tb = tab + team * T;
-    for (int s = t; s < T; s += W) tb[s] = -1;
-    if (t == 0) { s_cnt[team] = 0; s_abort[team] = 0; }
-    team_sync<WT>();
-
-    int cnt = 0;
-    int64_t row = 0;
-    if (active) {
-        row = bins ? (int64_t)bins[bin_off + idx] : bin_off + idx;
-        auto ins = [&](bool ok, int key) {
-            const int nw = sym_insert_wave(tb, (uint32_t)T, ok, key, &ctr->error);
-            if constexpr (ABORT) {
-                const unsigned long long m = __ballot(nw);
-                const int nm = (int)__popcll(m);
-                if (nm && lane_id() == 0) {
-                    if (atomicAdd(&s_cnt[team], nm) + nm > abort_thr) s_abort[team] = 1;
-                }
-            } else {
-                cnt += nw;
-            }
-        };
-        auto stop = [&]() -> bool {
-            if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
-            else return false;
-        };
-        row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6, NW,
-                            ins, stop);
-    }
-    if (ABORT) {
+    const int64_t stride = PERSIST ? (int64_t)gridDim.x * R : src.nrows + R;
+    for (int64_t b0 = (int64_t)blockIdx.x * R; b0 < src.nrows; b0 += stride) {
+        const int64_t idx = b0 + team;
+        const bool active = idx < src.nrows;
+        team_sync<WT>();   // the previous row of this team is done with the table
+        for (int s = t; s < T; s += W) tb[s] = -1;
+        if (t == 0) { s_cnt[team] = 0; s_abort[team] = 0; }
         team_sync<WT>();
-        if (active && t == 0) {
-            if (s_abort[team]) {
-                const unsigned f = atomicAdd(&ctr->fail, 1u);
-                fail_list[f] = (int32_t)row;
-            } else {
-                nnz[row] = s_cnt[team];
-            }
+
+        int cnt = 0;
+        int64_t row = 0;
+        if (active) {
+            row = src.row(idx);
+            auto ins = [&](bool ok, int key) {
+                const int nw = sym_insert_wave(tb, (uint32_t)T, ok, key, &ctr->error);
+                if constexpr (ABORT) {
+                    const unsigned long long m = __ballot(nw);
+                    const int nm = (int)__popcll(m);
+                    if (nm && lane_id() == 0) {
+                        if (atomicAdd(&s_cnt[team], nm) + nm > abort_thr) s_abort[team] = 1;
+                    }
+                } else {
+                    cnt += nw;
+                }
+            };
+            auto stop = [&]() -> bool {
+                if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
+                else return false;
+            };
+            row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6,
+                                NW, ins, stop);
         }
-    } else {
-        cnt = wave_sum(cnt);
-        if constexpr (WT) {
-            if (active && t == 0) nnz[row] = cnt;
-        } else {
-            if ((t & 63) == 0) red[t >> 6] = cnt;
-            __syncthreads();
+        if (ABORT) {
+            team_sync<WT>();
             if (active && t == 0) {
-                int sum = 0;
-                for (int i = 0; i < NW; ++i) sum += red[i];
-                nnz[row] = sum;
+                if (s_abort[team]) {
+                    const unsigned f = atomicAdd(&ctr->fail, 1u);
+                    fail_list[f] = (int32_t)row;
+                } else {
+                    nnz[row] = s_cnt[team];
+                }
+            }
+        } else {
+            cnt = wave_sum(cnt);
+            if constexpr (WT) {
+                if (active && t == 0) nnz[row] = cnt;
+            } else {
+                if ((t & 63) == 0) red[t >> 6] = cnt;
+                __syncthreads();
+                if (active && t == 0) {
+                    int sum = 0;
+                    for (int i = 0; i < NW; ++i) sum += red[i];
+                    nnz[row] = sum;
+                }
             }
         }
     }
@@ -178,17 +185,15 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
 // bin 8: global-memory tables, one slab per persistent workgroup
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_sym_global(
-    int64_t nrows_static, const unsigned int *__restrict__ count_dev,
-    const int32_t *__restrict__ rows, int64_t bin_off, const int64_t *__restrict__ arpt,
-    const int32_t *__restrict__ acol, const int64_t *__restrict__ brpt,
-    const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz, int64_t ncols, int *slabs,
-    int64_t slab_entries, Counters *__restrict__ ctr) {
+    RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
+    int64_t ncols, int *slabs, int64_t slab_entries, Counters *__restrict__ ctr) {
     __shared__ int red[16];
+    src.resolve();
     int *tb = slabs + (int64_t)blockIdx.x * slab_entries;
-    const int64_t nrows = count_dev ? (int64_t)*count_dev : nrows_static;
     const int t = threadIdx.x;
-    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int64_t row = rows ? (int64_t)rows[bin_off + r] : bin_off + r;
+    for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
+        const int64_t row = src.row(r);
         // C.rpt[row] still holds n_prod for rows that reach this kernel
         const int64_t np = nnz[row];
         const int64_t bound = np < ncols ? np : ncols;
@@ -213,25 +218,36 @@ __global__ __launch_bounds__(1024) void k_sym_global(
 }
 
 // ---------------------------------------------------------------------------
+static int64_t grid_for(const SymArgs &a, int64_t per_wg) {
+    if (a.grid > 0) return a.grid;
+    return (a.src.nrows + per_wg - 1) / per_wg;
+}
+
 template <int W, int T, bool ABORT>
 static hipError_t go_row(const SymArgs &a, hipStream_t s) {
     constexpr int R = (W == 64) ? 4 : 1;
-    const int64_t grid = (a.nrows + R - 1) / R;
-    hipLaunchKernelGGL((k_sym_row<W, T, ABORT>), dim3((unsigned)grid), dim3(W * R), 0, s, a.nrows,
-                       a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr,
-                       a.ctr, a.fail_list);
+    const int64_t grid = grid_for(a, R);
+    if (grid <= 0) return hipSuccess;
+    if (a.grid > 0)
+        hipLaunchKernelGGL((k_sym_row<W, T, ABORT, true>), dim3((unsigned)grid), dim3(W * R), 0, s,
+                           a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
+                           a.fail_list);
+    else
+        hipLaunchKernelGGL((k_sym_row<W, T, ABORT, false>), dim3((unsigned)grid), dim3(W * R), 0, s,
+                           a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
+                           a.fail_list);
     return hipGetLastError();
 }
 
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
-    if (bin != SYM_GLOBAL_BIN && a.nrows == 0) return hipSuccess;
+    if (!a.src.dctr && !a.src.count && a.src.nrows == 0) return hipSuccess;
     switch (bin) {
         case 0: {
             constexpr int RPW = 256 / SYM_GL;
-            const int64_t grid = (a.nrows + RPW - 1) / RPW;
+            const int64_t grid = grid_for(a, RPW);
+            if (grid <= 0) return hipSuccess;
             hipLaunchKernelGGL((k_sym_group<SYM_GL, SYM_T[0]>), dim3((unsigned)grid), dim3(256), 0, s,
-                               a.nrows, a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz,
-                               a.ctr);
+                               a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.ctr);
             return hipGetLastError();
         }
         case 1: return go_row<SYM_W[1], SYM_T[1], false>(a, s);
@@ -243,9 +259,9 @@ hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
         case 7: return go_row<SYM_W[7], SYM_T[7], true>(a, s);
         case SYM_GLOBAL_BIN: {
             if (a.grid <= 0) return hipSuccess;
-            hipLaunchKernelGGL(k_sym_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.nrows,
-                               a.count_dev, a.bins, a.bin_off, a.A.rpt, a.A.col, a.B.rpt, a.B.col,
-                               a.nnz, a.B.cols, a.slab, a.slab_entries, a.ctr);
+            hipLaunchKernelGGL(k_sym_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
+                               a.A.col, a.B.rpt, a.B.col, a.nnz, a.B.cols, a.slab, a.slab_entries,
+                               a.ctr);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

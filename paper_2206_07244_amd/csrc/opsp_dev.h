@@ -53,6 +53,32 @@ struct Counters {
     unsigned long long pad[6];
 };
 
+// Where a kernel finds the rows of its bin.  Host mode: `nrows` rows listed
+// from position `off` of `bins` (rows off, off+1, ... when bins == NULL).
+// Device mode (used by captured graphs, whose grids cannot depend on the
+// data): with `dctr` the bin's size and start are read from the binning
+// counters; with `count` the row count is read from device memory.  Kernels
+// walk their rows with grid-stride loops, so any grid size is valid.
+struct RowSrc {
+    const int32_t *bins;
+    int64_t off, nrows;
+    const Counters *dctr;
+    const unsigned int *count;
+    int bin;
+    __device__ __forceinline__ void resolve() {
+        if (dctr) {
+            nrows = (int64_t)dctr->size[bin];
+            int64_t o = 0;
+            for (int j = 0; j < bin; ++j) o += (int64_t)dctr->size[j];
+            off = o;
+        }
+        if (count) nrows = (int64_t)*count;
+    }
+    __device__ __forceinline__ int64_t row(int64_t idx) const {
+        return bins ? (int64_t)bins[off + idx] : off + idx;
+    }
+};
+
 // Wave helpers ---------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }

@@ -40,6 +40,7 @@ struct opsp_plan {
     int64_t num_off[OPSP_NUM_BINS] = {};
     int identity_bin = -1;              // bin holding all rows when bins == NULL
     bool check = false;
+    int64_t fixed_grid = 0;             // > 0: every bin kernel runs persistently with this grid
     Counters *ctr = nullptr;            // device counters (numeric step), owned
     opsp_stats stats = {};
 };
@@ -206,6 +207,15 @@ struct Timer {
     }
 };
 
+RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows) {
+    RowSrc r;
+    memset(&r, 0, sizeof(r));
+    r.bins = bins;
+    r.off = off;
+    r.nrows = nrows;
+    return r;
+}
+
 // Steps 1-5: everything up to C's row pointer and the numeric bins.
 opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config *cfg,
                          hipStream_t s, opsp_plan *plan, Timer &tm) {
@@ -219,6 +229,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     plan->K = A->cols;
     plan->N = N;
     plan->check = cfg && cfg->validate;
+    plan->fixed_grid = cfg ? cfg->fixed_grid : 0;
 
     Arena ar(s);
     void *p = nullptr;
@@ -294,9 +305,9 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     }
     for (int b = 7; b >= 0; --b) {
         if (ssz[b] == 0) continue;
-        sa.bins = (sym_identity == b) ? nullptr : bins;
-        sa.bin_off = (sym_identity == b) ? 0 : soff[b];
-        sa.nrows = ssz[b];
+        sa.src = host_rows((sym_identity == b) ? nullptr : bins, (sym_identity == b) ? 0 : soff[b], ssz[b]);
+        sa.grid = 0;
+        if (plan->fixed_grid > 0) sa.grid = plan->fixed_grid < ssz[b] ? plan->fixed_grid : ssz[b];
         if (b == 7) {
             const double frac = cfg && cfg->sym_abort_fraction != 0 ? cfg->sym_abort_fraction : 0.8;
             int64_t thr = frac < 0 ? -1 : (int64_t)(frac * SYM_T[7]);
@@ -311,10 +322,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
             CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
             slab = (int *)p;
             SymArgs g = sa;
-            g.bins = fail_list;
-            g.bin_off = 0;
-            g.nrows = ssz[7];
-            g.count_dev = &ctrS->fail;
+            g.src = host_rows(fail_list, 0, ssz[7]);
+            g.src.count = &ctrS->fail;
             g.slab = slab;
             g.slab_entries = slab_entries;
             g.grid = ssz[7] < sgrid ? ssz[7] : sgrid;
@@ -327,13 +336,11 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
             slab = (int *)p;
         }
         SymArgs g = sa;
-        g.bins = (sym_identity == SYM_GLOBAL_BIN) ? nullptr : bins;
-        g.bin_off = (sym_identity == SYM_GLOBAL_BIN) ? 0 : soff[SYM_GLOBAL_BIN];
-        g.nrows = ssz[SYM_GLOBAL_BIN];
-        g.count_dev = nullptr;
+        g.src = host_rows((sym_identity == SYM_GLOBAL_BIN) ? nullptr : bins,
+                          (sym_identity == SYM_GLOBAL_BIN) ? 0 : soff[SYM_GLOBAL_BIN], ssz[SYM_GLOBAL_BIN]);
         g.slab = slab;
         g.slab_entries = slab_entries;
-        g.grid = g.nrows < sgrid ? g.nrows : sgrid;
+        g.grid = g.src.nrows < sgrid ? g.src.nrows : sgrid;
         CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
     }
     tm.mark();
@@ -393,9 +400,10 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     for (int b = gb; b >= 0; --b) {
         const int64_t rows = plan->num_size[b];
         if (rows == 0) continue;
-        na.bins = (plan->identity_bin == b) ? nullptr : plan->bins;
-        na.bin_off = (plan->identity_bin == b) ? 0 : plan->num_off[b];
-        na.nrows = rows;
+        na.src = host_rows((plan->identity_bin == b) ? nullptr : plan->bins,
+                           (plan->identity_bin == b) ? 0 : plan->num_off[b], rows);
+        na.grid = 0;
+        if (plan->fixed_grid > 0 && b == 0) na.grid = plan->fixed_grid < rows ? plan->fixed_grid : rows;
         if (b == gb) {
             const int64_t entries = pow2_host(2 * plan->max_nnz > 64 ? 2 * plan->max_nnz : 64);
             const int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;

@@ -59,16 +59,13 @@ hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counter
 struct SymArgs {
     DevCSR A, B;
     int64_t *nnz;            // in: n_prod per row (C.rpt); out: distinct columns per row
-    const int32_t *bins;     // row list of the bin (NULL = identity rows bin_off..)
-    int64_t bin_off;         // offset of the bin in `bins`
-    int64_t nrows;           // rows in the bin
+    RowSrc src;              // rows of the bin
     int abort_thr;           // bin 7: abandon a row above this many keys
-    Counters *ctr;           // fail counter
+    Counters *ctr;           // fail / error counters
     int32_t *fail_list;      // abandoned rows (bin 7)
     int *slab;               // global tables (bin 8)
     int64_t slab_entries;
-    int64_t grid;            // persistent grid for bin 8
-    const unsigned int *count_dev;  // bin 8: device row count (NULL = nrows)
+    int64_t grid;            // fixed grid (persistent launch); 0 = one team per row
 };
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
 
@@ -78,9 +75,7 @@ struct NumArgs {
     const int64_t *crpt;     // C row pointer (exclusive offsets, crpt[M] = nnz)
     int32_t *ccol;
     double *cval;
-    const int32_t *bins;
-    int64_t bin_off;
-    int64_t nrows;
+    RowSrc src;              // rows of the bin
     Counters *ctr;           // error counter
     int *slab_keys;          // global tables (bin 7)
     double *slab_vals;

@@ -184,3 +184,22 @@ def test_structure_deterministic_over_runs():
             first = (r, c)
         else:
             assert np.array_equal(first[0], r) and np.array_equal(first[1], c)
+
+
+@pytest.mark.parametrize("b", list(range(9)))
+def test_forced_bins_persistent_launch(b):
+    """Symbolic bin kernels (and numeric bin 0) launched with a small fixed
+    grid, so each workgroup walks many rows (the launch form of captured
+    graphs)."""
+    ops = _ops()
+    st = ops.Stats()
+    cfg = ops.Config(force_sym_bin=b, force_num_bin=0 if b == 0 else -1, validate=1, fixed_grid=7)
+    check(syn.rmat(12, 16, seed=13), cfg=cfg, stats=st)
+    assert st.sym_bin_rows[b] > 0
+
+
+def test_persistent_launch_all_bins_rmat14():
+    ops = _ops()
+    st = ops.Stats()
+    check(syn.rmat(14, 16, seed=14), cfg=ops.Config(validate=1, fixed_grid=5), stats=st)
+    assert all(x > 0 for x in st.num_bin_rows)
