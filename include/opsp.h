@@ -156,6 +156,37 @@ void opsp_plan_destroy(opsp_plan *plan);
  * zero *C.  NULL arrays are skipped. */
 opsp_status opsp_csr_free(opsp_csr *C, void *stream);
 
+/* ---- Batched products --------------------------------------------------
+ * `count` independent products C_p = A_p * B_p computed as ONE block-diagonal
+ * product over the concatenation of their rows (rows of C are independent,
+ * Section 2.1): one pass of setup, binning, symbolic, scan and numeric covers
+ * all problems.  The work runs as two captured graphs: the structure graph
+ * (everything up to the row pointer, with the symbolic bin kernels launched
+ * persistently because their bin sizes are only known on the device) and,
+ * after one host read-back of nnz and the numeric bin sizes, the value graph
+ * (value gather + numeric kernels).  Both graphs are replayed by later
+ * executions of the same batch object.
+ *
+ * opsp_batch_create: A[p], B[p] (device CSR, A[p].cols == B[p].rows) are
+ *   borrowed by the batch object until it is destroyed; their structure must
+ *   not change, their values may (each execution reads them).  Problems may
+ *   be empty.  1 <= count <= 65535.
+ * opsp_batch_execute: fills C[0..count) with views into storage owned by the
+ *   batch: C[p].rpt points into a shared row pointer holding absolute offsets
+ *   (C[p].rpt[0] is generally not 0), C[p].col / C[p].val are the shared
+ *   arrays.  Views stay valid until the next execution or destroy.  The host
+ *   blocks once per execution (the read-back); C is complete when the stream
+ *   reaches the point of return.  stats may be NULL.
+ * opsp_spgemm_batched: create + execute; *owner receives the batch object
+ *   that owns the views (release with opsp_batch_destroy). */
+typedef struct opsp_batch opsp_batch;
+opsp_status opsp_batch_create(int32_t count, const opsp_csr *A, const opsp_csr *B,
+                              const opsp_config *config, opsp_batch **batch, void *stream);
+opsp_status opsp_batch_execute(opsp_batch *batch, opsp_csr *C, opsp_stats *stats, void *stream);
+void opsp_batch_destroy(opsp_batch *batch);
+opsp_status opsp_spgemm_batched(int32_t count, const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
+                                const opsp_config *config, opsp_batch **owner, void *stream);
+
 /* Device memory of the library (workspaces and C arrays) comes from a
  * per-device cache: blocks released by the library or by opsp_csr_free are
  * kept, per stream and size class, and handed out again to later calls on the

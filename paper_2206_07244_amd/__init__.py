@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "DeviceCSR", "Plan", "OpspError", "Config", "Stats", "spgemm", "spgemm_symbolic",
     "spgemm_numeric", "lib", "library_path", "exported_symbols", "table_sizes", "bin_bounds",
-    "SYM_BINS", "NUM_BINS", "cache_release", "cache_bytes",
+    "SYM_BINS", "NUM_BINS", "cache_release", "cache_bytes", "Batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -109,6 +109,15 @@ def lib():
         L.opsp_plan_destroy.argtypes = [c_void_p]
         L.opsp_csr_free.restype = ctypes.c_int
         L.opsp_csr_free.argtypes = [csr_p, P]
+        L.opsp_batch_create.restype = ctypes.c_int
+        L.opsp_batch_create.argtypes = [c_int32, csr_p, csr_p, POINTER(Config), POINTER(c_void_p), P]
+        L.opsp_batch_execute.restype = ctypes.c_int
+        L.opsp_batch_execute.argtypes = [c_void_p, csr_p, POINTER(Stats), P]
+        L.opsp_batch_destroy.restype = None
+        L.opsp_batch_destroy.argtypes = [c_void_p]
+        L.opsp_spgemm_batched.restype = ctypes.c_int
+        L.opsp_spgemm_batched.argtypes = [c_int32, csr_p, csr_p, csr_p, POINTER(Config),
+                                          POINTER(c_void_p), P]
         L.opsp_cache_release.restype = ctypes.c_int
         L.opsp_cache_release.argtypes = []
         L.opsp_cache_bytes.restype = c_int64
@@ -324,3 +333,72 @@ def spgemm_numeric(plan: Plan, A: DeviceCSR, B: DeviceCSR, out: Optional[DeviceC
     if out is not None:
         return out
     return _adopt(Cc, s, A.rpt.device)
+
+
+# ---------------------------------------------------------------------------
+# Batched products
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Many independent products C_p = A_p B_p as one block-diagonal product
+    (``opsp_batch_*``).  ``execute()`` returns views into storage the batch
+    owns; they stay valid until the next ``execute`` or until every view and
+    the batch object are gone."""
+
+    def __init__(self, As, Bs, config: Optional[Config] = None, stream=None):
+        assert len(As) == len(Bs) and len(As) > 0
+        self.As, self.Bs = list(As), list(Bs)      # keep the inputs alive
+        self.count = len(As)
+        self._a = (opsp_csr * self.count)(*[a._c() for a in As])
+        self._b = (opsp_csr * self.count)(*[b._c() for b in Bs])
+        self._s = _stream_handle(stream)
+        h = c_void_p()
+        _check(lib().opsp_batch_create(self.count, self._a, self._b,
+                                       byref(config) if config is not None else None,
+                                       byref(h), self._s), "opsp_batch_create")
+        self.handle = h.value
+        self.device = As[0].rpt.device
+
+    def execute(self, stats: Optional[Stats] = None, stream=None):
+        s = self._s if stream is None else _stream_handle(stream)
+        C = (opsp_csr * self.count)()
+        _check(lib().opsp_batch_execute(self.handle, C, byref(stats) if stats is not None else None,
+                                        s), "opsp_batch_execute")
+        torch = _torch()
+        res = []
+        for c in C:
+            rpt = _wrap(c.rpt, c.rows + 1, torch.int64, self, self.device)
+            lo = int(rpt[0].item()) if rpt.numel() else 0
+            res.append(_BatchView(c.rows, c.cols, rpt, lo, c.nnz, c.col, c.val, self))
+        return res
+
+    def raw_execute(self, stream_handle, C=None):
+        """Lowest-overhead execution (benchmark): fills a ctypes array."""
+        if C is None:
+            C = (opsp_csr * self.count)()
+        _check(lib().opsp_batch_execute(self.handle, C, None, stream_handle), "opsp_batch_execute")
+        return C
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.opsp_batch_destroy(self.handle)
+            self.handle = None
+
+
+class _BatchView:
+    """One C_p of a batch: row pointer with absolute offsets into the shared
+    col/val arrays."""
+
+    def __init__(self, rows, cols, rpt, lo, nnz, colp, valp, owner):
+        self.rows, self.cols, self.rpt, self.lo, self.nnz = rows, cols, rpt, lo, nnz
+        self._colp, self._valp, self._owner = colp, valp, owner
+
+    def to_host(self):
+        torch = _torch()
+        rpt = self.rpt.cpu().numpy()
+        n = int(self.nnz)
+        if n == 0:
+            return rpt - rpt[0], np.zeros(0, np.int32), np.zeros(0, np.float64)
+        col = _wrap(self._colp + 4 * self.lo, n, torch.int32, self._owner, self._owner.device)
+        val = _wrap(self._valp + 8 * self.lo, n, torch.float64, self._owner, self._owner.device)
+        return rpt - rpt[0], col.cpu().numpy(), val.cpu().numpy()
