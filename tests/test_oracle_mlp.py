@@ -1,0 +1,166 @@
+"""Pins of the predictor reference (oracle/mlp.py) against things other than
+itself: central finite differences, torch's float64 autograd and Adam, torch's
+bfloat16 conversion, closed-form networks and the capacity invariants."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+
+
+def rand_batch(B, seed):
+    r = np.random.default_rng(seed)
+    alen = r.integers(0, 40, B)
+    nprod = alen * r.integers(1, 60, B) + r.integers(0, 5, B)
+    bmax = np.minimum(r.integers(0, 60, B), nprod)
+    X = mlp.features(alen, nprod, bmax)
+    t = mlp.target(np.maximum(bmax, (nprod * r.uniform(0.2, 1.0, B)).astype(np.int64)))
+    return X, t
+
+
+def test_param_count():
+    assert mlp.NPARAM == 64 * 3 + 64 + 64 * 64 + 64 + 64 + 1 == 4481
+
+
+def test_grad_matches_central_differences():
+    X, t = rand_batch(37, 1)
+    th = mlp.init(3)
+    th[mlp.NPARAM - 1] = 0.3
+    th += np.random.default_rng(4).normal(0, 0.05, th.shape)   # nonzero biases
+    _, g = mlp.grad(th, X, t, quant=False)
+    h = 1e-6
+    idx = np.random.default_rng(5).choice(mlp.NPARAM, 300, replace=False)
+    idx = np.unique(np.concatenate([idx, np.arange(0, 192, 17), [4480, 4479, 4416, 4352]]))
+    for i in idx:
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (mlp.loss(tp, X, t, quant=False) - mlp.loss(tm, X, t, quant=False)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def torch_net(th):
+    p = mlp.unpack(th)
+    net = torch.nn.Sequential(torch.nn.Linear(3, 64), torch.nn.ReLU(), torch.nn.Linear(64, 64),
+                              torch.nn.ReLU(), torch.nn.Linear(64, 1)).double()
+    with torch.no_grad():
+        net[0].weight.copy_(torch.from_numpy(p["W1"]))
+        net[0].bias.copy_(torch.from_numpy(p["b1"]))
+        net[2].weight.copy_(torch.from_numpy(p["W2"]))
+        net[2].bias.copy_(torch.from_numpy(p["b2"]))
+        net[4].weight.copy_(torch.from_numpy(p["W3"]))
+        net[4].bias.copy_(torch.from_numpy(p["b3"]))
+    return net
+
+
+def test_forward_and_grad_match_torch_float64():
+    X, t = rand_batch(200, 2)
+    th = mlp.init(7) + np.random.default_rng(8).normal(0, 0.05, mlp.NPARAM)
+    net = torch_net(th)
+    xt = torch.from_numpy(X)
+    y = net(xt)[:, 0]
+    L = torch.mean((y - torch.from_numpy(t)) ** 2)
+    L.backward()
+    yo, _ = mlp.forward(th, X, quant=False)
+    lo, go = mlp.grad(th, X, t, quant=False)
+    np.testing.assert_allclose(yo, y.detach().numpy(), rtol=1e-12, atol=1e-12)
+    assert abs(lo - L.item()) <= 1e-12 * max(1, L.item())
+    gt = np.concatenate([net[0].weight.grad.numpy().ravel(), net[0].bias.grad.numpy(),
+                         net[2].weight.grad.numpy().ravel(), net[2].bias.grad.numpy(),
+                         net[4].weight.grad.numpy().ravel(), net[4].bias.grad.numpy()])
+    np.testing.assert_allclose(go, gt, rtol=1e-10, atol=1e-13)
+
+
+def test_round_bf16_matches_torch():
+    r = np.random.default_rng(9)
+    x = np.concatenate([r.normal(0, 1, 20000), r.normal(0, 1e-30, 200), r.normal(0, 1e30, 200),
+                        [0.0, -0.0, 1.0, -1.0, 3.0e38, 1e-40]]).astype(np.float32)
+    # exact ties: low 16 bits 0x8000 with even and odd kept parts
+    bits = (r.integers(0, 1 << 6, 500).astype(np.uint32) << 17) | (r.integers(100, 150, 500).astype(np.uint32) << 23)
+    ties = np.concatenate([(bits | 0x8000).view(np.float32), (bits | 0x18000).view(np.float32)])
+    x = np.concatenate([x, ties])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(mlp.round_bf16(x), ref)
+    np.testing.assert_array_equal(mlp.from_bf16_bits(mlp.bf16_bits(x)), ref)
+
+
+def test_quantised_layer1_matches_torch_float32_ops():
+    X, _ = rand_batch(500, 3)
+    th = mlp.round_bf16(mlp.init(11) + np.random.default_rng(12).normal(0, 0.1, mlp.NPARAM))
+    p = mlp.unpack(th)
+    z, h = mlp.layer1(p["W1"], p["b1"], X, quant=True)
+    x = torch.from_numpy(X.astype(np.float32))
+    w = torch.from_numpy(p["W1"].astype(np.float32))
+    b = torch.from_numpy(p["b1"].astype(np.float32))
+    zt = b[None, :] + w[None, :, 0] * x[:, 0:1]
+    zt = zt + w[None, :, 1] * x[:, 1:2]
+    zt = zt + w[None, :, 2] * x[:, 2:3]
+    np.testing.assert_array_equal(z, zt.double().numpy())
+    ht = torch.relu(zt).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(h, ht)
+    # the quantised forward differs from the exact one only through h1
+    y, (_, _, h1, _, _) = mlp.forward(th, X, quant=True)
+    y2, (_, _, h1x, _, _) = mlp.forward(th, X, quant=False)
+    assert np.max(np.abs(h1 - h1x)) <= 2.0 ** -8 * np.max(np.abs(h1x)) + 1e-6
+
+
+def test_closed_form_network():
+    """A network that computes x0 + 2 x1 + 3 x2 + 0.5 on nonnegative inputs:
+    three pass-through neurons in each hidden layer."""
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    p["W1"][0, 0] = p["W1"][1, 1] = p["W1"][2, 2] = 1.0
+    p["W2"][0, 0] = p["W2"][1, 1] = p["W2"][2, 2] = 1.0
+    p["W3"][0, :3] = [1.0, 2.0, 3.0]
+    p["b3"][0] = 0.5
+    th = mlp.pack(p)
+    X = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 3.0], [0.5, 0.25, 4.0], [10.0, 11.5, 7.0]])
+    for q in (True, False):
+        y, _ = mlp.forward(th, X, quant=q)
+        np.testing.assert_array_equal(y, X @ [1.0, 2.0, 3.0] + 0.5)
+    _, g = mlp.grad(th, X, X @ [1.0, 2.0, 3.0] + 0.5, quant=False)
+    np.testing.assert_array_equal(g, 0.0)   # exact fit, zero loss
+
+
+def test_adam_matches_torch():
+    r = np.random.default_rng(13)
+    th0 = r.normal(0, 1, 50)
+    w = torch.tensor(th0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([w], lr=3e-3, betas=(0.85, 0.995), eps=1e-7)
+    th, m, v = th0.copy(), np.zeros(50), np.zeros(50)
+    for step in range(1, 8):
+        g = r.normal(0, 1, 50) * (step % 3 + 0.1)
+        w.grad = torch.from_numpy(g.copy())
+        opt.step()
+        th, m, v = mlp.adam_step(th, m, v, g, step, lr=3e-3, b1=0.85, b2=0.995, eps=1e-7)
+        np.testing.assert_allclose(th, w.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_adam_training_reduces_loss():
+    X, t = rand_batch(512, 21)
+    th = mlp.init(22)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    l0 = mlp.loss(th, X, t)
+    for step in range(1, 301):
+        _, g = mlp.grad(th, X, t)
+        th, m, v = mlp.adam_step(th, m, v, g, step, lr=3e-3)
+    assert mlp.loss(th, X, t) < 0.1 * l0
+
+
+def test_capacity_rules():
+    pred = np.log2(1 + np.array([10.0, 10.0, 0.0, 1000.0, 3.2, 5.0]))
+    alen = np.array([3, 1, 4, 5, 2, 0])
+    nprod = np.array([40, 7, 12, 50, 30, 0])
+    bmax = np.array([12, 7, 5, 20, 9, 0])
+    cap = mlp.capacity(pred, 0.25, alen, nprod, bmax, ncols=45)
+    # ceil(10*1.25)=13 within [12, 40]; a_len<=1 exact; 0 -> b_max; 1250 -> min(50,45);
+    # ceil(3.2*1.25)=4 -> b_max 9; empty row 0
+    np.testing.assert_array_equal(cap, [13, 7, 5, 45, 9, 0])
+    r = np.random.default_rng(5)
+    n = 1000
+    alen = r.integers(0, 30, n)
+    nprod = alen * r.integers(0, 30, n)
+    bmax = np.minimum(r.integers(0, 30, n), nprod)
+    cap = mlp.capacity(r.normal(4, 3, n), 0.1, alen, nprod, bmax, ncols=200)
+    hi = np.minimum(nprod, 200)
+    assert np.all((cap >= np.minimum(bmax, hi)) & (cap <= np.maximum(hi, nprod * (alen <= 1))))
