@@ -52,10 +52,15 @@ def main():
     ap.add_argument("--workload", default="st27_100")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "learned"],
                     help="plain: the headline product; batched: 512 uneven products as one "
-                         "batch vs 512 plain calls")
+                         "batch vs 512 plain calls; learned: one-phase product with the trained "
+                         "predictor vs the plain two-phase product and the upper-bound rule")
     ap.add_argument("--count", type=int, default=512, help="problems in the batched mode")
+    ap.add_argument("--panel", default="", help="learned mode: 'k/P' = the k-th of P row panels "
+                                                 "of equal n_prod (for products beyond HBM)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="plain mode: skip the one-phase comparison on the same workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -76,6 +81,8 @@ def main():
 
     if args.mode == "batched":
         return bench_batched(args, dev)
+    if args.mode == "learned":
+        return bench_learned(args, dev)
 
     desc, builder = syn.WORKLOADS[args.workload]
     t0 = time.time()
@@ -165,6 +172,14 @@ def main():
                      "total": round(stage[4], 4)},
     }
 
+    if not args.no_learned and os.path.exists(ops.DEFAULT_WEIGHTS):
+        pred = ops.Predictor.load(device=dev)
+        r = time_learned(ops, torch, dA, dA, pred, args.steps, args.warmup)
+        out["learned"] = {"value": round(2.0 * nprod / (r["ms"] * 1e-3) / 1e9, 3),
+                          "ms_per_step": round(r["ms"], 4),
+                          "speedup_vs_plain": round(ms / r["ms"], 4), **r["stats"]}
+        log(f"learned one-phase: {r['ms']:.3f} ms/step ({ms / r['ms']:.3f}x plain)")
+
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
@@ -181,6 +196,129 @@ def main():
                                          "single-threaded C oracle (symbolic + numeric)"}
         log(f"cpu oracle: {cpu_gflops:.3f} GFLOPS over {reps} run(s)")
 
+    print(json.dumps(out), flush=True)
+
+
+def time_learned(ops, torch, dA, dB, pred, steps, warmup):
+    """ms per one-phase product (opsp_spgemm_learned, C allocated and freed
+    inside the timed region) and the predictor statistics of one call."""
+    sh = torch.cuda.current_stream().cuda_stream
+    Ac, Bc = dA._c(), dB._c()
+    ps = pred.struct()
+    L = ops.lib()
+    st = ops.Stats()
+
+    def once(stats=None):
+        C = ops.opsp_csr()
+        code = L.opsp_spgemm_learned(ops.byref(Ac), ops.byref(Bc), ops.byref(C), ops.byref(ps),
+                                     None, ops.byref(stats) if stats is not None else None, sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_learned")
+        ops.free_raw(C, sh)
+    once(st)
+    for _ in range(max(warmup, 1)):
+        once()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / steps
+    cfg = ops.Config(stage_timing=1)
+    C = ops.opsp_csr()
+    s2 = ops.Stats()
+    code = L.opsp_spgemm_learned(ops.byref(Ac), ops.byref(Bc), ops.byref(C), ops.byref(ps),
+                                 ops.byref(cfg), ops.byref(s2), sh)
+    if code:
+        raise ops.OpspError(code, "opsp_spgemm_learned")
+    ops.free_raw(C, sh)
+    torch.cuda.synchronize()
+    nnz = max(st.nnz, 1)
+    return {"ms": ms, "stats": {
+        "cap_over_nnz": round(st.cap_total / nnz, 4),
+        "slot_overflow_rows": st.slot_overflow_rows, "table_overflow_rows": st.table_overflow_rows,
+        "retry_rows": st.retry_rows, "arena_entries": st.arena_entries,
+        "stage_ms": {"setup_caps_bins": round(s2.ms_stage[0], 4), "numeric": round(s2.ms_stage[1], 4),
+                     "scan_retry_alloc": round(s2.ms_stage[2], 4), "copy": round(s2.ms_stage[3], 4),
+                     "total": round(s2.ms_stage[4], 4)}}}
+
+
+def time_plain(ops, torch, dA, dB, steps, warmup):
+    sh = torch.cuda.current_stream().cuda_stream
+    Ac, Bc = dA._c(), dB._c()
+    st = ops.Stats()
+    for i in range(max(warmup, 1)):
+        Cc = ops.opsp_csr()
+        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Bc), ops.byref(Cc), None,
+                                        ops.byref(st), sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_ex")
+        ops.free_raw(Cc, sh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        ops.free_raw(ops.spgemm_raw(Ac, Bc, sh), sh)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t1) * 1e3 / steps, st
+
+
+def bench_learned(args, dev):
+    """One-phase product with the trained predictor against the plain
+    two-phase product and the upper-bound one-phase rule (cap = min(n_prod,
+    N)), on the same inputs; optionally on one row panel of equal n_prod."""
+    import numpy as np
+    import torch
+    import synthetic as syn
+    import paper_2206_07244_amd as ops
+
+    desc, builder = syn.WORKLOADS[args.workload]
+    t0 = time.time()
+    A = builder()
+    log(f"workload {args.workload}: {A.rows} rows, {A.nnz} nnz ({time.time() - t0:.1f}s)")
+    dA = ops.DeviceCSR.from_host(A, dev)
+    dB = dA
+    panel = None
+    if args.panel:
+        k, P = (int(x) for x in args.panel.split("/"))
+        _, npd, _ = ops.row_features(dA, dA)
+        cum = np.cumsum(npd.cpu().numpy())
+        tot = int(cum[-1])
+        r0 = int(np.searchsorted(cum, tot * k / P, side="right")) if k else 0
+        r1 = int(np.searchsorted(cum, tot * (k + 1) / P, side="right")) if k + 1 < P else A.rows
+        dA = ops.DeviceCSR(r1 - r0, A.cols, dA.rpt[r0:r1 + 1], dA.col, dA.val)
+        panel = {"panel": args.panel, "rows": [r0, r1]}
+        log(f"row panel {args.panel}: rows [{r0}, {r1})")
+    del A
+    pred = ops.Predictor.load(device=dev)
+    ms_plain, st = time_plain(ops, torch, dA, dB, args.steps, args.warmup)
+    nprod, nnzC = st.nprod, st.nnz
+    log(f"plain: {ms_plain:.3f} ms, nprod={nprod}, nnz={nnzC}")
+    rl = time_learned(ops, torch, dA, dB, pred, args.steps, args.warmup)
+    log(f"learned: {rl['ms']:.3f} ms {rl['stats']}")
+    ru = time_learned(ops, torch, dA, dB, ops.Predictor(ops.PRED_UPPER), args.steps, args.warmup)
+    log(f"upper-bound rule: {ru['ms']:.3f} ms {ru['stats']}")
+    gf = lambda t: round(2.0 * nprod / (t * 1e-3) / 1e9, 3)
+    out = {
+        "metric": METRIC,
+        "value": gf(rl["ms"]),
+        "unit": "GFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(rl["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "rows": dA.rows,
+                   "nprod": nprod, "nnzC": nnzC, "path": "learned one-phase", **(panel or {})},
+        "learned": {"ms_per_step": round(rl["ms"], 4), **rl["stats"]},
+        "plain": {"value": gf(ms_plain), "ms_per_step": round(ms_plain, 4)},
+        "upper_bound_rule": {"value": gf(ru["ms"]), "ms_per_step": round(ru["ms"], 4), **ru["stats"]},
+        "speedup_vs_plain": round(ms_plain / rl["ms"], 4),
+        "speedup_vs_upper_bound_rule": round(ru["ms"] / rl["ms"], 4),
+    }
     print(json.dumps(out), flush=True)
 
 

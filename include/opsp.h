@@ -62,8 +62,9 @@ typedef struct {
 
 /* Optional tuning / test controls.  Pass NULL for the defaults.
  * Set `version` to OPSP_CONFIG_VERSION; zero-initialised fields take their
- * defaults. */
-#define OPSP_CONFIG_VERSION 1
+ * defaults.  Version 1 structs (without the explicit bin bounds) are still
+ * accepted. */
+#define OPSP_CONFIG_VERSION 2
 typedef struct {
     int32_t version;
     /* Binning ratio (Section 5.7): a row goes to the first table whose size is
@@ -93,6 +94,15 @@ typedef struct {
      * grid-stride loop (the launch form that captured graphs use for the
      * symbolic step); 0 = one team per row. */
     int32_t fixed_grid;
+    /* Version >= 2: explicit inclusive upper bounds of bins 0..6 of each
+     * step (symbolic: on n_prod, bin 7 takes larger rows; numeric: on nnz,
+     * bin 7 = global tables takes larger rows).  0 = from the ratio,
+     * -1 = the bin takes no rows, otherwise at most the bin's table size
+     * (opsp_table_sizes).  A row goes to the first bin whose bound it does
+     * not exceed, so the bounds need not be monotone.  This is what the
+     * autotuner searches. */
+    int64_t sym_bounds[7];
+    int64_t num_bounds[7];
 } opsp_config;
 
 /* Counters of one call (filled when a stats pointer is given). */
@@ -104,9 +114,18 @@ typedef struct {
     int64_t sym_bin_rows[OPSP_SYM_BINS];   /* rows per symbolic bin; [8] = rows recomputed globally */
     int64_t num_bin_rows[OPSP_NUM_BINS];
     /* Stage times in ms when config.stage_timing != 0:
-     * 0 setup+binning, 1 symbolic, 2 numeric binning+scan+allocation,
-     * 3 numeric, 4 total */
+     * two-phase calls: 0 setup+binning, 1 symbolic, 2 numeric
+     *   binning+scan+allocation, 3 numeric, 4 total;
+     * opsp_spgemm_learned: 0 setup+capacities+binning+slot scan,
+     *   1 one-phase numeric, 2 recompute+row-pointer scan+allocation of C,
+     *   3 copy into C, 4 total */
     float ms_stage[8];
+    /* opsp_spgemm_learned only (0 otherwise): */
+    int64_t cap_total;            /* sum of the row capacities (temporary slots) */
+    int64_t arena_entries;        /* entries stored in the overflow arena */
+    int64_t slot_overflow_rows;   /* rows with nnz above their capacity, stored in the arena */
+    int64_t table_overflow_rows;  /* rows whose hash table filled up (recomputed exactly) */
+    int64_t retry_rows;           /* rows recomputed exactly (table full or arena exhausted) */
 } opsp_stats;
 
 typedef struct opsp_plan opsp_plan;       /* opaque */
@@ -186,6 +205,89 @@ opsp_status opsp_batch_execute(opsp_batch *batch, opsp_csr *C, opsp_stats *stats
 void opsp_batch_destroy(opsp_batch *batch);
 opsp_status opsp_spgemm_batched(int32_t count, const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
                                 const opsp_config *config, opsp_batch **owner, void *stream);
+
+/* ---- Row-size predictor and the one-phase product ------------------------
+ * An extension beyond the paper.  Section 2.2 names the one-phase
+ * alternative to the two-phase method: each row is computed straight into
+ * space reserved from a bound on its size, and the rows are then copied into
+ * a compact C (temporary space and a copy are its two costs).  Here the bound
+ * of row i comes from a small network that predicts nnz(C_i*) from three
+ * features of the row, so no symbolic pass runs:
+ *   features  x_i = log2(1 + v) for v = (a_len_i, n_prod_i, b_max_i), float32:
+ *             the entries of A's row i, its intermediate products, and the
+ *             longest row of B that it references;
+ *   network   3 -> 64 -> 64 -> 1, ReLU, bfloat16 parameters packed as
+ *             W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3 (row-major,
+ *             OPSP_MLP_NPARAM bit patterns), predicting y_i = log2(1 + nnz_i):
+ *               z1 = ((b1 + w0 x0) + w1 x1) + w2 x2   float32, no fused ops
+ *               h1 = bf16(relu(z1))                   nearest, ties to even
+ *               y  = W3 relu(W2 h1 + b2) + b3        float32 accumulation
+ *   capacity  cap_i = ceil((2^y_i - 1)(1 + margin)) clamped to
+ *             [min(b_max_i, U_i), U_i] with U_i = min(n_prod_i, N); a row
+ *             with a_len_i <= 1 gets n_prod_i (exact).
+ * Whatever the capacities, the result is the C of opsp_spgemm (same
+ * structure; values summed in unspecified order): a row that outgrows its
+ * capacity is stored in an overflow arena, and a row whose hash table fills
+ * up is recomputed exactly with a table sized from U_i. */
+#define OPSP_MLP_NPARAM 4481
+#define OPSP_PREDICTOR_VERSION 1
+typedef enum {
+    OPSP_PRED_MLP = 0,    /* the network above */
+    OPSP_PRED_UPPER = 1,  /* cap_i = U_i: the upper-bound one-phase method */
+    OPSP_PRED_RATIO = 2   /* cap_i = ceil(n_prod_i / ratio * (1 + margin)), clamped as above */
+} opsp_predictor_kind;
+
+typedef struct {
+    int32_t version;          /* OPSP_PREDICTOR_VERSION */
+    int32_t kind;             /* opsp_predictor_kind */
+    const uint16_t *params;   /* device; OPSP_MLP_NPARAM bfloat16 bit patterns (kind MLP) */
+    double margin;            /* >= 0 */
+    double ratio;             /* kind RATIO: assumed n_prod / nnz, > 0 */
+    double cap_scale;         /* testing: capacities multiplied by this and floored
+                               * after clamping (0 = 1), e.g. 0.1 to overflow rows */
+    float *pred_out;          /* optional device float[A.rows]: network outputs y_i */
+    int64_t *cap_out;         /* optional device int64[A.rows]: capacities */
+} opsp_predictor;
+
+/* Integer features of every row of A*B into device arrays of A->rows
+ * elements (any may be NULL). */
+opsp_status opsp_row_features(const opsp_csr *A, const opsp_csr *B, int32_t *a_len,
+                              int64_t *n_prod, int32_t *b_max, void *stream);
+
+/* Network inputs x_i (float32 [A->rows][3], device) of every row of A*B. */
+opsp_status opsp_mlp_features(const opsp_csr *A, const opsp_csr *B, float *X, void *stream);
+
+/* y[i] = network(X[i]) for n rows (device arrays float[n][3] -> float[n]). */
+opsp_status opsp_mlp_forward(const uint16_t *params, const float *X, int64_t n, float *y,
+                             void *stream);
+
+/* Mean squared error L = sum_i (y_i - target_i)^2 / n over n >= 1 rows and its
+ * gradient with respect to the OPSP_MLP_NPARAM parameters (float32, same
+ * packing), evaluated at the bfloat16 parameters, with the rounding of h1
+ * passed straight through.  grad: device float[OPSP_MLP_NPARAM]; loss:
+ * device float[1] or NULL. */
+opsp_status opsp_mlp_grad(const uint16_t *params, const float *X, const float *target, int64_t n,
+                          float *grad, float *loss, void *stream);
+
+/* One Adam step (Kingma and Ba, 2015) on float32 master parameters with
+ * moments m, v (device float[OPSP_MLP_NPARAM] each, updated in place), step
+ * counted from 1; writes the rounded bfloat16 copy into params. */
+opsp_status opsp_mlp_adam(float *master, float *m, float *v, const float *grad, int64_t step,
+                          float lr, float beta1, float beta2, float eps, uint16_t *params,
+                          void *stream);
+
+/* C = A * B by the one-phase method with predicted capacities (see above):
+ * setup with the three features, capacities (network inference on the
+ * matrix cores), numeric binning by capacity and a scan of the capacities
+ * into slot offsets, one read-back, the numeric hash-accumulate kernels
+ * writing each row into its slot or the arena, the exact recompute of rows
+ * whose tables filled up, the scan of the exact row sizes, one read-back,
+ * allocation of C and the copy into C.  The host blocks two times (three
+ * when rows are recomputed).  Ownership and errors as for opsp_spgemm;
+ * config fields sym_* and fixed_grid are ignored.  stats may be NULL. */
+opsp_status opsp_spgemm_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
+                                const opsp_predictor *predictor, const opsp_config *config,
+                                opsp_stats *stats, void *stream);
 
 /* Device memory of the library (workspaces and C arrays) comes from a
  * per-device cache: blocks released by the library or by opsp_csr_free are

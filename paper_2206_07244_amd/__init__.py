@@ -22,7 +22,9 @@ import numpy as np
 __all__ = [
     "DeviceCSR", "Plan", "OpspError", "Config", "Stats", "spgemm", "spgemm_symbolic",
     "spgemm_numeric", "lib", "library_path", "exported_symbols", "table_sizes", "bin_bounds",
-    "SYM_BINS", "NUM_BINS", "cache_release", "cache_bytes", "Batch",
+    "SYM_BINS", "NUM_BINS", "cache_release", "cache_bytes", "Batch", "Predictor",
+    "row_features", "mlp_features", "mlp_forward", "mlp_grad", "mlp_adam", "spgemm_learned",
+    "MLP_NPARAM", "PRED_MLP", "PRED_UPPER", "PRED_RATIO",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +33,11 @@ _HEADER = os.path.join(os.path.dirname(_HERE), "include", "opsp.h")
 
 SYM_BINS = 9
 NUM_BINS = 8
-CONFIG_VERSION = 1
+CONFIG_VERSION = 2
+MLP_NPARAM = 4481
+PREDICTOR_VERSION = 1
+PRED_MLP, PRED_UPPER, PRED_RATIO = 0, 1, 2
+DEFAULT_WEIGHTS = os.path.join(_HERE, "predictor_weights.json")
 
 
 class opsp_csr(ctypes.Structure):
@@ -44,7 +50,8 @@ class Config(ctypes.Structure):
     _fields_ = [("version", c_int32), ("sym_ratio", c_double), ("num_ratio", c_double),
                 ("force_sym_bin", c_int32), ("force_num_bin", c_int32),
                 ("sym_abort_fraction", c_double), ("b_lanes", c_int32),
-                ("stage_timing", c_int32), ("validate", c_int32), ("fixed_grid", c_int32)]
+                ("stage_timing", c_int32), ("validate", c_int32), ("fixed_grid", c_int32),
+                ("sym_bounds", c_int64 * 7), ("num_bounds", c_int64 * 7)]
 
     def __init__(self, **kw):
         super().__init__()
@@ -52,19 +59,42 @@ class Config(ctypes.Structure):
         self.force_sym_bin = -1
         self.force_num_bin = -1
         for k, v in kw.items():
-            setattr(self, k, v)
+            if k in ("sym_bounds", "num_bounds"):
+                arr = getattr(self, k)
+                for j, x in enumerate(v):
+                    arr[j] = int(x)
+            else:
+                setattr(self, k, v)
+
+    def as_dict(self) -> dict:
+        return {"sym_ratio": self.sym_ratio, "num_ratio": self.num_ratio,
+                "sym_abort_fraction": self.sym_abort_fraction,
+                "sym_bounds": list(self.sym_bounds), "num_bounds": list(self.num_bounds)}
 
 
 class Stats(ctypes.Structure):
     """Mirror of ``opsp_stats``."""
     _fields_ = [("nprod", c_int64), ("nnz", c_int64), ("max_row_nprod", c_int64),
                 ("max_row_nnz", c_int64), ("sym_bin_rows", c_int64 * SYM_BINS),
-                ("num_bin_rows", c_int64 * NUM_BINS), ("ms_stage", ctypes.c_float * 8)]
+                ("num_bin_rows", c_int64 * NUM_BINS), ("ms_stage", ctypes.c_float * 8),
+                ("cap_total", c_int64), ("arena_entries", c_int64),
+                ("slot_overflow_rows", c_int64), ("table_overflow_rows", c_int64),
+                ("retry_rows", c_int64)]
 
     def as_dict(self):
         return {"nprod": self.nprod, "nnz": self.nnz, "max_row_nprod": self.max_row_nprod,
                 "max_row_nnz": self.max_row_nnz, "sym_bin_rows": list(self.sym_bin_rows),
-                "num_bin_rows": list(self.num_bin_rows), "ms_stage": list(self.ms_stage)[:5]}
+                "num_bin_rows": list(self.num_bin_rows), "ms_stage": list(self.ms_stage)[:5],
+                "cap_total": self.cap_total, "arena_entries": self.arena_entries,
+                "slot_overflow_rows": self.slot_overflow_rows,
+                "table_overflow_rows": self.table_overflow_rows, "retry_rows": self.retry_rows}
+
+
+class opsp_predictor(ctypes.Structure):
+    """Mirror of ``opsp_predictor``."""
+    _fields_ = [("version", c_int32), ("kind", c_int32), ("params", c_void_p),
+                ("margin", c_double), ("ratio", c_double), ("cap_scale", c_double),
+                ("pred_out", c_void_p), ("cap_out", c_void_p)]
 
 
 class OpspError(RuntimeError):
@@ -126,6 +156,20 @@ def lib():
         L.opsp_table_sizes.argtypes = [c_int32, POINTER(c_int64), c_int32]
         L.opsp_bin_bounds.restype = ctypes.c_int
         L.opsp_bin_bounds.argtypes = [c_int32, POINTER(c_int64), c_int32, c_double, POINTER(c_int64)]
+        L.opsp_row_features.restype = ctypes.c_int
+        L.opsp_row_features.argtypes = [csr_p, csr_p, P, P, P, P]
+        L.opsp_mlp_features.restype = ctypes.c_int
+        L.opsp_mlp_features.argtypes = [csr_p, csr_p, P, P]
+        L.opsp_mlp_forward.restype = ctypes.c_int
+        L.opsp_mlp_forward.argtypes = [P, P, c_int64, P, P]
+        L.opsp_mlp_grad.restype = ctypes.c_int
+        L.opsp_mlp_grad.argtypes = [P, P, P, c_int64, P, P, P]
+        L.opsp_mlp_adam.restype = ctypes.c_int
+        L.opsp_mlp_adam.argtypes = [P, P, P, P, c_int64, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, P, P]
+        L.opsp_spgemm_learned.restype = ctypes.c_int
+        L.opsp_spgemm_learned.argtypes = [csr_p, csr_p, csr_p, POINTER(opsp_predictor),
+                                          POINTER(Config), POINTER(Stats), P]
         _lib = L
     return _lib
 
@@ -402,3 +446,118 @@ class _BatchView:
         col = _wrap(self._colp + 4 * self.lo, n, torch.int32, self._owner, self._owner.device)
         val = _wrap(self._valp + 8 * self.lo, n, torch.float64, self._owner, self._owner.device)
         return rpt - rpt[0], col.cpu().numpy(), val.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# Row-size predictor and the one-phase product
+# ---------------------------------------------------------------------------
+
+def _ptr(t) -> Optional[int]:
+    return t.data_ptr() if t is not None else None
+
+
+def row_features(A: DeviceCSR, B: DeviceCSR, stream=None):
+    """(a_len int32, n_prod int64, b_max int32) per row of A*B, on the device."""
+    torch = _torch()
+    dev = A.rpt.device
+    al = torch.empty(A.rows, dtype=torch.int32, device=dev)
+    npd = torch.empty(A.rows, dtype=torch.int64, device=dev)
+    bm = torch.empty(A.rows, dtype=torch.int32, device=dev)
+    Ac, Bc = A._c(), B._c()
+    _check(lib().opsp_row_features(byref(Ac), byref(Bc), _ptr(al), _ptr(npd), _ptr(bm),
+                                   _stream_handle(stream)), "opsp_row_features")
+    return al, npd, bm
+
+
+def mlp_features(A: DeviceCSR, B: DeviceCSR, stream=None):
+    """Network inputs log2(1 + (a_len, n_prod, b_max)), float32 [rows, 3]."""
+    torch = _torch()
+    X = torch.empty((A.rows, 3), dtype=torch.float32, device=A.rpt.device)
+    Ac, Bc = A._c(), B._c()
+    _check(lib().opsp_mlp_features(byref(Ac), byref(Bc), _ptr(X), _stream_handle(stream)),
+           "opsp_mlp_features")
+    return X
+
+
+def _params_tensor(params):
+    torch = _torch()
+    assert params.dtype == torch.int16 and params.numel() == MLP_NPARAM and params.is_contiguous()
+    return params
+
+
+def mlp_forward(params, X, stream=None):
+    """y = network(X) for float32 X [n, 3] (params: int16 tensor of bf16 bits)."""
+    torch = _torch()
+    params = _params_tensor(params)
+    X = X.contiguous()
+    n = X.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().opsp_mlp_forward(_ptr(params), _ptr(X), n, _ptr(y), _stream_handle(stream)),
+           "opsp_mlp_forward")
+    return y
+
+
+def mlp_grad(params, X, target, stream=None):
+    """(gradient float32[MLP_NPARAM], loss float32[1]) of the mean squared error."""
+    torch = _torch()
+    params = _params_tensor(params)
+    X, target = X.contiguous(), target.contiguous()
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().opsp_mlp_grad(_ptr(params), _ptr(X), _ptr(target), X.shape[0], _ptr(g), _ptr(loss),
+                               _stream_handle(stream)), "opsp_mlp_grad")
+    return g, loss
+
+
+def mlp_adam(master, m, v, grad, step: int, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+             stream=None):
+    """One Adam step in place on (master, m, v); writes the bf16 copy into params."""
+    _check(lib().opsp_mlp_adam(_ptr(master), _ptr(m), _ptr(v), _ptr(grad), int(step), lr, beta1,
+                               beta2, eps, _ptr(_params_tensor(params)), _stream_handle(stream)),
+           "opsp_mlp_adam")
+
+
+class Predictor:
+    """Capacity source of the one-phase product: the network (bf16 parameters
+    on the device) or one of the reference rules (PRED_UPPER, PRED_RATIO)."""
+
+    def __init__(self, kind: int = PRED_MLP, params=None, margin: float = 0.0, ratio: float = 1.0,
+                 cap_scale: float = 0.0):
+        self.kind, self.params = kind, params
+        self.margin, self.ratio, self.cap_scale = float(margin), float(ratio), float(cap_scale)
+
+    @classmethod
+    def load(cls, path: Optional[str] = None, device="cuda", margin: Optional[float] = None):
+        """The trained network stored by the training driver (JSON with the
+        bf16 bit patterns in the packed order)."""
+        import json
+        torch = _torch()
+        with open(path or DEFAULT_WEIGHTS) as f:
+            d = json.load(f)
+        bits = np.asarray(d["params_bf16"], np.uint16)
+        assert bits.size == MLP_NPARAM
+        t = torch.from_numpy(bits.view(np.int16).copy()).to(device)
+        return cls(PRED_MLP, t, d.get("margin", 0.0) if margin is None else margin)
+
+    def struct(self, pred_out=None, cap_out=None) -> opsp_predictor:
+        p = opsp_predictor()
+        p.version = PREDICTOR_VERSION
+        p.kind = self.kind
+        p.params = _ptr(self.params) if self.params is not None else None
+        p.margin, p.ratio, p.cap_scale = self.margin, self.ratio, self.cap_scale
+        p.pred_out, p.cap_out = _ptr(pred_out), _ptr(cap_out)
+        return p
+
+
+def spgemm_learned(A: DeviceCSR, B: DeviceCSR, predictor: Predictor,
+                   config: Optional[Config] = None, stats: Optional[Stats] = None, stream=None,
+                   pred_out=None, cap_out=None) -> DeviceCSR:
+    """C = A*B by the one-phase method with predicted row capacities."""
+    s = _stream_handle(stream)
+    Ac, Bc, Cc = A._c(), B._c(), opsp_csr()
+    ps = predictor.struct(pred_out, cap_out)
+    code = lib().opsp_spgemm_learned(byref(Ac), byref(Bc), byref(Cc), byref(ps),
+                                     byref(config) if config is not None else None,
+                                     byref(stats) if stats is not None else None, s)
+    _check(code, "opsp_spgemm_learned")
+    return _adopt(Cc, s, A.rpt.device)

@@ -230,9 +230,10 @@ __global__ __launch_bounds__(1024) void k_finalize(int64_t nblk, int nslots, Blo
 // every row is read and written by the same thread.
 // ---------------------------------------------------------------------------
 template <bool SCAN>
-__global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *__restrict__ v, Bounds bd,
+__global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds bd,
                                                  const Counters *__restrict__ ctr,
-                                                 int32_t *__restrict__ bins, BlockParts parts) {
+                                                 int32_t *__restrict__ bins, BlockParts parts,
+                                                 int64_t *vout) {
     __shared__ unsigned int wcnt[4][BIN_SLOTS];
     __shared__ unsigned long long base[BIN_SLOTS];
     __shared__ unsigned long long wsum[4];
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *__restrict_
     if (SCAN && valid) {
         unsigned long long pre = parts.tot[blockIdx.x];
         for (int ww = 0; ww < w; ++ww) pre += wsum[ww];
-        v[i] = (int64_t)(pre + incl - (unsigned long long)x);
+        vout[i] = (int64_t)(pre + incl - (unsigned long long)x);
     }
 }
 
@@ -304,15 +305,17 @@ hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Count
 }
 
 hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
-                          int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s) {
+                          int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
+                          int64_t *vout) {
     if (M == 0) return hipSuccess;
     const int64_t grid = (M + 255) / 256;
+    if (!vout) vout = v;
     if (scan)
         hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, parts);
+                           bins, parts, vout);
     else
         hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, parts);
+                           bins, parts, vout);
     return hipGetLastError();
 }
 

@@ -42,11 +42,12 @@ __device__ __forceinline__ bool num_insert_lds(int *keys, double *vals, uint32_t
 // Accumulate one product per lane (lanes with ok == false take part without
 // one): compare-and-swap the key, then add the product to the slot holding it
 // (Alg. 5).  The probe loop is uniform over the wave and bounded by T
-// iterations with a scalar counter.
+// iterations with a scalar counter.  Returns 1 when this lane's key was new.
 template <class KeyT, class ValT, class AddF>
-__device__ __forceinline__ void num_insert_wave(KeyT *keys, ValT *vals, uint32_t T, bool ok, int key,
-                                                double v, unsigned int *err, AddF &&add) {
+__device__ __forceinline__ int num_insert_wave(KeyT *keys, ValT *vals, uint32_t T, bool ok, int key,
+                                               double v, unsigned int *err, AddF &&add) {
     bool pend = ok;
+    int isnew = 0;
     uint32_t s = ok ? hslot(key, T) : 0u;
     for (uint32_t it = 0; __ballot(pend); ++it) {
         if (it >= T) {
@@ -57,27 +58,63 @@ __device__ __forceinline__ void num_insert_wave(KeyT *keys, ValT *vals, uint32_t
             const int old = atomicCAS(&keys[s], -1, key);
             const bool hit = (old == -1) | (old == key);
             if (hit) add(&vals[s], v);
+            isnew = old == -1;
             pend = !hit;
             s = hit ? s : next_slot(s, T);
         }
     }
+    return isnew;
+}
+
+// ---------------------------------------------------------------------------
+// One-phase step (the upper-bound alternative of Section 2.2, with predicted
+// per-row capacities in place of a bound): where a finished row goes.
+// ---------------------------------------------------------------------------
+
+// Start index for the n entries of `row`: its slot when they fit, else a
+// range of the overflow arena; -1 when the arena is exhausted.
+__device__ __forceinline__ int64_t lrn_place(const Learn &L, int64_t row, int64_t n) {
+    const int64_t o = L.off ? L.off[row] : 0;
+    const int64_t cap = L.off ? L.off[row + 1] - o : 0;
+    if (n <= cap) return o;
+    const unsigned long long a = atomicAdd(&L.lc->arena_used, (unsigned long long)n);
+    if ((int64_t)a + n <= L.arena_cap) {
+        atomicAdd(&L.lc->slot_overflow, 1u);
+        return L.arena_base + (int64_t)a;
+    }
+    return -1;
+}
+
+// Queue `row` for the exact recompute (mode 2), with its output bound.
+__device__ __forceinline__ void lrn_retry(const Learn &L, int64_t row, bool table_full) {
+    const unsigned f = atomicAdd(&L.lc->retry, 1u);
+    L.retry[f] = (int32_t)row;
+    const int64_t np = L.nprod[row];
+    atomicAdd(&L.lc->retry_ub, (unsigned long long)(np < L.ncols ? np : L.ncols));
+    if (table_full) atomicAdd(&L.lc->table_overflow, 1u);
+}
+
+__device__ __forceinline__ void lrn_done(const Learn &L, int64_t row, int64_t n, int64_t base) {
+    L.nnz[row] = n;
+    L.loc[row] = base + L.loc_bias;
 }
 
 // ---------------------------------------------------------------------------
 // bin 0: GL lanes per row; rank counting over the packed keys
 // ---------------------------------------------------------------------------
-template <int GL, int T>
+template <int GL, int T, bool LRN>
 __global__ __launch_bounds__(256) void k_num_group(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    Counters *__restrict__ ctr) {
+    Counters *__restrict__ ctr, Learn L) {
     constexpr int RPW = 256 / GL;
     constexpr int ITEMS = (T + GL - 1) / GL;
     __shared__ double vals[RPW * T];
     __shared__ int keys[RPW * T];
     __shared__ int ck[RPW * T];
+    __shared__ int s_full[RPW];   // one-phase: the row's table filled up
     src.resolve();
     const int slot = threadIdx.x / GL, g = threadIdx.x % GL;
     int *tk = keys + slot * T;
@@ -87,6 +124,7 @@ __global__ __launch_bounds__(256) void k_num_group(
         const int64_t idx = b0 + slot;
         const bool active = idx < src.nrows;
         for (int s = g; s < T; s += GL) { tk[s] = -1; tv[s] = 0.0; }
+        if (LRN && g == 0) s_full[slot] = 0;
         __syncthreads();
         int64_t row = 0;
         if (active) {
@@ -96,8 +134,19 @@ __global__ __launch_bounds__(256) void k_num_group(
                 const int k = acol[p];
                 const double a = aval[p];
                 const int64_t b1 = brpt[k + 1];
-                for (int64_t q = brpt[k]; q < b1; ++q)
-                    if (!num_insert_lds(tk, tv, T, bcol[q], a * bval[q])) atomicAdd(&ctr->error, 1u);
+                bool full = false;
+                for (int64_t q = brpt[k]; q < b1; ++q) {
+                    if (!num_insert_lds(tk, tv, T, bcol[q], a * bval[q])) {
+                        if constexpr (LRN) {
+                            s_full[slot] = 1;
+                            full = true;
+                            break;
+                        } else {
+                            atomicAdd(&ctr->error, 1u);
+                        }
+                    }
+                }
+                if (LRN && (full || *(volatile int *)&s_full[slot])) break;
             }
         }
         __syncthreads();
@@ -122,10 +171,26 @@ __global__ __launch_bounds__(256) void k_num_group(
             if (s < T && tk[s] >= 0) pk[pos++] = tk[s];
         }
         __syncthreads();
+        int64_t base = 0, cap = 0;
         if (active) {
-            const int64_t base = crpt[row];
-            const int64_t cap = crpt[row + 1] - base;
-            if (g == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+            if constexpr (LRN) {
+                int64_t b = -1;
+                if (s_full[slot]) {
+                    if (g == 0) lrn_retry(L, row, true);
+                } else if (g == 0) {
+                    b = lrn_place(L, row, n);
+                    if (b < 0) lrn_retry(L, row, false);
+                    else lrn_done(L, row, n, b);
+                }
+                base = __shfl(b, 0, GL);
+                cap = base < 0 ? 0 : n;
+            } else {
+                base = crpt[row];
+                cap = crpt[row + 1] - base;
+                if (g == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+            }
+        }
+        if (active && cap > 0) {
 #pragma unroll
             for (int m = 0; m < ITEMS; ++m) {
                 const int s = g + m * GL;
@@ -255,22 +320,29 @@ __device__ __forceinline__ int team_excl_scan(int x, int &total, int *red) {
 // network instead; with binning ratios below 1.5 pairs may not fit at all and
 // entries are ranked by counting over the table.
 // ---------------------------------------------------------------------------
-template <int W, int T>
+template <int W, int T, bool LRN>
 __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    Counters *__restrict__ ctr) {
+    Counters *__restrict__ ctr, Learn L) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;
     constexpr int ITEMS = (T + W - 1) / W;
     constexpr int NPACK = (4 * T) / 6;               // pairs that fit the key array
     constexpr int EMAX = (NPACK + W - 1) / W;         // packed pairs per lane
+    // one-phase: abandon the row once its distinct count passes THR.  Until a
+    // wave sees the count above THR it inserts at most one more window of 64
+    // keys, so the table never holds more than THR + W <= T keys.
+    constexpr int THR = (4 * T) / 5 < T - W ? (4 * T) / 5 : T - W;
+    static_assert(THR > 0, "table too small for the one-phase bound");
     __shared__ double vals[R * T];
     __shared__ int keys[R * T];
     __shared__ int red[3 * NW];
+    __shared__ int s_cnt[R];
+    __shared__ long long s_base[R];
 
     src.resolve();
     const int team = threadIdx.x / W, t = threadIdx.x % W;
@@ -284,19 +356,33 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     const bool active = idx < src.nrows;
     team_sync<WT>();   // the previous row of this team is done with the table
     for (int s = t; s < T; s += W) { tk[s] = -1; tv[s] = 0.0; }
+    if (LRN && t == 0) s_cnt[team] = 0;
     team_sync<WT>();
 
     int64_t row = 0;
     if (active) {
         row = src.row(idx);
         auto ins = [&](bool ok, int key, double v) {
-            num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
-                            [](double *p, double x) { atomicAdd(p, x); });
+            const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
+                                           [](double *p, double x) { atomicAdd(p, x); });
+            if constexpr (LRN) {
+                const int nm = (int)__popcll(__ballot(nw));
+                if (nm && lane_id() == 0) atomicAdd(&s_cnt[team], nm);
+            }
         };
-        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, NW, ins,
-                           [] { return false; });
+        auto stop = [&]() -> bool {
+            if constexpr (LRN) return *(volatile int *)&s_cnt[team] > THR;
+            else return false;
+        };
+        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
     }
     team_sync<WT>();
+    if constexpr (LRN) {
+        if (s_cnt[team] > THR) {   // uniform over the team
+            if (active && t == 0) lrn_retry(L, row, true);
+            return;
+        }
+    }
 
     // count, range and keys of this lane's slots (s = t + m*W)
     int rk[ITEMS];
@@ -313,9 +399,23 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     }
     int n = c;
     team_min_max_sum<WT, NW>(kmin, kmax, n, red);
-    const int64_t base = active ? crpt[row] : 0;
-    const int64_t cap = active ? crpt[row + 1] - base : 0;
-    if (active && t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+    int64_t base, cap;
+    if constexpr (LRN) {
+        if (active && t == 0) {
+            const int64_t b = lrn_place(L, row, n);
+            if (b < 0) lrn_retry(L, row, false);
+            else lrn_done(L, row, n, b);
+            s_base[team] = b;
+        }
+        team_sync<WT>();
+        base = active ? (int64_t)s_base[team] : -1;
+        if (base < 0) return;   // uniform over the team
+        cap = n;
+    } else {
+        base = active ? crpt[row] : 0;
+        cap = active ? crpt[row + 1] - base : 0;
+        if (active && t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+    }
     if (n == 0) return;   // uniform over the team
 
     if (n > NPACK) {
@@ -453,12 +553,13 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
 // bin 7: global-memory tables (one slab per persistent workgroup), ordered
 // through LDS bitmaps of 2^19 columns at a time.
 // ---------------------------------------------------------------------------
+template <bool LRN>
 __global__ __launch_bounds__(1024) void k_num_global(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    int *slab_keys, double *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr) {
+    int *slab_keys, double *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr, Learn L) {
     constexpr int CW = NUM_GLOBAL_CHUNK_WORDS;
     constexpr int CBITS = CW * 32;
     constexpr int WPT = CW / 1024;  // bitmap words per thread
@@ -466,6 +567,8 @@ __global__ __launch_bounds__(1024) void k_num_global(
     __shared__ unsigned int prefix[CW];
     __shared__ unsigned int red[16];
     __shared__ int s_min, s_max;
+    __shared__ unsigned int s_cnt;
+    __shared__ long long s_base;
 
     src.resolve();
     int *tk = slab_keys + (int64_t)blockIdx.x * slab_entries;
@@ -474,12 +577,32 @@ __global__ __launch_bounds__(1024) void k_num_global(
 
     for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
         const int64_t row = src.row(r);
-        const int64_t base = crpt[row];
-        const int64_t n = crpt[row + 1] - base;
-        uint32_t T = pow2_at_least((uint64_t)(2 * n > 64 ? 2 * n : 64));
-        if ((int64_t)T > slab_entries) T = (uint32_t)slab_entries;
+        int64_t base = 0, n = 0;
+        uint32_t T, thr = 0xffffffffu;
+        if constexpr (LRN) {
+            // mode 1: table from the predicted capacity, abandoned past thr
+            // (at most one more window of 64 keys per wave after a wave sees
+            // the count above thr: thr + 1024 <= T for T >= 8192);
+            // mode 2: table from the row's bound min(n_prod, N), never full
+            int64_t sz;
+            if (L.mode == 1) {
+                sz = L.off[row + 1] - L.off[row];
+                T = pow2_at_least((uint64_t)(2 * sz > 8192 ? 2 * sz : 8192));
+            } else {
+                const int64_t np = L.nprod[row];
+                sz = np < L.ncols ? np : L.ncols;
+                T = pow2_at_least((uint64_t)(2 * sz > 64 ? 2 * sz : 64));
+            }
+            if ((int64_t)T > slab_entries) T = (uint32_t)slab_entries;
+            if (L.mode == 1) thr = (T / 5) * 4 < T - 1024 ? (T / 5) * 4 : T - 1024;
+        } else {
+            base = crpt[row];
+            n = crpt[row + 1] - base;
+            T = pow2_at_least((uint64_t)(2 * n > 64 ? 2 * n : 64));
+            if ((int64_t)T > slab_entries) T = (uint32_t)slab_entries;
+        }
         for (uint32_t s = t; s < T; s += 1024) { tk[s] = -1; tv[s] = 0.0; }
-        if (t == 0) { s_min = INT_MAX; s_max = -1; }
+        if (t == 0) { s_min = INT_MAX; s_max = -1; s_cnt = 0u; }
         __syncthreads();
 
         int kmin = INT_MAX, kmax = -1;
@@ -488,11 +611,18 @@ __global__ __launch_bounds__(1024) void k_num_global(
                 kmin = key < kmin ? key : kmin;
                 kmax = key > kmax ? key : kmax;
             }
-            num_insert_wave(tk, tv, T, ok, key, v, &ctr->error,
-                            [](double *p, double x) { unsafeAtomicAdd(p, x); });
+            const int nw = num_insert_wave(tk, tv, T, ok, key, v, &ctr->error,
+                                           [](double *p, double x) { unsafeAtomicAdd(p, x); });
+            if constexpr (LRN) {
+                const unsigned nm = (unsigned)__popcll(__ballot(nw));
+                if (nm && l == 0) atomicAdd(&s_cnt, nm);
+            }
         };
-        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, 16, ins,
-                           [] { return false; });
+        auto stop = [&]() -> bool {
+            if constexpr (LRN) return *(volatile unsigned int *)&s_cnt > thr;
+            else return false;
+        };
+        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, 16, ins, stop);
         kmin = wave_min(kmin);
         kmax = wave_max(kmax);
         if (l == 0) {
@@ -500,6 +630,23 @@ __global__ __launch_bounds__(1024) void k_num_global(
             atomicMax(&s_max, kmax);
         }
         __syncthreads();
+        if constexpr (LRN) {
+            n = (int64_t)s_cnt;
+            if (t == 0) {
+                int64_t b = -1;
+                if (n > (int64_t)thr) {
+                    lrn_retry(L, row, true);
+                } else {
+                    b = lrn_place(L, row, n);
+                    if (b < 0) lrn_retry(L, row, false);
+                    else lrn_done(L, row, n, b);
+                }
+                s_base = b;
+            }
+            __syncthreads();
+            base = (int64_t)s_base;
+            if (base < 0) continue;   // uniform; no barrier is pending
+        }
         const int lo = s_min, hi = s_max;
         int64_t run = 0;
         for (int64_t c0 = lo; c0 <= hi; c0 += CBITS) {
@@ -554,6 +701,96 @@ __global__ __launch_bounds__(1024) void k_num_global(
 }
 
 // ---------------------------------------------------------------------------
+// One-phase step, last stage: copy every row from where the numeric step
+// left it (its slot, the arena, or the second arena of recomputed rows) to
+// its place in C.  Work is split by output entries, CH per wave: a wave finds
+// the row holding its first entry with a 64-way search of C.rpt, then walks
+// 64 rows at a time with their bounds and sources staged in LDS; every lane
+// copies one entry per step, so reads and writes are coalesced within rows
+// and writes are contiguous across them.
+// ---------------------------------------------------------------------------
+constexpr int COMPACT_CH = 4096;
+
+__global__ __launch_bounds__(256) void k_compact(int64_t M, int64_t nnzC,
+                                                 const int64_t *__restrict__ crpt,
+                                                 const int64_t *__restrict__ loc,
+                                                 const int32_t *__restrict__ tcol,
+                                                 const double *__restrict__ tval, int64_t tsize,
+                                                 const int32_t *__restrict__ acol2,
+                                                 const double *__restrict__ aval2,
+                                                 int32_t *__restrict__ ccol,
+                                                 double *__restrict__ cval) {
+    __shared__ int64_t s_rs[4][65];
+    __shared__ int64_t s_src[4][64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t chunk = (int64_t)blockIdx.x * 4 + w;
+    const int64_t e0 = chunk * COMPACT_CH;
+    if (e0 >= nnzC) return;   // uniform per wave; no workgroup barrier follows
+    const int64_t e1 = e0 + COMPACT_CH < nnzC ? e0 + COMPACT_CH : nnzC;
+    // last row r with crpt[r] <= e0 (the row holding entry e0): 64-way search
+    int64_t lo = 0, hi = M;   // crpt[lo] <= e0, and hi == M or crpt[hi] > e0
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t p = lo + (int64_t)l * step;
+        const bool le = p < hi && crpt[p] <= e0;
+        const int c = (int)__popcll(__ballot(le));   // >= 1: p = lo holds
+        const int64_t nlo = lo + (int64_t)(c - 1) * step;
+        const int64_t nhi = nlo + step < hi ? nlo + step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    int64_t r = lo;
+    int64_t pos = e0;
+    while (pos < e1) {
+        // stage rows r .. r+63: starts (65 bounds) and source indices
+        const int64_t rr = r + l;
+        s_rs[w][l] = crpt[rr < M ? rr : M];
+        if (l == 0) s_rs[w][64] = crpt[r + 64 < M ? r + 64 : M];
+        s_src[w][l] = rr < M ? loc[rr] : 0;
+        wave_lds_sync();
+        const int64_t wend_rows = s_rs[w][64];
+        const int64_t stop = wend_rows < e1 ? wend_rows : e1;
+        for (int64_t b = pos; b < stop; b += 64) {
+            const int64_t e = b + l;
+            if (e < stop) {
+                // last staged row j with start <= e
+                int j = 0;
+#pragma unroll
+                for (int h = 32; h > 0; h >>= 1)
+                    if (s_rs[w][j + h] <= e) j += h;
+                const int64_t src = s_src[w][j] + (e - s_rs[w][j]);
+                int32_t cv;
+                double vv;
+                if (src < tsize) {
+                    cv = tcol[src];
+                    vv = tval[src];
+                } else {
+                    cv = acol2[src - tsize];
+                    vv = aval2[src - tsize];
+                }
+                ccol[e] = cv;
+                cval[e] = vv;
+            }
+        }
+        pos = stop;
+        r += 64;
+        wave_lds_sync();   // every lane is done with the staged rows
+    }
+}
+
+hipError_t launch_compact(int64_t M, int64_t nnzC, const int64_t *crpt, const int64_t *loc,
+                          const int32_t *tcol, const double *tval, int64_t tsize,
+                          const int32_t *acol2, const double *aval2, int32_t *ccol, double *cval,
+                          hipStream_t s) {
+    if (nnzC <= 0 || M <= 0) return hipSuccess;
+    const int64_t chunks = (nnzC + COMPACT_CH - 1) / COMPACT_CH;
+    const int64_t grid = (chunks + 3) / 4;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)grid), dim3(256), 0, s, M, nnzC, crpt, loc, tcol,
+                       tval, tsize, acol2, aval2, ccol, cval);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 static int64_t grid_for(const NumArgs &a, int64_t per_wg) {
     if (a.grid > 0) return a.grid;
     return (a.src.nrows + per_wg - 1) / per_wg;
@@ -564,8 +801,14 @@ static hipError_t go_row(const NumArgs &a, hipStream_t s) {
     constexpr int R = (W == 64) ? 4 : 1;
     const int64_t grid = (a.src.nrows + R - 1) / R;   // one team per row
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_num_row<W, T>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src, a.A.rpt,
-                       a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.ctr);
+    if (a.lrn.mode == 1)
+        hipLaunchKernelGGL((k_num_row<W, T, true>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
+                           a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
+                           a.cval, a.ctr, a.lrn);
+    else
+        hipLaunchKernelGGL((k_num_row<W, T, false>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
+                           a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
+                           a.cval, a.ctr, a.lrn);
     return hipGetLastError();
 }
 
@@ -576,9 +819,14 @@ hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
             constexpr int RPW = 256 / NUM_GL;
             const int64_t grid = grid_for(a, RPW);
             if (grid <= 0) return hipSuccess;
-            hipLaunchKernelGGL((k_num_group<NUM_GL, NUM_T[0]>), dim3((unsigned)grid), dim3(256), 0, s,
-                               a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt,
-                               a.ccol, a.cval, a.ctr);
+            if (a.lrn.mode == 1)
+                hipLaunchKernelGGL((k_num_group<NUM_GL, NUM_T[0], true>), dim3((unsigned)grid), dim3(256),
+                                   0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val,
+                                   a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
+            else
+                hipLaunchKernelGGL((k_num_group<NUM_GL, NUM_T[0], false>), dim3((unsigned)grid), dim3(256),
+                                   0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val,
+                                   a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
             return hipGetLastError();
         }
         case 1: return go_row<NUM_W[1], NUM_T[1]>(a, s);
@@ -589,9 +837,14 @@ hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
         case 6: return go_row<NUM_W[6], NUM_T[6]>(a, s);
         case NUM_GLOBAL_BIN: {
             if (a.grid <= 0) return hipSuccess;
-            hipLaunchKernelGGL(k_num_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
-                               a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval,
-                               a.slab_keys, a.slab_vals, a.slab_entries, a.ctr);
+            if (a.lrn.mode > 0)
+                hipLaunchKernelGGL(k_num_global<true>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
+                                   a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
+                                   a.cval, a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
+            else
+                hipLaunchKernelGGL(k_num_global<false>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
+                                   a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
+                                   a.cval, a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

@@ -24,12 +24,14 @@
 // Every result C_p is a view: its row pointer points into the stacked row
 // pointer (absolute offsets) and its col/val pointers are the stacked
 // arrays, all owned by the batch object.
+#include <stddef.h>
 #include <string.h>
 
 #include <vector>
 
 #include "opsp.h"
 #include "opsp_internal.h"
+#include "opsp_host_util.h"
 
 using namespace opsp;
 
@@ -162,29 +164,6 @@ hipError_t balloc(opsp_batch *b, void **p, size_t bytes, hipStream_t s) {
 void bfree_all(opsp_batch *b, hipStream_t s) {
     for (auto &pp : b->owned) (void)cache_free(pp.first, s);
     b->owned.clear();
-}
-
-Bounds mk_bounds(int step, double ratio) {
-    Bounds x;
-    memset(&x, 0, sizeof(x));
-    int64_t ts[16];
-    int nb = 0;
-    if (step == 0) {
-        nb = SYM_NLDS;
-        for (int j = 0; j < SYM_NLDS; ++j) ts[j] = SYM_T[j];
-        x.nb = SYM_NLDS;
-        x.nslots = SYM_NLDS + 1;
-    } else {
-        nb = NUM_NLDS + 1;
-        for (int j = 0; j < NUM_NLDS; ++j) ts[j] = NUM_T[j];
-        x.nb = NUM_NLDS + 1;
-        x.nslots = NUM_NLDS + 1;
-    }
-    int64_t out[16];
-    (void)opsp_bin_bounds(step, ts, nb, ratio, out);
-    for (int j = 0; j < nb - 1; ++j) x.ub[j] = out[j];
-    x.force = -1;
-    return x;
 }
 
 // Workgroups per CU of each symbolic kernel at full residency.
@@ -350,7 +329,10 @@ opsp_status opsp_batch_create(int32_t count, const opsp_csr *A, const opsp_csr *
     if (!out) return OPSP_ERR_INVALID;
     *out = nullptr;
     if (count < 1 || count > 65535 || !A || !B) return OPSP_ERR_INVALID;
-    if (cfg && cfg->version != OPSP_CONFIG_VERSION) return OPSP_ERR_INVALID;
+    {
+        const opsp_status cs = opsp::host::check_config(cfg);
+        if (cs != OPSP_OK) return cs;
+    }
     hipStream_t user = (hipStream_t)stream;
     opsp_batch *b = new (std::nothrow) opsp_batch();
     if (!b) return OPSP_ERR_ALLOC;
@@ -412,10 +394,14 @@ opsp_status opsp_batch_create(int32_t count, const opsp_csr *A, const opsp_csr *
     b->K = brow;
     b->nnzA = annz;
     b->nnzB = bnnz;
-    const double sr = (cfg && cfg->sym_ratio > 0) ? cfg->sym_ratio : 1.2;
-    const double nr = (cfg && cfg->num_ratio > 0) ? cfg->num_ratio : 2.0;
-    b->bs = mk_bounds(0, sr);
-    b->bn = mk_bounds(1, nr);
+    // the batch's kernels route every row by its natural bin
+    opsp_config c2;
+    memset(&c2, 0, sizeof(c2));
+    if (cfg) memcpy(&c2, cfg, cfg->version >= 2 ? sizeof(opsp_config)
+                                                : offsetof(opsp_config, sym_bounds));
+    c2.force_sym_bin = c2.force_num_bin = -1;
+    b->bs = opsp::host::config_bounds(0, &c2);
+    b->bn = opsp::host::config_bounds(1, &c2);
 
     // device memory
     void *p = nullptr;

@@ -53,6 +53,41 @@ struct Counters {
     unsigned long long pad[6];
 };
 
+// Counters of the one-phase (predicted-capacity) numeric step, zeroed
+// before use.
+struct LearnCtr {
+    unsigned long long arena_used;   // entries taken from the overflow arena
+    unsigned long long retry_ub;     // sum of min(n_prod, N) over rows to recompute
+    unsigned long long nprod_total;  // sum of n_prod (capacity kernel)
+    unsigned long long nprod_max;
+    unsigned int retry;              // rows pushed to the recompute list
+    unsigned int table_overflow;     // rows abandoned because their table filled up
+    unsigned int slot_overflow;      // rows stored in the arena (slot too small)
+    unsigned int error;
+};
+
+// Arguments of the one-phase numeric step (mode 0 = the exact two-phase
+// step, which ignores them).  Mode 1: every row has a slot of its predicted
+// capacity at off[row] in temporary arrays; a row that outgrows its slot is
+// stored in the overflow arena, a row whose table fills up is abandoned to
+// the recompute list.  Mode 2 (global-table kernel only): rows of the
+// recompute list, tables sized from min(n_prod, N), stored in a second arena
+// that holds their upper bounds.
+struct Learn {
+    int mode;
+    int pad;
+    const int64_t *off;       // slot offsets, off[M] = total (mode 1)
+    const int64_t *nprod;     // n_prod per row
+    int64_t *nnz;             // out: exact nnz per row
+    int64_t *loc;             // out: index of the row's first entry
+    int64_t loc_bias;         // added to the recorded index (second arena)
+    int64_t ncols;            // N
+    int64_t arena_base;       // first arena index in the written arrays
+    int64_t arena_cap;        // arena capacity in entries
+    LearnCtr *lc;
+    int32_t *retry;           // recompute list (capacity M)
+};
+
 // Where a kernel finds the rows of its bin.  Host mode: `nrows` rows listed
 // from position `off` of `bins` (rows off, off+1, ... when bins == NULL).
 // Device mode (used by captured graphs, whose grids cannot depend on the

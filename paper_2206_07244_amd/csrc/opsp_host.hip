@@ -25,6 +25,7 @@
 
 #include "opsp.h"
 #include "opsp_internal.h"
+#include "opsp_host_util.h"
 
 using namespace opsp;
 
@@ -46,15 +47,33 @@ struct opsp_plan {
 };
 
 namespace {
-
 const char *kVersion = "opsp 0.1.0 (gfx950)";
+}  // namespace
 
+namespace opsp {
+namespace host {
+
+namespace {
 struct DeviceInfo {
     bool ready = false;
     int cus = 256;
 };
 std::mutex g_mu;
 DeviceInfo g_dev[64];
+
+// Per-thread pinned host buffer for the small counter read-backs.
+struct PinnedBuf {
+    void *h = nullptr;
+    void *get() {
+        if (!h && hipHostMalloc(&h, PINNED_BYTES, hipHostMallocDefault) != hipSuccess) h = nullptr;
+        return h;
+    }
+    ~PinnedBuf() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+thread_local PinnedBuf t_pinned;
+}  // namespace
 
 opsp_status status_of(hipError_t e) {
     if (e == hipSuccess) return OPSP_OK;
@@ -87,41 +106,19 @@ opsp_status init_device(int *dev_out, int *cus_out) {
     return OPSP_OK;
 }
 
-// Stream-ordered allocations released on every exit path unless kept.
-struct Arena {
-    hipStream_t s;
-    void *p[16];
-    int n = 0;
-    explicit Arena(hipStream_t st) : s(st) {}
-    hipError_t alloc(void **out, size_t bytes) {
-        *out = nullptr;
-        if (bytes == 0) return hipSuccess;
-        hipError_t e = cache_alloc(out, bytes, s);
-        if (e == hipSuccess) p[n++] = *out;
-        return e;
-    }
-    void keep(void *q) {
-        for (int i = 0; i < n; ++i)
-            if (p[i] == q) p[i] = nullptr;
-    }
-    ~Arena() {
-        for (int i = 0; i < n; ++i)
-            if (p[i]) (void)cache_free(p[i], s);
-    }
-};
-
-#define CHK(x)                                  \
-    do {                                        \
-        hipError_t e_ = (x);                    \
-        if (e_ != hipSuccess) return status_of(e_); \
-    } while (0)
-
 bool csr_ok(const opsp_csr *X) {
     if (!X) return false;
     if (X->rows < 0 || X->cols < 0 || X->nnz < 0) return false;
     if (!X->rpt) return false;
     if (X->nnz > 0 && (!X->col || !X->val)) return false;
     return true;
+}
+
+opsp_status check_inputs(const opsp_csr *A, const opsp_csr *B) {
+    if (!csr_ok(A) || !csr_ok(B)) return OPSP_ERR_INVALID;
+    if (A->cols != B->rows) return OPSP_ERR_SHAPE;
+    if (B->cols > INT32_MAX || A->cols > INT32_MAX) return OPSP_ERR_SHAPE;
+    return OPSP_OK;
 }
 
 DevCSR dev_of(const opsp_csr *X) {
@@ -157,55 +154,50 @@ Bounds make_bounds(int step, double ratio, int force) {
     return b;
 }
 
-// Per-thread pinned host buffer for the small counter read-backs.
-struct PinnedCounters {
-    Counters *h = nullptr;
-    Counters *get() {
-        if (!h && hipHostMalloc((void **)&h, sizeof(Counters) * 2, hipHostMallocDefault) != hipSuccess)
-            h = nullptr;
-        return h;
+Bounds config_bounds(int step, const opsp_config *c) {
+    const int force = c ? (step == 0 ? c->force_sym_bin : c->force_num_bin) : -1;
+    Bounds b = make_bounds(step, step == 0 ? sym_ratio(c) : num_ratio(c), force);
+    if (c && c->version >= 2) {
+        const int64_t *eb = step == 0 ? c->sym_bounds : c->num_bounds;
+        for (int j = 0; j < 7; ++j)
+            if (eb[j] != 0) b.ub[j] = eb[j];
     }
-    ~PinnedCounters() {
-        if (h) (void)hipHostFree(h);
-    }
-};
-thread_local PinnedCounters t_pinned;
+    return b;
+}
 
-hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipStream_t s) {
-    Counters *pin = t_pinned.get();
+opsp_status check_config(const opsp_config *c) {
+    if (!c) return OPSP_OK;
+    if (c->version != 1 && c->version != 2) return OPSP_ERR_INVALID;
+    if (c->sym_ratio != 0 && !(c->sym_ratio >= 1.0)) return OPSP_ERR_INVALID;
+    if (c->num_ratio != 0 && !(c->num_ratio >= 1.0)) return OPSP_ERR_INVALID;
+    if (c->force_sym_bin < -1 || c->force_sym_bin > SYM_GLOBAL_BIN) return OPSP_ERR_INVALID;
+    if (c->force_num_bin < -1 || c->force_num_bin > NUM_GLOBAL_BIN) return OPSP_ERR_INVALID;
+    if (c->b_lanes != 0) return OPSP_ERR_INVALID;
+    if (c->version >= 2) {
+        for (int j = 0; j < 7; ++j) {
+            if (c->sym_bounds[j] < -1 || c->sym_bounds[j] > SYM_T[j]) return OPSP_ERR_INVALID;
+            if (c->num_bounds[j] < -1 || c->num_bounds[j] > NUM_T[j]) return OPSP_ERR_INVALID;
+        }
+    }
+    return OPSP_OK;
+}
+
+hipError_t read_back(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    void *pin = bytes <= PINNED_BYTES ? t_pinned.get() : nullptr;
     if (!pin) {
-        hipError_t e = hipMemcpyAsync(dst, src, sizeof(Counters) * count, hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e;
     }
-    hipError_t e = hipMemcpyAsync(pin, src, sizeof(Counters) * count, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) memcpy(dst, pin, sizeof(Counters) * count);
+    if (e == hipSuccess) memcpy(dst, pin, bytes);
     return e;
 }
 
-struct Timer {
-    bool on;
-    hipStream_t s;
-    hipEvent_t ev[8];
-    int n = 0;
-    Timer(bool enable, hipStream_t st) : on(enable), s(st) {}
-    void mark() {
-        if (!on || n >= 8) return;
-        if (hipEventCreate(&ev[n]) == hipSuccess) {
-            (void)hipEventRecord(ev[n], s);
-            ++n;
-        }
-    }
-    float between(int a, int b) {
-        float ms = 0.f;
-        if (on && a < n && b < n) (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
-        return ms;
-    }
-    ~Timer() {
-        for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
-    }
-};
+hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipStream_t s) {
+    return read_back(dst, src, sizeof(Counters) * count, s);
+}
 
 RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows) {
     RowSrc r;
@@ -215,6 +207,13 @@ RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows) {
     r.nrows = nrows;
     return r;
 }
+
+}  // namespace host
+}  // namespace opsp
+
+using namespace opsp::host;
+
+namespace {
 
 // Steps 1-5: everything up to C's row pointer and the numeric bins.
 opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config *cfg,
@@ -255,11 +254,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     parts.mx = parts.tot + nblk;
     parts.hist = (unsigned int *)(parts.mx + nblk);
 
-    const int fs = cfg ? cfg->force_sym_bin : -1;
-    const int fn = cfg ? cfg->force_num_bin : -1;
-    if (fs < -1 || fs > SYM_GLOBAL_BIN || fn < -1 || fn > NUM_GLOBAL_BIN) return OPSP_ERR_INVALID;
-    const Bounds bs = make_bounds(0, sym_ratio(cfg), fs);
-    const Bounds bn = make_bounds(1, num_ratio(cfg), fn);
+    const Bounds bs = config_bounds(0, cfg);
+    const Bounds bn = config_bounds(1, cfg);
     const DevCSR dA = dev_of(A), dB = dev_of(B);
 
     // 1 setup + first symbolic binning pass
@@ -438,13 +434,6 @@ void plan_release(opsp_plan *plan, hipStream_t s) {
     plan->ctr = nullptr;
 }
 
-opsp_status check_inputs(const opsp_csr *A, const opsp_csr *B) {
-    if (!csr_ok(A) || !csr_ok(B)) return OPSP_ERR_INVALID;
-    if (A->cols != B->rows) return OPSP_ERR_SHAPE;
-    if (B->cols > INT32_MAX || A->cols > INT32_MAX) return OPSP_ERR_SHAPE;
-    return OPSP_OK;
-}
-
 }  // namespace
 
 // ===========================================================================
@@ -472,7 +461,8 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
     memset(C, 0, sizeof(*C));
     opsp_status st = check_inputs(A, B);
     if (st != OPSP_OK) return st;
-    if (config && config->version != OPSP_CONFIG_VERSION) return OPSP_ERR_INVALID;
+    st = check_config(config);
+    if (st != OPSP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     opsp_plan plan;
     Timer tm(config && config->stage_timing, s);
@@ -530,7 +520,8 @@ opsp_status opsp_spgemm_symbolic(const opsp_csr *A, const opsp_csr *B, const ops
     *nnzC = 0;
     opsp_status st = check_inputs(A, B);
     if (st != OPSP_OK) return st;
-    if (config && config->version != OPSP_CONFIG_VERSION) return OPSP_ERR_INVALID;
+    st = check_config(config);
+    if (st != OPSP_OK) return st;
     opsp_plan *plan = new (std::nothrow) opsp_plan();
     if (!plan) return OPSP_ERR_ALLOC;
     hipStream_t s = (hipStream_t)stream;

@@ -51,9 +51,11 @@ hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, const Bloc
 hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Counters *ctr,
                            int64_t *total_out, bool scan, hipStream_t s);
 // Second binning pass: scatter row ids into `bins` (may be NULL when no
-// bins are needed); with `scan`, also turn v[] into exclusive offsets.
+// bins are needed); with `scan`, also write the exclusive offsets of v[] to
+// vout[] (NULL = in place).
 hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
-                          int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s);
+                          int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
+                          int64_t *vout = nullptr);
 
 // ---- symbolic step (kernels_sym.hip) ---------------------------------------
 struct SymArgs {
@@ -81,7 +83,42 @@ struct NumArgs {
     double *slab_vals;
     int64_t slab_entries;
     int64_t grid;
+    Learn lrn;               // one-phase step (lrn.mode > 0); crpt unused then
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
+
+// Copy the rows of the one-phase step from the temporary arrays (entries
+// [0, tsize)) and the second arena (indices tsize.. in `loc`) into C.
+hipError_t launch_compact(int64_t M, int64_t nnzC, const int64_t *crpt, const int64_t *loc,
+                          const int32_t *tcol, const double *tval, int64_t tsize,
+                          const int32_t *acol2, const double *aval2, int32_t *ccol, double *cval,
+                          hipStream_t s);
+
+// ---- predictor (kernels_mlp.hip) -------------------------------------------
+constexpr int MLP_NPARAM = 4481;
+// log2(1 + v) features of every row from the integer features.
+hipError_t launch_mlp_features(int64_t M, const int32_t *alen, const int64_t *nprod,
+                               const int32_t *bmax, float *X, hipStream_t s);
+hipError_t launch_mlp_forward(const uint16_t *P, const float *X, int64_t n, float *y, hipStream_t s);
+// Gradient of the mean squared error over n rows; `part` holds
+// ceil(n / 64) * (MLP_NPARAM + 1) floats.
+hipError_t launch_mlp_grad(const uint16_t *P, const float *X, const float *T, int64_t n,
+                           float *part, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *g, float lr, float b1,
+                           float b2, float eps, float c1, float c2, uint16_t *P, hipStream_t s);
+// Capacities of every row (predictor kind 0 = network, 1 = min(n_prod, N),
+// 2 = n_prod / ratio) into cap[0..M), with per-block numeric-bin records and
+// the n_prod total and maximum in lc.
+struct CapArgs {
+    int kind;
+    int pad;
+    const uint16_t *P;
+    double margin, ratio, scale;
+    int64_t ncols;
+    float *pred;             // optional: the network's outputs
+};
+hipError_t launch_mlp_caps(int64_t M, const CapArgs &ca, const int32_t *alen, const int64_t *nprod,
+                           const int32_t *bmax, int64_t *cap, const Bounds &bd,
+                           const BlockParts &parts, LearnCtr *lc, hipStream_t s);
 
 }  // namespace opsp

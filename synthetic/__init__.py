@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "CSR", "lap5", "stencil27", "stencil", "rmat", "poisson_uniform",
-    "banded", "random_csr", "identity", "batch_pairs", "training_set",
+    "banded", "random_csr", "identity", "batch_pairs", "training_set", "training_matrix",
     "WORKLOADS",
 ]
 
@@ -285,51 +285,51 @@ def batch_pairs(count: int = 512, seed: int = 4, n_lo: int = 1000,
     return out
 
 
+def training_matrix(j: int, seed0: int = 1000, n_lo_log2: int = 14,
+                    n_hi_log2: int = 18) -> Tuple[str, CSR]:
+    """Matrix j of the predictor's training set: family j mod 4 (R-MAT with
+    a in [.45,.6] and degree 4..32; banded with half-bandwidth 8..128 and 4..24
+    per row; Poisson-uniform rows with mean 2..16; stencils 2-D 5/9-point or
+    3-D 7/27-point), n = 2^k with k uniform in [n_lo_log2, n_hi_log2], all
+    drawn from seed seed0 + j."""
+    s = seed0 + j
+    r = np.random.default_rng([s, 7])
+    fam = j % 4
+    logn = int(r.integers(n_lo_log2, n_hi_log2 + 1))
+    n = 1 << logn
+    if fam == 0:
+        a = float(r.uniform(0.45, 0.6))
+        bb = (1.0 - a) * float(r.uniform(0.3, 0.4))
+        deg = int(r.integers(4, 33))
+        return f"rmat{logn}_a{a:.2f}_d{deg}", rmat(logn, deg, a, bb, bb, seed=s)
+    if fam == 1:
+        hb = int(r.integers(8, 129))
+        pr = int(r.integers(4, 25))
+        return f"band{logn}_h{hb}_k{pr}", banded(n, hb, min(pr, 2 * hb + 1), seed=s)
+    if fam == 2:
+        mean = float(r.uniform(2, 16))
+        return f"poisson{logn}_m{mean:.1f}", poisson_uniform(n, n, mean, seed=s, values="uniform")
+    kind = int(r.integers(0, 4))
+    if kind == 0:
+        g = int(round(n ** 0.5))
+        return f"st5_{g}", stencil([g, g], [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)], seed=s)
+    if kind == 1:
+        g = int(round(n ** 0.5))
+        offs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        return f"st9_{g}", stencil([g, g], offs, seed=s)
+    if kind == 2:
+        g = int(round(n ** (1 / 3)))
+        offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+        return f"st7_{g}", stencil([g, g, g], offs, seed=s)
+    g = int(round(n ** (1 / 3)))
+    return f"st27_{g}", stencil27(g, seed=s)
+
+
 def training_set(count: int = 200, seed0: int = 1000, n_lo_log2: int = 14,
                  n_hi_log2: int = 18) -> List[Tuple[str, CSR]]:
-    """Matrices whose squares label the row-size predictor: a quarter each of
-    R-MAT (a in [.45,.6], degree 4..32), banded (half-bandwidth 8..128, 4..24
-    per row), Poisson-uniform (mean 2..16) and stencils (2-D 5/9-point, 3-D
-    7/27-point).  Matrix j uses seed seed0 + j."""
-    out = []
-    for j in range(count):
-        s = seed0 + j
-        r = np.random.default_rng([s, 7])
-        fam = j % 4
-        logn = int(r.integers(n_lo_log2, n_hi_log2 + 1))
-        n = 1 << logn
-        if fam == 0:
-            a = float(r.uniform(0.45, 0.6))
-            bb = (1.0 - a) * float(r.uniform(0.3, 0.4))
-            cc = bb
-            deg = int(r.integers(4, 33))
-            out.append((f"rmat{logn}_a{a:.2f}_d{deg}", rmat(logn, deg, a, bb, cc, seed=s)))
-        elif fam == 1:
-            hb = int(r.integers(8, 129))
-            pr = int(r.integers(4, 25))
-            out.append((f"band{logn}_h{hb}_k{pr}", banded(n, hb, min(pr, 2 * hb + 1), seed=s)))
-        elif fam == 2:
-            mean = float(r.uniform(2, 16))
-            out.append((f"poisson{logn}_m{mean:.1f}", poisson_uniform(n, n, mean, seed=s,
-                                                                     values="uniform")))
-        else:
-            kind = int(r.integers(0, 4))
-            if kind == 0:
-                g = int(round(n ** 0.5))
-                A = stencil([g, g], [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)], seed=s)
-                out.append((f"st5_{g}", A))
-            elif kind == 1:
-                g = int(round(n ** 0.5))
-                offs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-                out.append((f"st9_{g}", stencil([g, g], offs, seed=s)))
-            elif kind == 2:
-                g = int(round(n ** (1 / 3)))
-                offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
-                out.append((f"st7_{g}", stencil([g, g, g], offs, seed=s)))
-            else:
-                g = int(round(n ** (1 / 3)))
-                out.append((f"st27_{g}", stencil27(g, seed=s)))
-    return out
+    """The first `count` matrices of the predictor's training set
+    (see training_matrix)."""
+    return [training_matrix(j, seed0, n_lo_log2, n_hi_log2) for j in range(count)]
 
 
 # Named workloads: (description, builder).  Sizes are the full benchmark sizes.

@@ -71,3 +71,44 @@ def test_invalid_arguments_rejected_on_host():
     assert L.opsp_spgemm(ctypes.byref(A), ctypes.byref(B), ctypes.byref(C), None) == 2
     assert L.opsp_spgemm(None, ctypes.byref(B), ctypes.byref(C), None) == 1
     assert L.opsp_spgemm(ctypes.byref(A), ctypes.byref(B), None, None) == 1
+
+
+def test_predictor_arguments_rejected_on_host():
+    """The one-phase entry point checks its predictor before any device work
+    (the fake device pointers below are never dereferenced)."""
+    L = ops.lib()
+    A = ops.opsp_csr(rows=3, cols=4, nnz=0, rpt=1, col=None, val=None)
+    B = ops.opsp_csr(rows=4, cols=2, nnz=0, rpt=1, col=None, val=None)
+    C = ops.opsp_csr()
+
+    def call(**kw):
+        p = ops.opsp_predictor(version=ops.PREDICTOR_VERSION, kind=ops.PRED_UPPER)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return L.opsp_spgemm_learned(ctypes.byref(A), ctypes.byref(B), ctypes.byref(C),
+                                     ctypes.byref(p), None, None, None)
+
+    assert call(version=0) == 1
+    assert call(kind=7) == 1
+    assert call(kind=ops.PRED_MLP) == 1               # no parameters
+    assert call(margin=-0.5) == 1
+    assert call(margin=float("nan")) == 1
+    assert call(kind=ops.PRED_RATIO, ratio=0.0) == 1
+    assert call(cap_scale=-1.0) == 1
+    assert L.opsp_spgemm_learned(ctypes.byref(A), ctypes.byref(B), ctypes.byref(C), None, None,
+                                 None, None) == 1
+    Bbad = ops.opsp_csr(rows=5, cols=2, nnz=0, rpt=1, col=None, val=None)
+    p = ops.opsp_predictor(version=ops.PREDICTOR_VERSION, kind=ops.PRED_UPPER)
+    assert L.opsp_spgemm_learned(ctypes.byref(A), ctypes.byref(Bbad), ctypes.byref(C),
+                                 ctypes.byref(p), None, None, None) == 2
+    # training entry points
+    assert L.opsp_mlp_grad(1, 1, 1, 0, 1, None, None) == 1
+    assert L.opsp_mlp_forward(None, 1, 5, 1, None) == 1
+    assert L.opsp_mlp_adam(1, 1, 1, 1, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None) == 1
+    assert L.opsp_mlp_adam(1, 1, 1, 1, 1, 1e-3, 1.0, 0.999, 1e-8, 1, None) == 1
+
+
+def test_stats_struct_matches_header():
+    """ctypes mirrors have the sizes the header implies."""
+    assert ctypes.sizeof(ops.Stats) == 8 * (4 + ops.SYM_BINS + ops.NUM_BINS) + 4 * 8 + 8 * 5
+    assert ctypes.sizeof(ops.opsp_predictor) == 4 + 4 + 8 + 8 * 3 + 8 + 8

@@ -1,0 +1,177 @@
+"""GPU parity of the one-phase product with predicted capacities
+(opsp_spgemm_learned) against the CPU oracle.
+
+Whatever the capacities, C must be the oracle's product: row pointers and
+columns identical, values within 1e-12 * S_ij.  The capacity sources cover
+the paths of the one-phase kernels: exact-or-larger slots (upper bound),
+slots that are too small (rows go to the overflow arena), tables that fill up
+(rows are recomputed with tables sized from min(n_prod, N)), an exhausted
+arena, every numeric bin forced, and a network with random weights.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _ops():
+    import paper_2206_07244_amd as ops
+    return ops
+
+
+def rand_predictor(seed=3, margin=0.1, **kw):
+    import torch
+    ops = _ops()
+    th = mlp.init(seed) + np.random.default_rng(seed).normal(0, 0.1, mlp.NPARAM)
+    bits = mlp.bf16_bits(th)
+    return ops.Predictor(ops.PRED_MLP, torch.from_numpy(bits.view(np.int16).copy()).cuda(),
+                         margin=margin, **kw)
+
+
+def run(A, B, pred, cfg=None, exact=False, want_caps=False):
+    import torch
+    ops = _ops()
+    dA = ops.DeviceCSR.from_host(A)
+    dB = dA if B is None else ops.DeviceCSR.from_host(B)
+    st = ops.Stats()
+    caps = torch.zeros(A.rows, dtype=torch.int64, device="cuda") if want_caps else None
+    preds = torch.zeros(A.rows, dtype=torch.float32, device="cuda") if want_caps else None
+    C = ops.spgemm_learned(dA, dB, pred, config=cfg, stats=st, pred_out=preds, cap_out=caps)
+    torch.cuda.synchronize()
+    got = C.to_host()
+    ref = oracle.spgemm(A, A if B is None else B)
+    info = oracle.compare(*got, ref, tol=TOL)
+    if exact:
+        assert info["bit_exact_values"], info
+    assert st.nnz == int(ref[0][-1])
+    if want_caps:
+        return st, caps.cpu().numpy(), preds.cpu().numpy()
+    return st
+
+
+def kinds():
+    ops = _ops()
+    return {
+        "upper": ops.Predictor(ops.PRED_UPPER),
+        "ratio2": ops.Predictor(ops.PRED_RATIO, ratio=2.0, margin=0.1),
+        "mlp_random": rand_predictor(),
+        "shrunk": rand_predictor(cap_scale=0.1),
+        "tiny": ops.Predictor(ops.PRED_RATIO, ratio=1e6),
+    }
+
+
+MATS = {
+    "lap5_32": lambda: (syn.lap5(32), None),
+    "st27_12": lambda: (syn.stencil27(12, seed=2), None),
+    "rmat11": lambda: (syn.rmat(11, 16, seed=5), None),
+    "rmat14": lambda: (syn.rmat(14, 16, seed=14), None),
+    "banded": lambda: (syn.banded(20000, 64, 12, seed=3), None),
+    "rect": lambda: (syn.poisson_uniform(3000, 5000, 6.0, seed=1),
+                     syn.poisson_uniform(5000, 2000, 9.0, seed=2)),
+    "ints": lambda: (syn.random_csr(257, 300, 0.05, seed=9, values="int"),
+                     syn.random_csr(300, 129, 0.05, seed=10, values="int")),
+}
+
+
+@pytest.mark.parametrize("mat", list(MATS))
+@pytest.mark.parametrize("kind", ["upper", "ratio2", "mlp_random", "shrunk", "tiny"])
+def test_learned_matches_oracle(mat, kind):
+    A, B = MATS[mat]()
+    st = run(A, B, kinds()[kind], exact=(mat in ("lap5_32", "ints")))
+    if kind == "upper":
+        assert st.retry_rows == 0 and st.slot_overflow_rows == 0
+    if kind == "shrunk" and mat == "rmat14":
+        assert st.slot_overflow_rows > 0 or st.retry_rows > 0
+
+
+@pytest.mark.parametrize("m,k,n,d", [(1, 1, 1, 1.0), (7, 0, 5, 0.5), (0, 4, 4, 0.5),
+                                     (30, 40, 0, 0.5), (50, 60, 70, 0.0), (100, 100, 100, 0.6)])
+def test_learned_degenerate(m, k, n, d):
+    A = syn.random_csr(m, k, d, seed=m + k, values="int")
+    B = syn.random_csr(k, n, d, seed=n + k + 1, values="int")
+    for p in kinds().values():
+        run(A, B, p, exact=True)
+
+
+@pytest.mark.parametrize("b", range(8))
+def test_learned_forced_bins(b):
+    ops = _ops()
+    A = syn.rmat(11, 16, seed=7)
+    run(A, None, rand_predictor(seed=b), cfg=ops.Config(force_num_bin=b))
+    run(A, None, ops.Predictor(ops.PRED_RATIO, ratio=1e6), cfg=ops.Config(force_num_bin=b))
+
+
+def test_table_overflow_recomputes_rows():
+    """Capacities far below the row sizes: small tables fill up, the rows are
+    recomputed exactly into the second arena."""
+    ops = _ops()
+    A = syn.stencil27(16, seed=4)
+    st = run(A, None, ops.Predictor(ops.PRED_RATIO, ratio=1e6, cap_scale=0.01))
+    assert st.table_overflow_rows > 0 and st.retry_rows >= st.table_overflow_rows
+
+
+def test_arena_exhaustion_recomputes_rows():
+    """Slots of zero capacity in tables large enough for the rows (bins 0 and
+    1 take no rows): every nonempty row needs the arena, which holds only
+    65536 entries here, so the rest are recomputed."""
+    ops = _ops()
+    A = syn.banded(40000, 64, 12, seed=8)
+    cfg = ops.Config(num_bounds=[-1, -1, 0, 0, 0, 0, 0])
+    st = run(A, None, ops.Predictor(ops.PRED_UPPER, cap_scale=1e-9), cfg=cfg)
+    assert st.cap_total == 0
+    assert st.arena_entries > 0 and st.retry_rows > 0
+
+
+def test_capacities_follow_the_rule():
+    """Capacities reported by the call equal the rule applied (in float64, as
+    the kernel does) to the network outputs it reports, and obey the bounds."""
+    A = syn.rmat(12, 16, seed=12)
+    pred = rand_predictor(seed=12, margin=0.25)
+    st, caps, y = run(A, None, pred, want_caps=True)
+    nprod, alen, bmax, _ = oracle.row_stats(A, A)
+    ref = mlp.capacity(y.astype(np.float64), 0.25, alen, nprod, bmax, A.cols)
+    hi = np.minimum(nprod, A.cols)
+    assert np.all((caps >= np.minimum(bmax, hi)) | (alen <= 1))
+    assert np.all((caps <= hi) | (alen <= 1))
+    np.testing.assert_array_equal(caps[alen <= 1], nprod[alen <= 1])
+    diff = np.abs(caps - ref)
+    assert np.all(diff <= 1) and np.mean(diff > 0) < 1e-3
+    assert st.cap_total == int(caps.sum())
+    # the reported outputs are the network's outputs for the row features
+    import torch
+    X = _ops().mlp_features(_ops().DeviceCSR.from_host(A), _ops().DeviceCSR.from_host(A))
+    y2 = _ops().mlp_forward(pred.params, X).cpu().numpy()
+    np.testing.assert_array_equal(y, y2)
+
+
+def test_learned_structure_equals_plain_path():
+    import torch
+    ops = _ops()
+    A = syn.rmat(13, 16, seed=21)
+    dA = ops.DeviceCSR.from_host(A)
+    C1 = ops.spgemm(dA, dA)
+    C2 = ops.spgemm_learned(dA, dA, rand_predictor(seed=21))
+    torch.cuda.synchronize()
+    assert torch.equal(C1.rpt, C2.rpt) and torch.equal(C1.col, C2.col)
+
+
+def test_repeated_calls_reuse_memory():
+    import torch
+    ops = _ops()
+    A = syn.stencil27(20, seed=3)
+    dA = ops.DeviceCSR.from_host(A)
+    p = rand_predictor(seed=4)
+    first = None
+    for _ in range(5):
+        C = ops.spgemm_learned(dA, dA, p)
+        torch.cuda.synchronize()
+        if first is None:
+            first = (C.rpt.clone(), C.col.clone())
+        else:
+            assert torch.equal(first[0], C.rpt) and torch.equal(first[1], C.col)
+        del C
