@@ -52,7 +52,7 @@ def main():
     ap.add_argument("--workload", default="st27_100")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "learned"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "learned", "copy"],
                     help="plain: the headline product; batched: 512 uneven products as one "
                          "batch vs 512 plain calls; learned: one-phase product with the trained "
                          "predictor vs the plain two-phase product and the upper-bound rule")
@@ -83,6 +83,8 @@ def main():
         return bench_batched(args, dev)
     if args.mode == "learned":
         return bench_learned(args, dev)
+    if args.mode == "copy":
+        return bench_copy(args, dev)
 
     desc, builder = syn.WORKLOADS[args.workload]
     t0 = time.time()
@@ -197,6 +199,27 @@ def main():
         log(f"cpu oracle: {cpu_gflops:.3f} GFLOPS over {reps} run(s)")
 
     print(json.dumps(out), flush=True)
+
+
+def bench_copy(args, dev):
+    """Calibration of the HBM byte counters: `steps` device-to-device copies
+    of a 1 GiB buffer (1 GiB read + 1 GiB written per copy); the counters'
+    reading for this run over the known bytes is the scale factor applied to
+    the kernels' readings."""
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
+                      "copies": args.steps, "ms_per_copy": round(ms, 4),
+                      "GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
 def time_learned(ops, torch, dA, dB, pred, steps, warmup):

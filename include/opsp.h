@@ -103,6 +103,11 @@ typedef struct {
      * autotuner searches. */
     int64_t sym_bounds[7];
     int64_t num_bounds[7];
+    /* Version >= 2: 1 = every row takes the hash tables, as in the paper;
+     * 0 = rows whose output columns span a short range are counted in a
+     * bitmap of that range (symbolic) and accumulated in a dense array of it
+     * (numeric), which gives the same result without probing. */
+    int32_t hash_all_rows;
 } opsp_config;
 
 /* Counters of one call (filled when a stats pointer is given). */

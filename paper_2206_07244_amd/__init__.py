@@ -51,7 +51,8 @@ class Config(ctypes.Structure):
                 ("force_sym_bin", c_int32), ("force_num_bin", c_int32),
                 ("sym_abort_fraction", c_double), ("b_lanes", c_int32),
                 ("stage_timing", c_int32), ("validate", c_int32), ("fixed_grid", c_int32),
-                ("sym_bounds", c_int64 * 7), ("num_bounds", c_int64 * 7)]
+                ("sym_bounds", c_int64 * 7), ("num_bounds", c_int64 * 7),
+                ("hash_all_rows", c_int32)]
 
     def __init__(self, **kw):
         super().__init__()
@@ -69,7 +70,8 @@ class Config(ctypes.Structure):
     def as_dict(self) -> dict:
         return {"sym_ratio": self.sym_ratio, "num_ratio": self.num_ratio,
                 "sym_abort_fraction": self.sym_abort_fraction,
-                "sym_bounds": list(self.sym_bounds), "num_bounds": list(self.num_bounds)}
+                "sym_bounds": list(self.sym_bounds), "num_bounds": list(self.num_bounds),
+                "hash_all_rows": self.hash_all_rows}
 
 
 class Stats(ctypes.Structure):

@@ -47,12 +47,13 @@ class Candidate(dict):
 
     def key(self):
         return (round(self["sym_ratio"], 6), round(self["num_ratio"], 6), tuple(self["sym_bounds"]),
-                tuple(self["num_bounds"]), round(self["sym_abort_fraction"], 6))
+                tuple(self["num_bounds"]), round(self["sym_abort_fraction"], 6),
+                int(self.get("hash_all_rows", 0)))
 
 
 def base_candidate(sr=1.2, nr=2.0) -> Candidate:
     return Candidate(sym_ratio=sr, num_ratio=nr, sym_bounds=[0] * 7, num_bounds=[0] * 7,
-                     sym_abort_fraction=0.8)
+                     sym_abort_fraction=0.8, hash_all_rows=0)
 
 
 def derived_bounds(step: int, tsizes: List[int], ratio: float) -> List[int]:
@@ -128,7 +129,8 @@ def search(cost: Callable[[Candidate], float], sym_t: List[int], num_t: List[int
                         cur, cc = c, v
         if cc < bc:
             best, bc = cur, cc
-    # 4. abort fraction of the largest symbolic table
+    # 4. abort fraction of the largest symbolic table, and hashing every row
+    #    (the paper's method) against the bitmap / dense paths for narrow rows
     if abort:
         for a in ABORT_FRACTIONS:
             c = Candidate(best)
@@ -136,6 +138,11 @@ def search(cost: Callable[[Candidate], float], sym_t: List[int], num_t: List[int
             v = ev(c)
             if v < bc:
                 best, bc = c, v
+        c = Candidate(best)
+        c["hash_all_rows"] = 1 - int(best.get("hash_all_rows", 0))
+        v = ev(c)
+        if v < bc:
+            best, bc = c, v
     return best, bc
 
 
@@ -143,7 +150,7 @@ def to_config(c: dict):
     import paper_2206_07244_amd as ops
     return ops.Config(sym_ratio=c["sym_ratio"], num_ratio=c["num_ratio"],
                       sym_abort_fraction=c["sym_abort_fraction"], sym_bounds=c["sym_bounds"],
-                      num_bounds=c["num_bounds"])
+                      num_bounds=c["num_bounds"], hash_all_rows=int(c.get("hash_all_rows", 0)))
 
 
 def load_config(cls: str, path: Optional[str] = None):

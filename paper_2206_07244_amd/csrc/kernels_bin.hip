@@ -9,6 +9,8 @@
 // and, for the numeric step, per-block row-pointer offsets.  The second pass
 // then places every row with no global atomic at all: rows of a bin appear in
 // ascending order, so the bin lists are deterministic.
+#include <limits.h>
+
 #include "opsp_internal.h"
 
 namespace opsp {
@@ -26,10 +28,14 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
                                                int64_t *__restrict__ nprod, Bounds bd,
                                                BlockParts parts,
                                                int32_t *__restrict__ f_alen,
-                                               int32_t *__restrict__ f_bmax) {
+                                               int32_t *__restrict__ f_bmax,
+                                               const int32_t *__restrict__ bcol,
+                                               int32_t *__restrict__ f_lo,
+                                               int32_t *__restrict__ f_hi) {
     __shared__ int64_t rs[4][65];
     __shared__ unsigned long long acc[4][64];
     __shared__ unsigned int bmx[4][64];
+    __shared__ int clo[4][64], chi[4][64];
     __shared__ unsigned int hist[BIN_SLOTS];
     __shared__ unsigned long long s_tot, s_max;
 
@@ -44,18 +50,30 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     }
     acc[w][l] = 0;
     bmx[w][l] = 0;
+    clo[w][l] = INT_MAX;
+    chi[w][l] = -1;
     __syncthreads();
+    const bool range = f_lo != nullptr;   // column range of each row's output
 
     if (nrows > 0) {
         const int64_t e0 = rs[w][0], e1 = rs[w][64];
         // four entries per lane per step so that their gathers overlap
         for (int64_t eb = e0 + l; eb < e1; eb += 256) {
-            int64_t len[4];
+            int64_t len[4], b0[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t e = eb + 64 * u;
                 const int k = e < e1 ? acol[e] : -1;
-                len[u] = k >= 0 ? brpt[k + 1] - brpt[k] : -1;
+                b0[u] = k >= 0 ? brpt[k] : 0;
+                len[u] = k >= 0 ? brpt[k + 1] - b0[u] : -1;
+            }
+            int first[4], last[4];
+            if (range) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    first[u] = len[u] > 0 ? bcol[b0[u]] : INT_MAX;
+                    last[u] = len[u] > 0 ? bcol[b0[u] + len[u] - 1] : -1;
+                }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -69,6 +87,10 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
                 }
                 atomicAdd(&acc[w][lo], (unsigned long long)len[u]);
                 atomicMax(&bmx[w][lo], (unsigned)(len[u] > 0xffffffffll ? 0xffffffffll : len[u]));
+                if (range && len[u] > 0) {
+                    atomicMin(&clo[w][lo], first[u]);
+                    atomicMax(&chi[w][lo], last[u]);
+                }
             }
         }
     }
@@ -81,6 +103,10 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
         nprod[i] = (int64_t)v;
         if (f_alen) f_alen[i] = (int32_t)(rs[w][l + 1] - rs[w][l]);
         if (f_bmax) f_bmax[i] = (int32_t)bmx[w][l];
+        if (range) {
+            f_lo[i] = clo[w][l];
+            f_hi[i] = chi[w][l];
+        }
     }
     const int b = valid ? bin_of((int64_t)v, bd) : -1;
     for (int j = 0; j < bd.nslots; ++j) {
@@ -276,11 +302,12 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds b
 
 // ---------------------------------------------------------------------------
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
-                        const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s) {
+                        const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s,
+                        int32_t *f_lo, int32_t *f_hi) {
     if (A.rows == 0) return hipSuccess;
     const int64_t grid = (A.rows + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)grid), dim3(256), 0, s, A.rows, A.rpt, A.col, B.rpt,
-                       nprod, bd, parts, f_alen, f_bmax);
+                       nprod, bd, parts, f_alen, f_bmax, B.col, f_lo, f_hi);
     return hipGetLastError();
 }
 

@@ -326,7 +326,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    Counters *__restrict__ ctr, Learn L) {
+    Counters *__restrict__ ctr, Learn L, const int32_t *__restrict__ rlo,
+    const int32_t *__restrict__ rhi) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;
@@ -345,7 +346,9 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     __shared__ long long s_base[R];
 
     src.resolve();
-    const int team = threadIdx.x / W, t = threadIdx.x % W;
+    // the team index is uniform over each wave: keep it (and all per-row
+    // values derived from it) in scalar registers
+    const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / W), t = threadIdx.x % W;
     const int wv = t >> 6;
     int *tk = keys + team * T;
     double *tv = vals + team * T;
@@ -354,14 +357,99 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     // the same early returns
     auto do_row = [&](const int64_t idx) {
     const bool active = idx < src.nrows;
+    // A row whose output columns span at most T positions accumulates into a
+    // dense array of that range (values) plus a bitmap (occupancy): no
+    // probing, and the rank of a column is a popcount.
+    int64_t row = 0;
+    bool dn = false;
+    int lo = 0, dspan = 0;
+    if (active) {
+        row = src.row(idx);
+        if (rlo) {
+            lo = rlo[row];
+            const int64_t sp = (int64_t)rhi[row] - lo + 1;
+            if (sp <= T) {
+                dn = true;
+                dspan = sp > 0 ? (int)sp : 0;
+            }
+        }
+    }
+    const int nwd = (dspan + 31) >> 5;
     team_sync<WT>();   // the previous row of this team is done with the table
-    for (int s = t; s < T; s += W) { tk[s] = -1; tv[s] = 0.0; }
+    if (dn) {
+        for (int s = t; s < dspan; s += W) tv[s] = 0.0;
+        for (int s = t; s < nwd; s += W) tk[s] = 0;
+    } else {
+        for (int s = t; s < T; s += W) { tk[s] = -1; tv[s] = 0.0; }
+    }
     if (LRN && t == 0) s_cnt[team] = 0;
     team_sync<WT>();
 
-    int64_t row = 0;
+    // where the n entries of the row go: (base, cap), base < 0 = skip
+    auto place = [&](int n, int64_t &base, int64_t &cap) {
+        if constexpr (LRN) {
+            if (active && t == 0) {
+                const int64_t b = lrn_place(L, row, n);
+                if (b < 0) lrn_retry(L, row, false);
+                else lrn_done(L, row, n, b);
+                s_base[team] = b;
+            }
+            team_sync<WT>();
+            base = active ? (int64_t)s_base[team] : -1;
+            cap = n;
+        } else {
+            base = active ? crpt[row] : -1;
+            cap = active ? crpt[row + 1] - base : 0;
+            if (active && t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
+        }
+    };
+
+    if (dn) {   // uniform over the team
+        if (active) {
+            unsigned int *bits = reinterpret_cast<unsigned int *>(tk);
+            auto acc = [&](bool ok, int key, double v) {
+                const uint32_t o = (uint32_t)(key - lo);
+                if (ok && o < (uint32_t)dspan) {
+                    atomicOr(&bits[o >> 5], 1u << (o & 31));
+                    atomicAdd(&tv[o], v);
+                }
+            };
+            row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, NW, acc,
+                               [] { return false; });
+        }
+        team_sync<WT>();
+        // exclusive popcount prefix per bitmap word, after the words
+        unsigned int *bits = reinterpret_cast<unsigned int *>(tk);
+        int *pre = tk + nwd;
+        const int q = (nwd + W - 1) / W;
+        const int w0 = t * q, w1 = w0 + q < nwd ? w0 + q : nwd;
+        int sum = 0;
+        for (int w = w0; w < w1; ++w) sum += __popc(bits[w]);
+        int n;
+        int p0 = team_excl_scan<WT, NW>(sum, n, red);
+        for (int w = w0; w < w1; ++w) {
+            pre[w] = p0;
+            p0 += __popc(bits[w]);
+        }
+        team_sync<WT>();
+        int64_t base, cap;
+        place(n, base, cap);
+        if (base < 0 || n == 0) return;   // uniform over the team
+        for (int o = t; o < dspan; o += W) {
+            const unsigned int word = bits[o >> 5];
+            const unsigned int bit = 1u << (o & 31);
+            if (word & bit) {
+                const int rank = pre[o >> 5] + __popc(word & (bit - 1u));
+                if (rank < cap) {
+                    ccol[base + rank] = lo + o;
+                    cval[base + rank] = tv[o];
+                }
+            }
+        }
+        return;
+    }
+
     if (active) {
-        row = src.row(idx);
         auto ins = [&](bool ok, int key, double v) {
             const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
                                            [](double *p, double x) { atomicAdd(p, x); });
@@ -400,23 +488,9 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     int n = c;
     team_min_max_sum<WT, NW>(kmin, kmax, n, red);
     int64_t base, cap;
-    if constexpr (LRN) {
-        if (active && t == 0) {
-            const int64_t b = lrn_place(L, row, n);
-            if (b < 0) lrn_retry(L, row, false);
-            else lrn_done(L, row, n, b);
-            s_base[team] = b;
-        }
-        team_sync<WT>();
-        base = active ? (int64_t)s_base[team] : -1;
-        if (base < 0) return;   // uniform over the team
-        cap = n;
-    } else {
-        base = active ? crpt[row] : 0;
-        cap = active ? crpt[row + 1] - base : 0;
-        if (active && t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
-    }
-    if (n == 0) return;   // uniform over the team
+    place(n, base, cap);
+    if (LRN && base < 0) return;   // uniform over the team
+    if (n == 0) return;            // uniform over the team
 
     if (n > NPACK) {
         // rank by counting against the intact table
@@ -804,11 +878,11 @@ static hipError_t go_row(const NumArgs &a, hipStream_t s) {
     if (a.lrn.mode == 1)
         hipLaunchKernelGGL((k_num_row<W, T, true>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
                            a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                           a.cval, a.ctr, a.lrn);
+                           a.cval, a.ctr, a.lrn, a.rlo, a.rhi);
     else
         hipLaunchKernelGGL((k_num_row<W, T, false>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
                            a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                           a.cval, a.ctr, a.lrn);
+                           a.cval, a.ctr, a.lrn, a.rlo, a.rhi);
     return hipGetLastError();
 }
 

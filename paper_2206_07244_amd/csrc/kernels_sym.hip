@@ -110,7 +110,8 @@ template <int W, int T, bool ABORT, bool PERSIST>
 __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
-    int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list) {
+    int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list,
+    const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;  // waves per team
@@ -120,21 +121,53 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     __shared__ int red[NW];
     src.resolve();
 
-    const int team = threadIdx.x / W, t = threadIdx.x % W;
+    // the team index is uniform over each wave: keep it (and all per-row
+    // values derived from it) in scalar registers
+    const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / W), t = threadIdx.x % W;
     int *tb = tab + team * T;
     const int64_t stride = PERSIST ? (int64_t)gridDim.x * R : src.nrows + R;
     for (int64_t b0 = (int64_t)blockIdx.x * R; b0 < src.nrows; b0 += stride) {
         const int64_t idx = b0 + team;
         const bool active = idx < src.nrows;
+        // A row whose output columns span at most 32 T positions, with no
+        // more bitmap words than twice its products, is counted in a bitmap
+        // of that range (an atomic OR per product, a popcount at the end)
+        // instead of the hash table: same count, no probing.
+        int64_t row = 0;
+        bool bm = false;
+        int lo = 0, nwords = 0;
+        uint32_t span = 0;
+        if (active) {
+            row = src.row(idx);
+            if (rlo) {
+                lo = rlo[row];
+                const int64_t sp = (int64_t)rhi[row] - lo + 1;
+                const int64_t w = sp > 0 ? (sp + 31) >> 5 : 0;
+                if (sp <= 32ll * T && w <= 2 * nnz[row]) {
+                    bm = true;
+                    nwords = (int)w;
+                    span = sp > 0 ? (uint32_t)sp : 0u;
+                }
+            }
+        }
         team_sync<WT>();   // the previous row of this team is done with the table
-        for (int s = t; s < T; s += W) tb[s] = -1;
+        if (bm) {
+            for (int s = t; s < nwords; s += W) tb[s] = 0;
+        } else {
+            for (int s = t; s < T; s += W) tb[s] = -1;
+        }
         if (t == 0) { s_cnt[team] = 0; s_abort[team] = 0; }
         team_sync<WT>();
 
         int cnt = 0;
-        int64_t row = 0;
-        if (active) {
-            row = src.row(idx);
+        if (active && bm) {
+            auto set = [&](bool ok, int key) {
+                const uint32_t o = (uint32_t)(key - lo);
+                if (ok && o < span) atomicOr((unsigned int *)&tb[o >> 5], 1u << (o & 31));
+            };
+            row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6,
+                                NW, set, [] { return false; });
+        } else if (active) {
             auto ins = [&](bool ok, int key) {
                 const int nw = sym_insert_wave(tb, (uint32_t)T, ok, key, &ctr->error);
                 if constexpr (ABORT) {
@@ -154,7 +187,11 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
             row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6,
                                 NW, ins, stop);
         }
-        if (ABORT) {
+        if (bm) {   // uniform over the team
+            team_sync<WT>();
+            for (int s = t; s < nwords; s += W) cnt += __popc((unsigned int)tb[s]);
+        }
+        if (ABORT && !bm) {
             team_sync<WT>();
             if (active && t == 0) {
                 if (s_abort[team]) {
@@ -231,11 +268,11 @@ static hipError_t go_row(const SymArgs &a, hipStream_t s) {
     if (a.grid > 0)
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, true>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list);
+                           a.fail_list, a.rlo, a.rhi);
     else
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, false>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list);
+                           a.fail_list, a.rlo, a.rhi);
     return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ struct opsp_plan {
     bool check = false;
     int64_t fixed_grid = 0;             // > 0: every bin kernel runs persistently with this grid
     Counters *ctr = nullptr;            // device counters (numeric step), owned
+    int32_t *range = nullptr;           // output column range per row: lo[M], hi[M] (owned)
     opsp_stats stats = {};
 };
 
@@ -248,6 +249,13 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     const int64_t nblk = (M + 255) / 256;
     CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M));
     int32_t *bins = (int32_t *)p;
+    // output column range per row (narrow rows avoid the hash tables)
+    int32_t *rlo = nullptr, *rhi = nullptr;
+    if (!(cfg && cfg->version >= 2 && cfg->hash_all_rows)) {
+        CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 2));
+        rlo = (int32_t *)p;
+        rhi = rlo + M;
+    }
     CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
     BlockParts parts;
     parts.tot = (unsigned long long *)p;
@@ -260,7 +268,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 
     // 1 setup + first symbolic binning pass
     tm.mark();
-    CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s));
+    CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s, rlo, rhi));
     CHK(launch_finalize(M, bs.nslots, parts, ctrS, nullptr, false, s));
     Counters hS;
     CHK(read_counters(&hS, ctrS, 1, s));
@@ -286,6 +294,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.B = dB;
     sa.nnz = crpt;
     sa.ctr = ctrS;
+    sa.rlo = rlo;
+    sa.rhi = rhi;
     int32_t *fail_list = nullptr;
     const int64_t big = ssz[7] + ssz[SYM_GLOBAL_BIN];
     int *slab = nullptr;
@@ -366,6 +376,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     tm.mark();
     ar.keep(crpt);
     ar.keep(ctrS);
+    if (rlo) ar.keep(rlo);
+    plan->range = rlo;
     if (identity < 0) ar.keep(bins);
     plan->identity_bin = identity;
     plan->crpt = crpt;
@@ -390,6 +402,8 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     na.ccol = ccol;
     na.cval = cval;
     na.ctr = plan->ctr;
+    na.rlo = plan->range;
+    na.rhi = plan->range ? plan->range + plan->M : nullptr;
     const int gb = NUM_GLOBAL_BIN;
     bool first = true;
     void *pk = nullptr, *pv = nullptr;
@@ -428,6 +442,8 @@ void plan_release(opsp_plan *plan, hipStream_t s) {
     if (!plan) return;
     if (plan->crpt) (void)cache_free(plan->crpt, s);
     if (plan->bins) (void)cache_free(plan->bins, s);
+    if (plan->range) (void)cache_free(plan->range, s);
+    plan->range = nullptr;
     if (plan->ctr) (void)cache_free(plan->ctr - 1, s);  // both counters share one allocation
     plan->crpt = nullptr;
     plan->bins = nullptr;

@@ -39,9 +39,13 @@ struct BlockParts {
 };
 
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
-// per-block bin counts / totals / maxima into `parts`; optional features.
+// per-block bin counts / totals / maxima into `parts`; optional features
+// (a_len, b_max) and the column range [f_lo, f_hi] of each row's output (the
+// smallest first and largest last column of the B rows it references;
+// INT_MAX / -1 for rows without products).
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
-                        const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s);
+                        const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s,
+                        int32_t *f_lo = nullptr, int32_t *f_hi = nullptr);
 // First binning pass over existing row values (numeric step).
 hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, const BlockParts &parts,
                        hipStream_t s);
@@ -68,6 +72,8 @@ struct SymArgs {
     int *slab;               // global tables (bin 8)
     int64_t slab_entries;
     int64_t grid;            // fixed grid (persistent launch); 0 = one team per row
+    const int32_t *rlo;      // optional column range of each row (setup step): rows
+    const int32_t *rhi;      // with a narrow range are counted with a bitmap
 };
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
 
@@ -84,6 +90,8 @@ struct NumArgs {
     int64_t slab_entries;
     int64_t grid;
     Learn lrn;               // one-phase step (lrn.mode > 0); crpt unused then
+    const int32_t *rlo;      // optional column range of each row (setup step): rows
+    const int32_t *rhi;      // with a narrow range accumulate densely (bins 1-6)
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 

@@ -96,8 +96,9 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     int64_t *nz = (int64_t *)p;
     CHK(ar.alloc(&p, sizeof(int64_t) * (size_t)M));
     int64_t *loc = (int64_t *)p;
-    CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 4));
+    CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 6));
     int32_t *alen = (int32_t *)p, *bmax = alen + M, *bins = alen + 2 * M, *retry = alen + 3 * M;
+    int32_t *rlo = alen + 4 * M, *rhi = alen + 5 * M;   // output column range per row
     CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
     BlockParts parts;
     parts.tot = (unsigned long long *)p;
@@ -114,7 +115,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     // 1-2 setup, capacities, numeric bins by capacity, slot offsets
     tm.mark();
     CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnCtr), s));
-    CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s));
+    CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s, rlo, rhi));
     CapArgs ca;
     memset(&ca, 0, sizeof(ca));
     ca.kind = pr->kind;
@@ -158,6 +159,9 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     na.ccol = tcol;
     na.cval = tval;
     na.ctr = &dc->num;
+    const bool ranges = !(cfg && cfg->version >= 2 && cfg->hash_all_rows);
+    na.rlo = ranges ? rlo : nullptr;
+    na.rhi = ranges ? rhi : nullptr;
     na.lrn.mode = 1;
     na.lrn.off = off;
     na.lrn.nprod = np;

@@ -94,26 +94,30 @@ def test_explicit_zero_kept():
 
 
 @pytest.mark.parametrize("b", list(range(9)))
-def test_forced_symbolic_bin(b):
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_forced_symbolic_bin(b, hash_all):
     ops = _ops()
-    cfg = ops.Config(force_sym_bin=b, validate=1)
+    cfg = ops.Config(force_sym_bin=b, validate=1, hash_all_rows=hash_all)
     st = ops.Stats()
     check(syn.rmat(12, 16, seed=5), cfg=cfg, stats=st)
     assert st.sym_bin_rows[b] > 0
 
 
 @pytest.mark.parametrize("b", list(range(8)))
-def test_forced_numeric_bin(b):
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_forced_numeric_bin(b, hash_all):
     ops = _ops()
-    cfg = ops.Config(force_num_bin=b, validate=1)
+    cfg = ops.Config(force_num_bin=b, validate=1, hash_all_rows=hash_all)
     st = ops.Stats()
     check(syn.rmat(12, 16, seed=6), cfg=cfg, stats=st)
     assert st.num_bin_rows[b] > 0
 
 
 def test_every_big_row_recomputed_globally():
+    """With every row hashed (the paper's method), abort-fraction -1 sends
+    every bin-7 row to the global tables."""
     ops = _ops()
-    cfg = ops.Config(sym_abort_fraction=-1.0, validate=1)
+    cfg = ops.Config(sym_abort_fraction=-1.0, validate=1, hash_all_rows=1)
     st = ops.Stats()
     check(syn.rmat(14, 16, seed=7), cfg=cfg, stats=st)
     assert st.sym_bin_rows[7] > 0 and st.sym_bin_rows[8] >= st.sym_bin_rows[7]
@@ -187,13 +191,15 @@ def test_structure_deterministic_over_runs():
 
 
 @pytest.mark.parametrize("b", list(range(9)))
-def test_forced_bins_persistent_launch(b):
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_forced_bins_persistent_launch(b, hash_all):
     """Symbolic bin kernels (and numeric bin 0) launched with a small fixed
     grid, so each workgroup walks many rows (the launch form of captured
     graphs)."""
     ops = _ops()
     st = ops.Stats()
-    cfg = ops.Config(force_sym_bin=b, force_num_bin=0 if b == 0 else -1, validate=1, fixed_grid=7)
+    cfg = ops.Config(force_sym_bin=b, force_num_bin=0 if b == 0 else -1, validate=1, fixed_grid=7,
+                     hash_all_rows=hash_all)
     check(syn.rmat(12, 16, seed=13), cfg=cfg, stats=st)
     assert st.sym_bin_rows[b] > 0
 
@@ -203,3 +209,42 @@ def test_persistent_launch_all_bins_rmat14():
     st = ops.Stats()
     check(syn.rmat(14, 16, seed=14), cfg=ops.Config(validate=1, fixed_grid=5), stats=st)
     assert all(x > 0 for x in st.num_bin_rows)
+
+
+@pytest.mark.parametrize("b", list(range(9)))
+@pytest.mark.parametrize("grid", [0, 7])
+def test_forced_symbolic_bin_narrow_rows(b, grid):
+    """Rows whose output columns span a narrow range are counted with a
+    bitmap of that range in bins 1-7 (hash tables in bins 0 and 8): force
+    every row of a banded matrix and of a 27-point stencil through each bin,
+    with one team per row and with a small persistent grid."""
+    ops = _ops()
+    mats = [syn.banded(3000, 40, 9, seed=b)]
+    if b > 0:   # no 27-point row has as few products as bin 0 holds
+        mats.append(syn.stencil27(9, seed=b))
+    for A in mats:
+        st = ops.Stats()
+        cfg = ops.Config(force_sym_bin=b, validate=1, fixed_grid=grid)
+        check(A, cfg=cfg, stats=st)
+        assert st.sym_bin_rows[b] > 0
+
+
+def test_narrow_and_wide_rows_mixed():
+    """One product whose rows alternate between a narrow column range and
+    the full width (wide rows take the hash table)."""
+    n = 4000
+    A = syn.banded(n, 8, 5, seed=1)
+    W = syn.random_csr(n, n, 3.0 / n, seed=2)
+    rows = np.arange(n)
+    pick = (rows % 2 == 0)
+    rpt = [0]
+    col, val = [], []
+    for i in range(n):
+        src = A if pick[i] else W
+        a, b = src.rpt[i], src.rpt[i + 1]
+        col.append(src.col[a:b])
+        val.append(src.val[a:b])
+        rpt.append(rpt[-1] + (b - a))
+    M = syn.CSR(n, n, np.array(rpt, np.int64), np.concatenate(col).astype(np.int32),
+                np.concatenate(val))
+    check(M)
