@@ -30,6 +30,46 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# Sources whose change invalidates a stored HBM-traffic measurement of the
+# numeric kernels (the counters were taken on the build of these files).
+TRAFFIC_SOURCES = ["paper_2206_07244_amd/csrc/kernels_num.hip", "paper_2206_07244_amd/csrc/opsp_dev.h",
+                   "paper_2206_07244_amd/csrc/opsp_tables.h"]
+
+
+def sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summaries under profiles/ (a line 'traffic_record: {json}'),
+    scaled by the copy calibration; None when no record matches the current
+    kernel sources."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    digest = sources_digest()
+    for f in sorted(os.listdir(d)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for line in fh:
+                if line.startswith("traffic_record:"):
+                    try:
+                        r = json.loads(line.split(":", 1)[1])
+                    except ValueError:
+                        continue
+                    if (r.get("kernel") == kernel and r.get("workload") == workload
+                            and r.get("sources_sha1") == digest):
+                        return r
+    return None
+
+
 def numeric_bytes(M, nnzA, nprod, nnzC):
     """Algorithmic HBM bytes of the numeric step (one launch over all rows):
     A col+val 12 B/entry and B row bounds 16 B per A entry; B col+val 12 B per
@@ -173,6 +213,11 @@ def main():
                      "numbin_scan_alloc": round(stage[2], 4), "numeric": round(stage[3], 4),
                      "total": round(stage[4], 4)},
     }
+
+    rec = stored_traffic(kernel, args.workload)
+    if rec is not None:
+        out["roofline"]["traffic"] = int(rec["bytes_per_launch"])
+        out["roofline"]["traffic_source"] = rec.get("file", "profiles")
 
     if not args.no_learned and os.path.exists(ops.DEFAULT_WEIGHTS):
         pred = ops.Predictor.load(device=dev)

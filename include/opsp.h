@@ -266,13 +266,16 @@ opsp_status opsp_mlp_features(const opsp_csr *A, const opsp_csr *B, float *X, vo
 opsp_status opsp_mlp_forward(const uint16_t *params, const float *X, int64_t n, float *y,
                              void *stream);
 
-/* Mean squared error L = sum_i (y_i - target_i)^2 / n over n >= 1 rows and its
- * gradient with respect to the OPSP_MLP_NPARAM parameters (float32, same
- * packing), evaluated at the bfloat16 parameters, with the rounding of h1
- * passed straight through.  grad: device float[OPSP_MLP_NPARAM]; loss:
- * device float[1] or NULL. */
+/* Loss over n >= 1 rows and its gradient with respect to the OPSP_MLP_NPARAM
+ * parameters (float32, same packing), evaluated at the bfloat16 parameters,
+ * with the rounding of h1 passed straight through.  tau == 0: mean squared
+ * error L = sum_i (y_i - target_i)^2 / n; 0 < tau < 1: mean pinball loss of
+ * level tau, L = sum_i rho(target_i - y_i) / n with rho(r) = tau r for r > 0
+ * and (tau - 1) r otherwise (the network then estimates the tau-quantile of
+ * the row size).  grad: device float[OPSP_MLP_NPARAM]; loss: device float[1]
+ * or NULL. */
 opsp_status opsp_mlp_grad(const uint16_t *params, const float *X, const float *target, int64_t n,
-                          float *grad, float *loss, void *stream);
+                          float tau, float *grad, float *loss, void *stream);
 
 /* One Adam step (Kingma and Ba, 2015) on float32 master parameters with
  * moments m, v (device float[OPSP_MLP_NPARAM] each, updated in place), step

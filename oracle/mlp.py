@@ -28,9 +28,10 @@ GPU).  `quant=False` evaluates the plain float64 network instead (used for
 the finite-difference checks, where the quantisation would make the loss
 piecewise constant in W1 and b1).
 
-Backward pass: mean squared error over a batch of B rows, gradients by the
-chain rule with the bf16 rounding of h1 passed straight through (its
-derivative taken as 1).  `absolute=True` evaluates the same formulas on the
+Backward pass: mean squared error (or the pinball loss of a quantile level
+tau, which makes the network predict an upper quantile of the row size) over
+a batch of B rows, gradients by the chain rule with the bf16 rounding of h1
+passed straight through (its derivative taken as 1).  `absolute=True` evaluates the same formulas on the
 absolute values of every factor, which bounds the magnitude of the terms
 summed into each gradient entry (the scale for rounding-error tolerances).
 """
@@ -123,19 +124,33 @@ def forward(theta: np.ndarray, X: np.ndarray, quant: bool = True):
     return y, (np.asarray(X, np.float64), z1, h1, z2, h2)
 
 
-def loss(theta: np.ndarray, X: np.ndarray, t: np.ndarray, quant: bool = True) -> float:
+def pointwise_loss(y, t, tau=None):
+    """Squared error (tau None), or the pinball (quantile) loss of level tau
+    on r = t - y: tau * r for r > 0, (tau - 1) * r otherwise."""
+    r = np.asarray(t, np.float64) - np.asarray(y, np.float64)
+    if tau is None:
+        return r * r
+    return np.where(r > 0, tau * r, (tau - 1.0) * r)
+
+
+def loss(theta: np.ndarray, X: np.ndarray, t: np.ndarray, quant: bool = True, tau=None) -> float:
     y, _ = forward(theta, X, quant)
-    return float(np.mean((y - np.asarray(t, np.float64)) ** 2))
+    return float(np.mean(pointwise_loss(y, t, tau)))
 
 
 def grad(theta: np.ndarray, X: np.ndarray, t: np.ndarray, quant: bool = True,
-         absolute: bool = False):
-    """(loss, dloss/dtheta) of the mean squared error over the batch."""
+         absolute: bool = False, tau=None):
+    """(loss, dloss/dtheta) of the mean squared error (tau None) or of the
+    mean pinball loss of level tau over the batch.  The pinball loss has
+    derivative -tau / B for t > y and (1 - tau) / B otherwise."""
     p = unpack(theta)
     y, (X, z1, h1, z2, h2) = forward(theta, X, quant)
     B = X.shape[0]
-    r = y - np.asarray(t, np.float64)
-    dy = 2.0 * r / B
+    t = np.asarray(t, np.float64)
+    if tau is None:
+        dy = 2.0 * (y - t) / B
+    else:
+        dy = np.where(t - y > 0, -tau, 1.0 - tau) / B
     W2, W3 = p["W2"], p["W3"]
     if absolute:
         dy, W2, W3, X, h1, h2 = (np.abs(a) for a in (dy, W2, W3, X, h1, h2))
@@ -148,7 +163,7 @@ def grad(theta: np.ndarray, X: np.ndarray, t: np.ndarray, quant: bool = True,
     dz1 = (dz2 @ W2) * (z1 > 0)
     g["W1"] = dz1.T @ X
     g["b1"] = dz1.sum(axis=0)
-    return float(np.mean(r ** 2)), pack(g)
+    return float(np.mean(pointwise_loss(y, t, tau))), pack(g)
 
 
 def adam_step(theta, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

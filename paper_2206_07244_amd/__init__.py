@@ -165,7 +165,7 @@ def lib():
         L.opsp_mlp_forward.restype = ctypes.c_int
         L.opsp_mlp_forward.argtypes = [P, P, c_int64, P, P]
         L.opsp_mlp_grad.restype = ctypes.c_int
-        L.opsp_mlp_grad.argtypes = [P, P, P, c_int64, P, P, P]
+        L.opsp_mlp_grad.argtypes = [P, P, P, c_int64, ctypes.c_float, P, P, P]
         L.opsp_mlp_adam.restype = ctypes.c_int
         L.opsp_mlp_adam.argtypes = [P, P, P, P, c_int64, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_float, P, P]
@@ -499,15 +499,16 @@ def mlp_forward(params, X, stream=None):
     return y
 
 
-def mlp_grad(params, X, target, stream=None):
-    """(gradient float32[MLP_NPARAM], loss float32[1]) of the mean squared error."""
+def mlp_grad(params, X, target, tau: float = 0.0, stream=None):
+    """(gradient float32[MLP_NPARAM], loss float32[1]) of the mean squared error
+    (tau = 0) or of the mean pinball loss of level tau."""
     torch = _torch()
     params = _params_tensor(params)
     X, target = X.contiguous(), target.contiguous()
     g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=X.device)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
-    _check(lib().opsp_mlp_grad(_ptr(params), _ptr(X), _ptr(target), X.shape[0], _ptr(g), _ptr(loss),
-                               _stream_handle(stream)), "opsp_mlp_grad")
+    _check(lib().opsp_mlp_grad(_ptr(params), _ptr(X), _ptr(target), X.shape[0], float(tau), _ptr(g),
+                               _ptr(loss), _stream_handle(stream)), "opsp_mlp_grad")
     return g, loss
 
 

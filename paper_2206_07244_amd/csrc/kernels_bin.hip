@@ -29,9 +29,8 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
                                                BlockParts parts,
                                                int32_t *__restrict__ f_alen,
                                                int32_t *__restrict__ f_bmax,
-                                               const int32_t *__restrict__ bcol,
-                                               int32_t *__restrict__ f_lo,
-                                               int32_t *__restrict__ f_hi) {
+                                               const int2 *__restrict__ bfl,
+                                               int2 *__restrict__ rng) {
     __shared__ int64_t rs[4][65];
     __shared__ unsigned long long acc[4][64];
     __shared__ unsigned int bmx[4][64];
@@ -53,27 +52,20 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     clo[w][l] = INT_MAX;
     chi[w][l] = -1;
     __syncthreads();
-    const bool range = f_lo != nullptr;   // column range of each row's output
+    const bool range = rng != nullptr;   // column range of each row's output
 
     if (nrows > 0) {
         const int64_t e0 = rs[w][0], e1 = rs[w][64];
         // four entries per lane per step so that their gathers overlap
         for (int64_t eb = e0 + l; eb < e1; eb += 256) {
-            int64_t len[4], b0[4];
+            int64_t len[4];
+            int2 fl[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t e = eb + 64 * u;
                 const int k = e < e1 ? acol[e] : -1;
-                b0[u] = k >= 0 ? brpt[k] : 0;
-                len[u] = k >= 0 ? brpt[k + 1] - b0[u] : -1;
-            }
-            int first[4], last[4];
-            if (range) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    first[u] = len[u] > 0 ? bcol[b0[u]] : INT_MAX;
-                    last[u] = len[u] > 0 ? bcol[b0[u] + len[u] - 1] : -1;
-                }
+                len[u] = k >= 0 ? brpt[k + 1] - brpt[k] : -1;
+                if (range) fl[u] = k >= 0 ? bfl[k] : make_int2(INT_MAX, -1);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -88,8 +80,8 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
                 atomicAdd(&acc[w][lo], (unsigned long long)len[u]);
                 atomicMax(&bmx[w][lo], (unsigned)(len[u] > 0xffffffffll ? 0xffffffffll : len[u]));
                 if (range && len[u] > 0) {
-                    atomicMin(&clo[w][lo], first[u]);
-                    atomicMax(&chi[w][lo], last[u]);
+                    atomicMin(&clo[w][lo], fl[u].x);
+                    atomicMax(&chi[w][lo], fl[u].y);
                 }
             }
         }
@@ -103,10 +95,7 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
         nprod[i] = (int64_t)v;
         if (f_alen) f_alen[i] = (int32_t)(rs[w][l + 1] - rs[w][l]);
         if (f_bmax) f_bmax[i] = (int32_t)bmx[w][l];
-        if (range) {
-            f_lo[i] = clo[w][l];
-            f_hi[i] = chi[w][l];
-        }
+        if (range) rng[i] = make_int2(clo[w][l], chi[w][l]);
     }
     const int b = valid ? bin_of((int64_t)v, bd) : -1;
     for (int j = 0; j < bd.nslots; ++j) {
@@ -303,11 +292,30 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds b
 // ---------------------------------------------------------------------------
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
                         const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s,
-                        int32_t *f_lo, int32_t *f_hi) {
+                        const int2 *bfl, int2 *rng) {
     if (A.rows == 0) return hipSuccess;
     const int64_t grid = (A.rows + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)grid), dim3(256), 0, s, A.rows, A.rpt, A.col, B.rpt,
-                       nprod, bd, parts, f_alen, f_bmax, B.col, f_lo, f_hi);
+                       nprod, bd, parts, f_alen, f_bmax, bfl, bfl ? rng : nullptr);
+    return hipGetLastError();
+}
+
+// First and last column of every row of B, so that the setup step gets a
+// row's output column range with one extra load per A entry, issued with
+// the B row bounds it already loads.
+__global__ __launch_bounds__(256) void k_brange(int64_t K, const int64_t *__restrict__ brpt,
+                                                const int32_t *__restrict__ bcol,
+                                                int2 *__restrict__ bfl) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    const int64_t b0 = brpt[k], b1 = brpt[k + 1];
+    bfl[k] = b1 > b0 ? make_int2(bcol[b0], bcol[b1 - 1]) : make_int2(INT_MAX, -1);
+}
+
+hipError_t launch_brange(const DevCSR &B, int2 *bfl, hipStream_t s) {
+    if (B.rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_brange, dim3((unsigned)((B.rows + 255) / 256)), dim3(256), 0, s, B.rows,
+                       B.rpt, B.col, bfl);
     return hipGetLastError();
 }
 

@@ -272,7 +272,8 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
 
 // ---------------------------------------------------------------------------
 // Training: gradient of the mean squared error (sum over rows of
-// (y - t)^2 / n) for GR rows per workgroup.
+// (y - t)^2 / n), or of the mean pinball loss of level tau, for GR rows per
+// workgroup.
 // ---------------------------------------------------------------------------
 constexpr int GR = 64;
 constexpr int LD = H + 1;   // padded LDS row stride
@@ -280,7 +281,8 @@ constexpr int LD = H + 1;   // padded LDS row stride
 __global__ __launch_bounds__(256) void k_mlp_grad_part(const uint16_t *__restrict__ P,
                                                        const float *__restrict__ X,
                                                        const float *__restrict__ Tg, int64_t n,
-                                                       float two_over_n, float *__restrict__ part) {
+                                                       float inv_n, float tau,
+                                                       float *__restrict__ part) {
     __shared__ float sW1[H * 3], sb1[H], sW2[H * LD], sb2[H], sW3[H];
     __shared__ float sX[GR][3];
     __shared__ float sH1[GR][LD], sH2[GR][LD], sDZ2[GR][LD], sDZ1[GR][LD];
@@ -337,10 +339,18 @@ __global__ __launch_bounds__(256) void k_mlp_grad_part(const uint16_t *__restric
     yp += __shfl_xor(yp, 2);
     const float y = yp + sb3;
     const float diff = valid ? y - Tg[row] : 0.f;
-    const float dy = diff * two_over_n;
+    // squared error (tau == 0) or pinball loss of level tau on t - y
+    float dy, lrow;
+    if (tau > 0.f) {
+        dy = valid ? (diff < 0.f ? -tau : 1.f - tau) * inv_n : 0.f;
+        lrow = diff < 0.f ? -tau * diff : (1.f - tau) * diff;
+    } else {
+        dy = 2.f * diff * inv_n;
+        lrow = diff * diff;
+    }
     if (q == 0) {
         sDY[r] = dy;
-        sL[r] = diff * diff;
+        sL[r] = lrow;
     }
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
@@ -451,12 +461,12 @@ hipError_t launch_mlp_forward(const uint16_t *P, const float *X, int64_t n, floa
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const uint16_t *P, const float *X, const float *T, int64_t n, float *part,
-                           float *grad, float *loss, hipStream_t s) {
+hipError_t launch_mlp_grad(const uint16_t *P, const float *X, const float *T, int64_t n, float tau,
+                           float *part, float *grad, float *loss, hipStream_t s) {
     if (n <= 0) return hipErrorInvalidValue;
     const int64_t nblk = (n + GR - 1) / GR;
     hipLaunchKernelGGL(k_mlp_grad_part, dim3((unsigned)nblk), dim3(256), 0, s, P, X, T, n,
-                       (float)(2.0 / (double)n), part);
+                       (float)(1.0 / (double)n), tau, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, part,

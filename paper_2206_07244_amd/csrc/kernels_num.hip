@@ -326,8 +326,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    Counters *__restrict__ ctr, Learn L, const int32_t *__restrict__ rlo,
-    const int32_t *__restrict__ rhi) {
+    Counters *__restrict__ ctr, Learn L, const int2 *__restrict__ rng) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;
@@ -360,14 +359,17 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
     // A row whose output columns span at most T positions accumulates into a
     // dense array of that range (values) plus a bitmap (occupancy): no
     // probing, and the rank of a column is a popcount.
-    int64_t row = 0;
+    int64_t row = 0, a0 = 0, a1 = 0;
     bool dn = false;
     int lo = 0, dspan = 0;
     if (active) {
         row = src.row(idx);
-        if (rlo) {
-            lo = rlo[row];
-            const int64_t sp = (int64_t)rhi[row] - lo + 1;
+        a0 = arpt[row];   // issued together with the range load
+        a1 = arpt[row + 1];
+        if (rng) {
+            const int2 r = rng[row];
+            lo = r.x;
+            const int64_t sp = (int64_t)r.y - lo + 1;
             if (sp <= T) {
                 dn = true;
                 dspan = sp > 0 ? (int)sp : 0;
@@ -414,8 +416,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
                     atomicAdd(&tv[o], v);
                 }
             };
-            row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, NW, acc,
-                               [] { return false; });
+            row_products<true>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, acc, [] { return false; });
         }
         team_sync<WT>();
         // exclusive popcount prefix per bitmap word, after the words
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
             if constexpr (LRN) return *(volatile int *)&s_cnt[team] > THR;
             else return false;
         };
-        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
+        row_products<true>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
     }
     team_sync<WT>();
     if constexpr (LRN) {
@@ -878,11 +879,11 @@ static hipError_t go_row(const NumArgs &a, hipStream_t s) {
     if (a.lrn.mode == 1)
         hipLaunchKernelGGL((k_num_row<W, T, true>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
                            a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                           a.cval, a.ctr, a.lrn, a.rlo, a.rhi);
+                           a.cval, a.ctr, a.lrn, a.rng);
     else
         hipLaunchKernelGGL((k_num_row<W, T, false>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
                            a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                           a.cval, a.ctr, a.lrn, a.rlo, a.rhi);
+                           a.cval, a.ctr, a.lrn, a.rng);
     return hipGetLastError();
 }
 

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list,
-    const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi) {
+    const int2 *__restrict__ rng) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;  // waves per team
@@ -129,24 +129,36 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     for (int64_t b0 = (int64_t)blockIdx.x * R; b0 < src.nrows; b0 += stride) {
         const int64_t idx = b0 + team;
         const bool active = idx < src.nrows;
-        // A row whose output columns span at most 32 T positions, with no
-        // more bitmap words than twice its products, is counted in a bitmap
-        // of that range (an atomic OR per product, a popcount at the end)
-        // instead of the hash table: same count, no probing.
-        int64_t row = 0;
+        // A row whose output columns span a range that fits a bitmap of at
+        // most TP words (TP = the largest power of two <= T), with no more
+        // words than twice its products, is counted in that bitmap (an atomic
+        // OR per product, a popcount at the end) instead of the hash table:
+        // same count, no probing.  Column offset o sets bit o >> lg of word
+        // o & (nw - 1), so neighbouring columns land in different words
+        // (different banks, no serialised ORs on one word).
+        constexpr int TP = 1 << (31 - __builtin_clz(T));
+        int64_t row = 0, a0 = 0, a1 = 0;
         bool bm = false;
-        int lo = 0, nwords = 0;
+        int lo = 0, nwords = 0, lgw = 0;
         uint32_t span = 0;
         if (active) {
             row = src.row(idx);
-            if (rlo) {
-                lo = rlo[row];
-                const int64_t sp = (int64_t)rhi[row] - lo + 1;
-                const int64_t w = sp > 0 ? (sp + 31) >> 5 : 0;
-                if (sp <= 32ll * T && w <= 2 * nnz[row]) {
-                    bm = true;
-                    nwords = (int)w;
-                    span = sp > 0 ? (uint32_t)sp : 0u;
+            a0 = arpt[row];   // issued together with the range and n_prod loads
+            a1 = arpt[row + 1];
+            if (rng) {
+                const int2 r = rng[row];
+                const int64_t np = nnz[row];
+                lo = r.x;
+                const int64_t sp = (int64_t)r.y - lo + 1;
+                if (sp <= 32ll * TP) {
+                    int nw = 1;
+                    while (32ll * nw < sp) nw <<= 1;
+                    if (nw <= 2 * np || sp <= 0) {
+                        bm = true;
+                        nwords = sp > 0 ? nw : 0;
+                        span = sp > 0 ? (uint32_t)sp : 0u;
+                        lgw = 31 - __builtin_clz((unsigned)nw);
+                    }
                 }
             }
         }
@@ -161,12 +173,13 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
 
         int cnt = 0;
         if (active && bm) {
+            const uint32_t wmask = (uint32_t)nwords - 1u;
             auto set = [&](bool ok, int key) {
                 const uint32_t o = (uint32_t)(key - lo);
-                if (ok && o < span) atomicOr((unsigned int *)&tb[o >> 5], 1u << (o & 31));
+                if (ok && o < span) atomicOr((unsigned int *)&tb[o & wmask], 1u << (o >> lgw));
             };
-            row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6,
-                                NW, set, [] { return false; });
+            row_products<false>(a0, a1, acol, nullptr, brpt, bcol, nullptr, t >> 6, NW, set,
+                                [] { return false; });
         } else if (active) {
             auto ins = [&](bool ok, int key) {
                 const int nw = sym_insert_wave(tb, (uint32_t)T, ok, key, &ctr->error);
@@ -184,8 +197,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
                 if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
                 else return false;
             };
-            row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6,
-                                NW, ins, stop);
+            row_products<false>(a0, a1, acol, nullptr, brpt, bcol, nullptr, t >> 6, NW, ins, stop);
         }
         if (bm) {   // uniform over the team
             team_sync<WT>();
@@ -268,11 +280,11 @@ static hipError_t go_row(const SymArgs &a, hipStream_t s) {
     if (a.grid > 0)
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, true>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list, a.rlo, a.rhi);
+                           a.fail_list, a.rng);
     else
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, false>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list, a.rlo, a.rhi);
+                           a.fail_list, a.rng);
     return hipGetLastError();
 }
 

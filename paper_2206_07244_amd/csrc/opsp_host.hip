@@ -43,7 +43,7 @@ struct opsp_plan {
     bool check = false;
     int64_t fixed_grid = 0;             // > 0: every bin kernel runs persistently with this grid
     Counters *ctr = nullptr;            // device counters (numeric step), owned
-    int32_t *range = nullptr;           // output column range per row: lo[M], hi[M] (owned)
+    int2 *range = nullptr;              // output column range (lo, hi) per row (owned)
     opsp_stats stats = {};
 };
 
@@ -249,12 +249,14 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     const int64_t nblk = (M + 255) / 256;
     CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M));
     int32_t *bins = (int32_t *)p;
-    // output column range per row (narrow rows avoid the hash tables)
-    int32_t *rlo = nullptr, *rhi = nullptr;
+    // output column range per row (narrow rows avoid the hash tables), from
+    // the first and last column of every row of B
+    int2 *rng = nullptr, *bfl = nullptr;
     if (!(cfg && cfg->version >= 2 && cfg->hash_all_rows)) {
-        CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 2));
-        rlo = (int32_t *)p;
-        rhi = rlo + M;
+        CHK(ar.alloc(&p, sizeof(int2) * (size_t)M));
+        rng = (int2 *)p;
+        CHK(ar.alloc(&p, sizeof(int2) * (size_t)(B->rows > 0 ? B->rows : 1)));
+        bfl = (int2 *)p;
     }
     CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
     BlockParts parts;
@@ -268,7 +270,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 
     // 1 setup + first symbolic binning pass
     tm.mark();
-    CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s, rlo, rhi));
+    if (bfl) CHK(launch_brange(dB, bfl, s));
+    CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s, bfl, rng));
     CHK(launch_finalize(M, bs.nslots, parts, ctrS, nullptr, false, s));
     Counters hS;
     CHK(read_counters(&hS, ctrS, 1, s));
@@ -294,8 +297,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.B = dB;
     sa.nnz = crpt;
     sa.ctr = ctrS;
-    sa.rlo = rlo;
-    sa.rhi = rhi;
+    sa.rng = rng;
     int32_t *fail_list = nullptr;
     const int64_t big = ssz[7] + ssz[SYM_GLOBAL_BIN];
     int *slab = nullptr;
@@ -376,8 +378,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     tm.mark();
     ar.keep(crpt);
     ar.keep(ctrS);
-    if (rlo) ar.keep(rlo);
-    plan->range = rlo;
+    if (rng) ar.keep(rng);
+    plan->range = rng;
     if (identity < 0) ar.keep(bins);
     plan->identity_bin = identity;
     plan->crpt = crpt;
@@ -402,8 +404,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     na.ccol = ccol;
     na.cval = cval;
     na.ctr = plan->ctr;
-    na.rlo = plan->range;
-    na.rhi = plan->range ? plan->range + plan->M : nullptr;
+    na.rng = plan->range;
     const int gb = NUM_GLOBAL_BIN;
     bool first = true;
     void *pk = nullptr, *pv = nullptr;

@@ -38,14 +38,16 @@ struct BlockParts {
     unsigned long long *mx;      // [nblk] max row value
 };
 
+// First and last column of every row of B (INT_MAX / -1 for empty rows).
+hipError_t launch_brange(const DevCSR &B, int2 *bfl, hipStream_t s);
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
 // per-block bin counts / totals / maxima into `parts`; optional features
-// (a_len, b_max) and the column range [f_lo, f_hi] of each row's output (the
-// smallest first and largest last column of the B rows it references;
-// INT_MAX / -1 for rows without products).
+// (a_len, b_max) and, given B's row bounds `bfl`, the column range
+// (lo, hi) of each row's output (the smallest first and largest last column
+// of the B rows it references; INT_MAX / -1 for rows without products).
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
                         const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s,
-                        int32_t *f_lo = nullptr, int32_t *f_hi = nullptr);
+                        const int2 *bfl = nullptr, int2 *rng = nullptr);
 // First binning pass over existing row values (numeric step).
 hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, const BlockParts &parts,
                        hipStream_t s);
@@ -72,8 +74,8 @@ struct SymArgs {
     int *slab;               // global tables (bin 8)
     int64_t slab_entries;
     int64_t grid;            // fixed grid (persistent launch); 0 = one team per row
-    const int32_t *rlo;      // optional column range of each row (setup step): rows
-    const int32_t *rhi;      // with a narrow range are counted with a bitmap
+    const int2 *rng;         // optional column range of each row (setup step): rows
+                             // with a narrow range are counted with a bitmap
 };
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
 
@@ -90,8 +92,8 @@ struct NumArgs {
     int64_t slab_entries;
     int64_t grid;
     Learn lrn;               // one-phase step (lrn.mode > 0); crpt unused then
-    const int32_t *rlo;      // optional column range of each row (setup step): rows
-    const int32_t *rhi;      // with a narrow range accumulate densely (bins 1-6)
+    const int2 *rng;         // optional column range of each row (setup step): rows
+                             // with a narrow range accumulate densely (bins 1-6)
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 
@@ -108,9 +110,10 @@ constexpr int MLP_NPARAM = 4481;
 hipError_t launch_mlp_features(int64_t M, const int32_t *alen, const int64_t *nprod,
                                const int32_t *bmax, float *X, hipStream_t s);
 hipError_t launch_mlp_forward(const uint16_t *P, const float *X, int64_t n, float *y, hipStream_t s);
-// Gradient of the mean squared error over n rows; `part` holds
-// ceil(n / 64) * (MLP_NPARAM + 1) floats.
-hipError_t launch_mlp_grad(const uint16_t *P, const float *X, const float *T, int64_t n,
+// Gradient of the mean squared error (tau == 0) or of the mean pinball
+// loss of level tau over n rows; `part` holds ceil(n / 64) * (MLP_NPARAM + 1)
+// floats.
+hipError_t launch_mlp_grad(const uint16_t *P, const float *X, const float *T, int64_t n, float tau,
                            float *part, float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *g, float lr, float b1,
                            float b2, float eps, float c1, float c2, uint16_t *P, hipStream_t s);

@@ -96,9 +96,16 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     int64_t *nz = (int64_t *)p;
     CHK(ar.alloc(&p, sizeof(int64_t) * (size_t)M));
     int64_t *loc = (int64_t *)p;
-    CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 6));
+    CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 4));
     int32_t *alen = (int32_t *)p, *bmax = alen + M, *bins = alen + 2 * M, *retry = alen + 3 * M;
-    int32_t *rlo = alen + 4 * M, *rhi = alen + 5 * M;   // output column range per row
+    const bool ranges = !(cfg && cfg->version >= 2 && cfg->hash_all_rows);
+    int2 *rng = nullptr, *bfl = nullptr;   // output column range per row, B's row bounds
+    if (ranges) {
+        CHK(ar.alloc(&p, sizeof(int2) * (size_t)M));
+        rng = (int2 *)p;
+        CHK(ar.alloc(&p, sizeof(int2) * (size_t)(B->rows > 0 ? B->rows : 1)));
+        bfl = (int2 *)p;
+    }
     CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
     BlockParts parts;
     parts.tot = (unsigned long long *)p;
@@ -115,7 +122,8 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     // 1-2 setup, capacities, numeric bins by capacity, slot offsets
     tm.mark();
     CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnCtr), s));
-    CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s, rlo, rhi));
+    if (bfl) CHK(launch_brange(dB, bfl, s));
+    CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s, bfl, rng));
     CapArgs ca;
     memset(&ca, 0, sizeof(ca));
     ca.kind = pr->kind;
@@ -159,9 +167,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     na.ccol = tcol;
     na.cval = tval;
     na.ctr = &dc->num;
-    const bool ranges = !(cfg && cfg->version >= 2 && cfg->hash_all_rows);
-    na.rlo = ranges ? rlo : nullptr;
-    na.rhi = ranges ? rhi : nullptr;
+    na.rng = rng;
     na.lrn.mode = 1;
     na.lrn.off = off;
     na.lrn.nprod = np;
@@ -336,8 +342,9 @@ opsp_status opsp_mlp_forward(const uint16_t *params, const float *X, int64_t n, 
 }
 
 opsp_status opsp_mlp_grad(const uint16_t *params, const float *X, const float *target, int64_t n,
-                          float *grad, float *loss, void *stream) {
+                          float tau, float *grad, float *loss, void *stream) {
     if (n < 1 || !params || !X || !target || !grad) return OPSP_ERR_INVALID;
+    if (!(tau >= 0.f && tau < 1.f)) return OPSP_ERR_INVALID;
     int dev = 0, cus = 0;
     opsp_status st = init_device(&dev, &cus);
     if (st != OPSP_OK) return st;
@@ -346,7 +353,7 @@ opsp_status opsp_mlp_grad(const uint16_t *params, const float *X, const float *t
     void *p = nullptr;
     const int64_t nblk = (n + 63) / 64;
     CHK(ar.alloc(&p, sizeof(float) * (size_t)(nblk * (MLP_NPARAM + 1))));
-    CHK(launch_mlp_grad(params, X, target, n, (float *)p, grad, loss, s));
+    CHK(launch_mlp_grad(params, X, target, n, tau, (float *)p, grad, loss, s));
     return OPSP_OK;
 }
 

@@ -102,7 +102,8 @@ def test_predictor_arguments_rejected_on_host():
     assert L.opsp_spgemm_learned(ctypes.byref(A), ctypes.byref(Bbad), ctypes.byref(C),
                                  ctypes.byref(p), None, None, None) == 2
     # training entry points
-    assert L.opsp_mlp_grad(1, 1, 1, 0, 1, None, None) == 1
+    assert L.opsp_mlp_grad(1, 1, 1, 0, 0.0, 1, None, None) == 1
+    assert L.opsp_mlp_grad(1, 1, 1, 5, 1.0, 1, None, None) == 1
     assert L.opsp_mlp_forward(None, 1, 5, 1, None) == 1
     assert L.opsp_mlp_adam(1, 1, 1, 1, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None) == 1
     assert L.opsp_mlp_adam(1, 1, 1, 1, 1, 1e-3, 1.0, 0.999, 1e-8, 1, None) == 1

@@ -100,7 +100,8 @@ def kink_free(th, X, rel=1e-3):
 
 
 @pytest.mark.parametrize("n,seed", [(1, 5), (64, 6), (100, 7), (2000, 8), (20000, 9)])
-def test_gradient_matches_reference(n, seed):
+@pytest.mark.parametrize("tau", [0.0, 0.9])
+def test_gradient_matches_reference(n, seed, tau):
     torch = _torch()
     ops = _ops()
     bits = params_bits(seed)
@@ -111,11 +112,13 @@ def test_gradient_matches_reference(n, seed):
     y0, _ = mlp.forward(th, X.astype(np.float64))
     r = np.random.default_rng(seed)
     t = (y0 + np.where(r.random(n) < 0.5, -1, 1) * (0.5 + r.random(n))).astype(np.float32)
-    g, loss = ops.mlp_grad(dev_params(bits), torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda())
+    g, loss = ops.mlp_grad(dev_params(bits), torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda(),
+                           tau=tau)
     g = g.cpu().numpy().astype(np.float64)
     loss = float(loss.cpu().numpy()[0])
-    lref, gref = mlp.grad(th, X.astype(np.float64), t.astype(np.float64))
-    _, gabs = mlp.grad(th, X.astype(np.float64), t.astype(np.float64), absolute=True)
+    tr = None if tau == 0.0 else float(np.float32(tau))
+    lref, gref = mlp.grad(th, X.astype(np.float64), t.astype(np.float64), tau=tr)
+    _, gabs = mlp.grad(th, X.astype(np.float64), t.astype(np.float64), absolute=True, tau=tr)
     tol = 400 * U32 * gabs + 1e-12 * np.max(gabs)
     bad = np.abs(g - gref) > tol
     assert not bad.any(), (np.nonzero(bad)[0][:10], np.max(np.abs(g - gref) / (gabs + 1e-300)))

@@ -164,3 +164,48 @@ def test_capacity_rules():
     cap = mlp.capacity(r.normal(4, 3, n), 0.1, alen, nprod, bmax, ncols=200)
     hi = np.minimum(nprod, 200)
     assert np.all((cap >= np.minimum(bmax, hi)) & (cap <= np.maximum(hi, nprod * (alen <= 1))))
+
+
+def test_pinball_gradient_matches_torch_and_differences():
+    """Pinball loss: gradient against torch autograd of the same loss in
+    float64, and against central differences at a point away from kinks."""
+    X, t = rand_batch(120, 31)
+    th = mlp.init(17) + np.random.default_rng(18).normal(0, 0.05, mlp.NPARAM)
+    y0, _ = mlp.forward(th, X, quant=False)
+    t = y0 + np.random.default_rng(19).choice([-1.0, 1.0], 120) * (0.3 + np.random.default_rng(20).random(120))
+    for tau in (0.5, 0.9):
+        net = torch_net(th)
+        y = net(torch.from_numpy(X))[:, 0]
+        r = torch.from_numpy(t) - y
+        L = torch.mean(torch.where(r > 0, tau * r, (tau - 1.0) * r))
+        L.backward()
+        lo, go = mlp.grad(th, X, t, quant=False, tau=tau)
+        gt = np.concatenate([net[0].weight.grad.numpy().ravel(), net[0].bias.grad.numpy(),
+                             net[2].weight.grad.numpy().ravel(), net[2].bias.grad.numpy(),
+                             net[4].weight.grad.numpy().ravel(), net[4].bias.grad.numpy()])
+        assert abs(lo - L.item()) <= 1e-12
+        np.testing.assert_allclose(go, gt, rtol=1e-10, atol=1e-13)
+        h = 1e-7
+        for i in (0, 5, 200, 1000, 4400, 4480):
+            tp, tm = th.copy(), th.copy()
+            tp[i] += h
+            tm[i] -= h
+            fd = (mlp.loss(tp, X, t, quant=False, tau=tau) - mlp.loss(tm, X, t, quant=False, tau=tau)) / (2 * h)
+            assert abs(fd - go[i]) <= 1e-5 * max(1.0, abs(go[i])), (tau, i, fd, go[i])
+
+
+def test_pinball_level_is_the_empirical_quantile():
+    """A constant model trained with the pinball loss of level tau settles at
+    the tau-quantile of the targets (the defining property of the loss)."""
+    r = np.random.default_rng(3)
+    tgt = r.exponential(2.0, 1001)
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    X = np.zeros((tgt.size, 3))
+    th = mlp.pack(p)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for step in range(1, 2001):
+        _, g = mlp.grad(th, X, tgt, quant=False, tau=0.9)
+        g[:-1] = 0.0                  # only the output bias moves
+        th, m, v = mlp.adam_step(th, m, v, g, step, lr=0.02)
+    assert abs(th[-1] - np.quantile(tgt, 0.9)) < 0.08
