@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
                                                BlockParts parts,
                                                int32_t *__restrict__ f_alen,
                                                int32_t *__restrict__ f_bmax,
-                                               const int2 *__restrict__ bfl,
+                                               const int4 *__restrict__ brec,
                                                int2 *__restrict__ rng) {
     __shared__ int64_t rs[4][65];
     __shared__ unsigned long long acc[4][64];
@@ -64,8 +64,13 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
             for (int u = 0; u < 4; ++u) {
                 const int64_t e = eb + 64 * u;
                 const int k = e < e1 ? acol[e] : -1;
-                len[u] = k >= 0 ? brpt[k + 1] - brpt[k] : -1;
-                if (range) fl[u] = k >= 0 ? bfl[k] : make_int2(INT_MAX, -1);
+                if (range) {   // one 16-byte record per B row: length, first, last column
+                    const int4 r = k >= 0 ? brec[k] : make_int4(-1, INT_MAX, -1, 0);
+                    len[u] = r.x;
+                    fl[u] = make_int2(r.y, r.z);
+                } else {
+                    len[u] = k >= 0 ? brpt[k + 1] - brpt[k] : -1;
+                }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -292,30 +297,31 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds b
 // ---------------------------------------------------------------------------
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
                         const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s,
-                        const int2 *bfl, int2 *rng) {
+                        const int4 *brec, int2 *rng) {
     if (A.rows == 0) return hipSuccess;
     const int64_t grid = (A.rows + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)grid), dim3(256), 0, s, A.rows, A.rpt, A.col, B.rpt,
-                       nprod, bd, parts, f_alen, f_bmax, bfl, bfl ? rng : nullptr);
+                       nprod, bd, parts, f_alen, f_bmax, brec, brec ? rng : nullptr);
     return hipGetLastError();
 }
 
-// First and last column of every row of B, so that the setup step gets a
-// row's output column range with one extra load per A entry, issued with
-// the B row bounds it already loads.
+// Length, first and last column of every row of B in one 16-byte record,
+// so that the setup step reads one record per A entry (instead of two row
+// bounds) and also gets each row's output column range.
 __global__ __launch_bounds__(256) void k_brange(int64_t K, const int64_t *__restrict__ brpt,
                                                 const int32_t *__restrict__ bcol,
-                                                int2 *__restrict__ bfl) {
+                                                int4 *__restrict__ brec) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= K) return;
     const int64_t b0 = brpt[k], b1 = brpt[k + 1];
-    bfl[k] = b1 > b0 ? make_int2(bcol[b0], bcol[b1 - 1]) : make_int2(INT_MAX, -1);
+    brec[k] = b1 > b0 ? make_int4((int)(b1 - b0), bcol[b0], bcol[b1 - 1], 0)
+                      : make_int4(0, INT_MAX, -1, 0);
 }
 
-hipError_t launch_brange(const DevCSR &B, int2 *bfl, hipStream_t s) {
+hipError_t launch_brange(const DevCSR &B, int4 *brec, hipStream_t s) {
     if (B.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_brange, dim3((unsigned)((B.rows + 255) / 256)), dim3(256), 0, s, B.rows,
-                       B.rpt, B.col, bfl);
+                       B.rpt, B.col, brec);
     return hipGetLastError();
 }
 

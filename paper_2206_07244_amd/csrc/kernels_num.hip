@@ -621,7 +621,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
         }
     }
     };
-    do_row((int64_t)blockIdx.x * R + team);
+    do_row(xcd_block(blockIdx.x, gridDim.x) * R + team);
 }
 
 // ---------------------------------------------------------------------------
@@ -773,6 +773,149 @@ __global__ __launch_bounds__(1024) void k_num_global(
         if (t == 0 && run != n) atomicAdd(&ctr->error, 1u);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// bin 7, rows with a known column range: bucketed dense accumulation.
+// A long row's products are partitioned by 16384-column chunk of its output
+// range into a per-workgroup staging buffer (a counting pass, a scan over
+// the chunks, a scatter pass), then each chunk is accumulated densely in
+// LDS (an FP64 add and an occupancy bit per product) and emitted in column
+// order through a popcount prefix.  Global traffic is sequential (the
+// staging writes and reads) instead of one random global atomic per product.
+// The dense array and the bitmap are re-zeroed only where written.
+// ---------------------------------------------------------------------------
+constexpr int BK_LG = 14;
+constexpr int BK_CW = 1 << BK_LG;   // columns per chunk
+constexpr int BK_NB = 1024;         // chunks per row at most
+
+__global__ __launch_bounds__(1024) void k_num_bucket(
+    RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
+    const double *__restrict__ aval, const int64_t *__restrict__ brpt,
+    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
+    const int2 *__restrict__ rng, int *stage_keys, double *stage_vals, int64_t stage_cap,
+    Counters *__restrict__ ctr) {
+    __shared__ double dense[BK_CW];
+    __shared__ unsigned int bits[BK_CW / 32];
+    __shared__ unsigned int cnt[BK_NB];
+    __shared__ unsigned int off[BK_NB + 1];
+    __shared__ unsigned int red[16];
+
+    src.resolve();
+    const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+    int *sk = stage_keys + (int64_t)blockIdx.x * stage_cap;
+    double *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
+    for (int i = t; i < BK_CW; i += 1024) dense[i] = 0.0;
+    for (int i = t; i < BK_CW / 32; i += 1024) bits[i] = 0u;
+    __syncthreads();
+
+    for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
+        const int64_t row = src.row(r);
+        const int64_t a0 = arpt[row], a1 = arpt[row + 1];
+        const int2 rg = rng[row];
+        const int64_t base = crpt[row];
+        const int64_t n = crpt[row + 1] - base;
+        const int lo = rg.x;
+        const int64_t span = (int64_t)rg.y - lo + 1;
+        if (span <= 0) continue;   // no products (uniform; no barrier pending)
+        const int nb = (int)((span + BK_CW - 1) >> BK_LG);
+        for (int b = t; b < nb; b += 1024) cnt[b] = 0u;
+        __syncthreads();
+        // 1. products per chunk
+        row_products<false>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
+                            [&](bool ok, int key) {
+                                const uint32_t o = (uint32_t)(key - lo);
+                                if (ok && o < (uint64_t)span) atomicAdd(&cnt[o >> BK_LG], 1u);
+                            },
+                            [] { return false; });
+        __syncthreads();
+        // 2. chunk offsets (exclusive scan, nb <= 1024: one chunk per thread)
+        {
+            const unsigned int x = t < nb ? cnt[t] : 0u;
+            const unsigned int incl = wave_incl_scan(x);
+            if (l == 63) red[wv] = incl;
+            __syncthreads();
+            unsigned int pre = 0, tot = 0;
+            for (int i = 0; i < 16; ++i) {
+                if (i < wv) pre += red[i];
+                tot += red[i];
+            }
+            if (t < nb) {
+                off[t] = pre + incl - x;
+                cnt[t] = pre + incl - x;   // running fill position of the chunk
+            }
+            if (t == 0) off[nb] = tot;
+            __syncthreads();
+        }
+        // 3. scatter the products into their chunks
+        row_products<true>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
+                           [&](bool ok, int key, double v) {
+                               const uint32_t o = (uint32_t)(key - lo);
+                               if (ok && o < (uint64_t)span) {
+                                   const unsigned int p = atomicAdd(&cnt[o >> BK_LG], 1u);
+                                   sk[p] = key;
+                                   sv[p] = v;
+                               }
+                           },
+                           [] { return false; });
+        __threadfence();
+        __syncthreads();
+        // 4. per chunk: dense accumulation, popcount prefix, emission
+        int64_t run = 0;
+        for (int b = 0; b < nb; ++b) {
+            const unsigned int p0 = off[b], p1 = off[b + 1];
+            if (p0 == p1) continue;   // empty chunk (uniform)
+            const int c0 = lo + (b << BK_LG);
+            for (unsigned int p = p0 + t; p < p1; p += 1024) {
+                const int key = ld_coherent(&sk[p]);
+                const double v = ld_coherent(&sv[p]);
+                const uint32_t o = (uint32_t)(key - c0);
+                atomicAdd(&dense[o], v);
+                atomicOr(&bits[o >> 5], 1u << (o & 31));
+            }
+            __syncthreads();
+            // threads 0..511 own one bitmap word each
+            const unsigned int wd = t < BK_CW / 32 ? bits[t] : 0u;
+            const unsigned int c = __popc(wd);
+            const unsigned int incl = wave_incl_scan(c);
+            if (l == 63) red[wv] = incl;
+            __syncthreads();
+            unsigned int pre = 0, tot = 0;
+            for (int i = 0; i < 16; ++i) {
+                if (i < wv) pre += red[i];
+                tot += red[i];
+            }
+            if (wd) {
+                unsigned int m = wd;
+                int64_t k = run + pre + incl - c;
+                while (m) {
+                    const int bit = __ffs(m) - 1;
+                    m &= m - 1u;
+                    const int o = (t << 5) + bit;
+                    if (k < n) {
+                        ccol[base + k] = c0 + o;
+                        cval[base + k] = dense[o];
+                    }
+                    dense[o] = 0.0;
+                    ++k;
+                }
+                bits[t] = 0u;
+            }
+            run += tot;
+            __syncthreads();
+        }
+        if (t == 0 && run != n) atomicAdd(&ctr->error, 1u);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s) {
+    if (a.grid <= 0 || !a.rng) return hipSuccess;
+    hipLaunchKernelGGL(k_num_bucket, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt, a.A.col,
+                       a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng, a.slab_keys,
+                       a.slab_vals, a.slab_entries, a.ctr);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

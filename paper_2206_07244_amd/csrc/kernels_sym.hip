@@ -126,7 +126,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
     const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / W), t = threadIdx.x % W;
     int *tb = tab + team * T;
     const int64_t stride = PERSIST ? (int64_t)gridDim.x * R : src.nrows + R;
-    for (int64_t b0 = (int64_t)blockIdx.x * R; b0 < src.nrows; b0 += stride) {
+    for (int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * R; b0 < src.nrows; b0 += stride) {
         const int64_t idx = b0 + team;
         const bool active = idx < src.nrows;
         // A row whose output columns span a range that fits a bitmap of at

@@ -114,6 +114,17 @@ struct RowSrc {
     }
 };
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs of the
+// chip, each with its own L2.  This bijection on [0, n) gives XCD x the
+// contiguous logical blocks [x q + min(x, r), ...) (q = n / 8, r = n % 8),
+// so neighbouring rows, which read overlapping rows of B, share an L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t n) {
+    const int64_t q = n / NUM_XCD, r = n % NUM_XCD;
+    const int64_t x = bid % NUM_XCD, local = bid / NUM_XCD;
+    return x * q + (x < r ? x : r) + local;
+}
+
 // Wave helpers ---------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }

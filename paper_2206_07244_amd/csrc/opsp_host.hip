@@ -251,12 +251,13 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     int32_t *bins = (int32_t *)p;
     // output column range per row (narrow rows avoid the hash tables), from
     // the first and last column of every row of B
-    int2 *rng = nullptr, *bfl = nullptr;
+    int2 *rng = nullptr;
+    int4 *bfl = nullptr;
     if (!(cfg && cfg->version >= 2 && cfg->hash_all_rows)) {
         CHK(ar.alloc(&p, sizeof(int2) * (size_t)M));
         rng = (int2 *)p;
-        CHK(ar.alloc(&p, sizeof(int2) * (size_t)(B->rows > 0 ? B->rows : 1)));
-        bfl = (int2 *)p;
+        CHK(ar.alloc(&p, sizeof(int4) * (size_t)(B->rows > 0 ? B->rows : 1)));
+        bfl = (int4 *)p;
     }
     CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
     BlockParts parts;
@@ -415,6 +416,24 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
                            (plan->identity_bin == b) ? 0 : plan->num_off[b], rows);
         na.grid = 0;
         if (plan->fixed_grid > 0 && b == 0) na.grid = plan->fixed_grid < rows ? plan->fixed_grid : rows;
+        if (b == gb && plan->range && plan->N <= BUCKET_MAX_COLS) {
+            // bucketed dense accumulation: staging for the largest n_prod per
+            // workgroup, at most 32 GB of staging in total
+            const int64_t cap = plan->stats.max_row_nprod > 1 ? plan->stats.max_row_nprod : 1;
+            int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
+            const int64_t budget = (int64_t)32 << 30;
+            const int64_t fit = budget / (cap * 12);
+            if (grid > fit) grid = fit > 1 ? fit : 1;
+            CHK(ar.alloc(&pk, sizeof(int) * (size_t)(cap * grid)));
+            CHK(ar.alloc(&pv, sizeof(double) * (size_t)(cap * grid)));
+            na.slab_keys = (int *)pk;
+            na.slab_vals = (double *)pv;
+            na.slab_entries = cap;
+            na.grid = grid;
+            CHK(launch_numeric_bucket(na, s));
+            first = false;
+            continue;
+        }
         if (b == gb) {
             const int64_t entries = pow2_host(2 * plan->max_nnz > 64 ? 2 * plan->max_nnz : 64);
             const int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;

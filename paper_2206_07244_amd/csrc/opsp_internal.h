@@ -38,16 +38,17 @@ struct BlockParts {
     unsigned long long *mx;      // [nblk] max row value
 };
 
-// First and last column of every row of B (INT_MAX / -1 for empty rows).
-hipError_t launch_brange(const DevCSR &B, int2 *bfl, hipStream_t s);
+// Length, first and last column of every row of B (0, INT_MAX, -1 for
+// empty rows) as int4 records.
+hipError_t launch_brange(const DevCSR &B, int4 *brec, hipStream_t s);
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
 // per-block bin counts / totals / maxima into `parts`; optional features
-// (a_len, b_max) and, given B's row bounds `bfl`, the column range
+// (a_len, b_max) and, given B's row records `brec`, the column range
 // (lo, hi) of each row's output (the smallest first and largest last column
 // of the B rows it references; INT_MAX / -1 for rows without products).
 hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const Bounds &bd,
                         const BlockParts &parts, int32_t *f_alen, int32_t *f_bmax, hipStream_t s,
-                        const int2 *bfl = nullptr, int2 *rng = nullptr);
+                        const int4 *brec = nullptr, int2 *rng = nullptr);
 // First binning pass over existing row values (numeric step).
 hipError_t launch_hist(int64_t M, const int64_t *v, const Bounds &bd, const BlockParts &parts,
                        hipStream_t s);
@@ -96,6 +97,12 @@ struct NumArgs {
                              // with a narrow range accumulate densely (bins 1-6)
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
+// Bin 7 by bucketed dense accumulation (rows with a column range in `rng`;
+// the matrix must have at most BUCKET_MAX_COLS columns).  slab_keys /
+// slab_vals / slab_entries are the staging buffers: slab_entries >= the
+// largest n_prod of the bin's rows, one per workgroup of the grid.
+constexpr int64_t BUCKET_MAX_COLS = (int64_t)1 << 24;
+hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s);
 
 // Copy the rows of the one-phase step from the temporary arrays (entries
 // [0, tsize)) and the second arena (indices tsize.. in `loc`) into C.

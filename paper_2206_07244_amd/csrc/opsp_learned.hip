@@ -99,12 +99,13 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 4));
     int32_t *alen = (int32_t *)p, *bmax = alen + M, *bins = alen + 2 * M, *retry = alen + 3 * M;
     const bool ranges = !(cfg && cfg->version >= 2 && cfg->hash_all_rows);
-    int2 *rng = nullptr, *bfl = nullptr;   // output column range per row, B's row bounds
+    int2 *rng = nullptr;
+    int4 *bfl = nullptr;   // output column range per row, B's row bounds
     if (ranges) {
         CHK(ar.alloc(&p, sizeof(int2) * (size_t)M));
         rng = (int2 *)p;
-        CHK(ar.alloc(&p, sizeof(int2) * (size_t)(B->rows > 0 ? B->rows : 1)));
-        bfl = (int2 *)p;
+        CHK(ar.alloc(&p, sizeof(int4) * (size_t)(B->rows > 0 ? B->rows : 1)));
+        bfl = (int4 *)p;
     }
     CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
     BlockParts parts;
