@@ -54,7 +54,45 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     __syncthreads();
     const bool range = rng != nullptr;   // column range of each row's output
 
-    if (nrows > 0) {
+    // Short rows (the wave's longest at most 64 entries): every lane walks
+    // its own row, accumulating in registers; no per-entry row search and no
+    // LDS atomics.  Otherwise the wave walks the flat range of its rows'
+    // entries, so that one long row does not serialise a single lane.
+    const int64_t my_len = (nrows > 0 && l < nrows) ? rs[w][l + 1] - rs[w][l] : 0;
+    const bool lane_rows = nrows > 0 && wave_max(my_len) <= 64;
+    if (lane_rows) {
+        unsigned long long a = 0;
+        unsigned int bm = 0;
+        int mn = INT_MAX, mx = -1;
+        const int64_t p0 = l < nrows ? rs[w][l] : 0;
+        for (int64_t p = p0; p < p0 + my_len; p += 4) {
+            int k[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) k[u] = p + u < p0 + my_len ? acol[p + u] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k[u] < 0) continue;
+                int64_t len;
+                if (range) {
+                    const int4 r = brec[k[u]];
+                    len = r.x;
+                    if (len > 0) {
+                        mn = r.y < mn ? r.y : mn;
+                        mx = r.z > mx ? r.z : mx;
+                    }
+                } else {
+                    len = brpt[k[u] + 1] - brpt[k[u]];
+                }
+                a += (unsigned long long)len;
+                const unsigned int lc = (unsigned)(len > 0xffffffffll ? 0xffffffffll : len);
+                bm = lc > bm ? lc : bm;
+            }
+        }
+        acc[w][l] = a;
+        bmx[w][l] = bm;
+        clo[w][l] = mn;
+        chi[w][l] = mx;
+    } else if (nrows > 0) {
         const int64_t e0 = rs[w][0], e1 = rs[w][64];
         // four entries per lane per step so that their gathers overlap
         for (int64_t eb = e0 + l; eb < e1; eb += 256) {

@@ -789,18 +789,20 @@ constexpr int BK_LG = 14;
 constexpr int BK_CW = 1 << BK_LG;   // columns per chunk
 constexpr int BK_NB = 1024;         // chunks per row at most
 
+template <bool LRN>
 __global__ __launch_bounds__(1024) void k_num_bucket(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
     const int2 *__restrict__ rng, int *stage_keys, double *stage_vals, int64_t stage_cap,
-    Counters *__restrict__ ctr) {
+    Counters *__restrict__ ctr, Learn L) {
     __shared__ double dense[BK_CW];
     __shared__ unsigned int bits[BK_CW / 32];
     __shared__ unsigned int cnt[BK_NB];
     __shared__ unsigned int off[BK_NB + 1];
     __shared__ unsigned int red[16];
+    __shared__ long long s_base;
 
     src.resolve();
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
@@ -814,11 +816,17 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         const int64_t row = src.row(r);
         const int64_t a0 = arpt[row], a1 = arpt[row + 1];
         const int2 rg = rng[row];
-        const int64_t base = crpt[row];
-        const int64_t n = crpt[row + 1] - base;
+        int64_t base = 0, n = 0;
+        if constexpr (!LRN) {
+            base = crpt[row];
+            n = crpt[row + 1] - base;
+        }
         const int lo = rg.x;
         const int64_t span = (int64_t)rg.y - lo + 1;
-        if (span <= 0) continue;   // no products (uniform; no barrier pending)
+        if (span <= 0) {   // no products (uniform; no barrier pending)
+            if (LRN && t == 0) lrn_done(L, row, 0, L.off ? L.off[row] : 0);
+            continue;
+        }
         const int nb = (int)((span + BK_CW - 1) >> BK_LG);
         for (int b = t; b < nb; b += 1024) cnt[b] = 0u;
         __syncthreads();
@@ -861,6 +869,38 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
                            [] { return false; });
         __threadfence();
         __syncthreads();
+        if constexpr (LRN) {
+            // the row's size decides where it goes: count the distinct
+            // columns chunk by chunk first
+            unsigned int tot_n = 0;
+            for (int b = 0; b < nb; ++b) {
+                const unsigned int p0 = off[b], p1 = off[b + 1];
+                if (p0 == p1) continue;   // uniform
+                const int c0 = lo + (b << BK_LG);
+                for (unsigned int p = p0 + t; p < p1; p += 1024) {
+                    const uint32_t o = (uint32_t)(ld_coherent(&sk[p]) - c0);
+                    atomicOr(&bits[o >> 5], 1u << (o & 31));
+                }
+                __syncthreads();
+                unsigned int c = t < BK_CW / 32 ? __popc(bits[t]) : 0u;
+                if (t < BK_CW / 32) bits[t] = 0u;
+                c = wave_sum(c);
+                if (l == 0) red[wv] = c;
+                __syncthreads();
+                for (int i = 0; i < 16; ++i) tot_n += red[i];
+                __syncthreads();
+            }
+            n = tot_n;
+            if (t == 0) {
+                const int64_t bb = lrn_place(L, row, n);
+                if (bb < 0) lrn_retry(L, row, false);
+                else lrn_done(L, row, n, bb);
+                s_base = bb;
+            }
+            __syncthreads();
+            base = (int64_t)s_base;
+            if (base < 0) continue;   // uniform; no barrier pending
+        }
         // 4. per chunk: dense accumulation, popcount prefix, emission
         int64_t run = 0;
         for (int b = 0; b < nb; ++b) {
@@ -912,9 +952,14 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
 
 hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s) {
     if (a.grid <= 0 || !a.rng) return hipSuccess;
-    hipLaunchKernelGGL(k_num_bucket, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt, a.A.col,
-                       a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng, a.slab_keys,
-                       a.slab_vals, a.slab_entries, a.ctr);
+    if (a.lrn.mode > 0)
+        hipLaunchKernelGGL(k_num_bucket<true>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
+                           a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng,
+                           a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
+    else
+        hipLaunchKernelGGL(k_num_bucket<false>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
+                           a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng,
+                           a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
     return hipGetLastError();
 }
 

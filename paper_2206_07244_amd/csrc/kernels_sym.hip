@@ -130,10 +130,9 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
         const int64_t idx = b0 + team;
         const bool active = idx < src.nrows;
         // A row whose output columns span a range that fits a bitmap of at
-        // most TP words (TP = the largest power of two <= T), with no more
-        // words than twice its products, is counted in that bitmap (an atomic
-        // OR per product, a popcount at the end) instead of the hash table:
-        // same count, no probing.  Column offset o sets bit o >> lg of word
+        // most TP words (TP = the largest power of two <= T) is counted in
+        // that bitmap (an atomic OR per product, a popcount at the end)
+        // instead of the hash table: same count, no probing.  Column offset o sets bit o >> lg of word
         // o & (nw - 1), so neighbouring columns land in different words
         // (different banks, no serialised ORs on one word).
         constexpr int TP = 1 << (31 - __builtin_clz(T));
@@ -153,7 +152,10 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
                 if (sp <= 32ll * TP) {
                     int nw = 1;
                     while (32ll * nw < sp) nw <<= 1;
-                    if (nw <= 2 * np || sp <= 0) {
+                    // the largest bin counts by bitmap whenever it fits (no
+                    // abandoned rows); the others when the bitmap is small
+                    // against the row's products
+                    if ((ABORT ? nw <= 2 * np : 2 * nw <= np) || sp <= 0) {
                         bm = true;
                         nwords = sp > 0 ? nw : 0;
                         span = sp > 0 ? (uint32_t)sp : 0u;

@@ -34,6 +34,16 @@ namespace {
 
 constexpr int64_t ARENA_MIN = 1 << 16;
 
+// Workgroups of the bucketed kernel: one per CU at most, staging (12 bytes
+// per product of the longest row, per workgroup) under 32 GB.
+int64_t bucket_grid(int64_t rows, int cus, int64_t max_nprod) {
+    int64_t g = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
+    const int64_t per = (max_nprod > 1 ? max_nprod : 1) * 12;
+    const int64_t fit = ((int64_t)32 << 30) / per;
+    if (g > fit) g = fit > 1 ? fit : 1;
+    return g;
+}
+
 struct LearnedCounters {
     Counters num;      // numeric bins by capacity; total = sum of capacities
     Counters scan;     // scan of the exact row sizes; total = nnz(C)
@@ -184,6 +194,21 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         if (nsz[b] == 0) continue;
         na.src = host_rows(bins, noff[b], nsz[b]);
         na.grid = 0;
+        if (b == NUM_GLOBAL_BIN && rng && N <= BUCKET_MAX_COLS) {
+            // long rows: bucketed dense accumulation (never overflows)
+            void *pk = nullptr, *pv = nullptr;
+            const int64_t grid = bucket_grid(nsz[b], cus, S.max_row_nprod);
+            const int64_t sc = S.max_row_nprod > 1 ? S.max_row_nprod : 1;
+            CHK(ar.alloc(&pk, sizeof(int) * (size_t)(sc * grid)));
+            CHK(ar.alloc(&pv, sizeof(double) * (size_t)(sc * grid)));
+            NumArgs ba = na;
+            ba.slab_keys = (int *)pk;
+            ba.slab_vals = (double *)pv;
+            ba.slab_entries = sc;
+            ba.grid = grid;
+            CHK(launch_numeric_bucket(ba, s));
+            continue;
+        }
         if (b == NUM_GLOBAL_BIN) {
             const int64_t entries = pow2_host(2 * cap_max > 8192 ? 2 * cap_max : 8192);
             const int64_t grid = nsz[b] < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? nsz[b]
@@ -219,20 +244,10 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         a2col = (int32_t *)p;
         CHK(ar.alloc(&p, sizeof(double) * (size_t)(ub > 0 ? ub : 1)));
         a2val = (double *)p;
-        const int64_t bmx = S.max_row_nprod < N ? S.max_row_nprod : N;
-        const int64_t entries = pow2_host(2 * bmx > 64 ? 2 * bmx : 64);
-        const int64_t grid = nretry < (int64_t)cus ? nretry : (int64_t)cus;
-        void *pk = nullptr, *pv = nullptr;
-        CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
-        CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));
         NumArgs ra = na;
         ra.ccol = a2col;
         ra.cval = a2val;
         ra.src = host_rows(retry, 0, nretry);
-        ra.slab_keys = (int *)pk;
-        ra.slab_vals = (double *)pv;
-        ra.slab_entries = entries;
-        ra.grid = grid;
         ra.lrn.mode = 2;
         ra.lrn.off = nullptr;
         ra.lrn.loc_bias = tsize;
@@ -240,7 +255,32 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         ra.lrn.arena_cap = ub;
         // the second arena starts empty: count its use from zero
         CHK(hipMemsetAsync(&dc->lc.arena_used, 0, sizeof(unsigned long long), s));
-        CHK(launch_numeric_bin(NUM_GLOBAL_BIN, ra, s));
+        if (rng && N <= BUCKET_MAX_COLS) {
+            // bucketed dense accumulation: staging for the longest row
+            const int64_t sc = S.max_row_nprod > 1 ? S.max_row_nprod : 1;
+            const int64_t g2 = bucket_grid(nretry, cus, sc);
+            void *sk = nullptr, *sv = nullptr;
+            CHK(ar.alloc(&sk, sizeof(int) * (size_t)(sc * g2)));
+            CHK(ar.alloc(&sv, sizeof(double) * (size_t)(sc * g2)));
+            ra.slab_keys = (int *)sk;
+            ra.slab_vals = (double *)sv;
+            ra.slab_entries = sc;
+            ra.grid = g2;
+            CHK(launch_numeric_bucket(ra, s));
+        } else {
+            // global hash tables sized from min(n_prod, N)
+            const int64_t bmx = S.max_row_nprod < N ? S.max_row_nprod : N;
+            const int64_t entries = pow2_host(2 * bmx > 64 ? 2 * bmx : 64);
+            const int64_t grid = nretry < (int64_t)cus ? nretry : (int64_t)cus;
+            void *pk = nullptr, *pv = nullptr;
+            CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
+            CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));
+            ra.slab_keys = (int *)pk;
+            ra.slab_vals = (double *)pv;
+            ra.slab_entries = entries;
+            ra.grid = grid;
+            CHK(launch_numeric_bin(NUM_GLOBAL_BIN, ra, s));
+        }
         st = scan_sizes(M, nz, crpt, parts, dc, &hc, s);
         if (st != OPSP_OK) return st;
         if (hc.num.error || hc.lc.error || (int64_t)hc.lc.retry != nretry) return OPSP_ERR_INTERNAL;

@@ -99,29 +99,37 @@ def test_learned_degenerate(m, k, n, d):
 
 
 @pytest.mark.parametrize("b", range(8))
-def test_learned_forced_bins(b):
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_learned_forced_bins(b, hash_all):
+    """Every row forced into each numeric bin; bin 7 takes the bucketed dense
+    kernel (hash_all 0) or the global hash tables (hash_all 1)."""
     ops = _ops()
     A = syn.rmat(11, 16, seed=7)
-    run(A, None, rand_predictor(seed=b), cfg=ops.Config(force_num_bin=b))
-    run(A, None, ops.Predictor(ops.PRED_RATIO, ratio=1e6), cfg=ops.Config(force_num_bin=b))
+    run(A, None, rand_predictor(seed=b), cfg=ops.Config(force_num_bin=b, hash_all_rows=hash_all))
+    run(A, None, ops.Predictor(ops.PRED_RATIO, ratio=1e6),
+        cfg=ops.Config(force_num_bin=b, hash_all_rows=hash_all))
 
 
-def test_table_overflow_recomputes_rows():
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_table_overflow_recomputes_rows(hash_all):
     """Capacities far below the row sizes: small tables fill up, the rows are
-    recomputed exactly into the second arena."""
+    recomputed exactly into the second arena (bucketed dense kernel, or
+    global hash tables sized from min(n_prod, N))."""
     ops = _ops()
     A = syn.stencil27(16, seed=4)
-    st = run(A, None, ops.Predictor(ops.PRED_RATIO, ratio=1e6, cap_scale=0.01))
+    st = run(A, None, ops.Predictor(ops.PRED_RATIO, ratio=1e6, cap_scale=0.01),
+             cfg=ops.Config(hash_all_rows=hash_all))
     assert st.table_overflow_rows > 0 and st.retry_rows >= st.table_overflow_rows
 
 
-def test_arena_exhaustion_recomputes_rows():
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_arena_exhaustion_recomputes_rows(hash_all):
     """Slots of zero capacity in tables large enough for the rows (bins 0 and
     1 take no rows): every nonempty row needs the arena, which holds only
     65536 entries here, so the rest are recomputed."""
     ops = _ops()
     A = syn.banded(40000, 64, 12, seed=8)
-    cfg = ops.Config(num_bounds=[-1, -1, 0, 0, 0, 0, 0])
+    cfg = ops.Config(num_bounds=[-1, -1, 0, 0, 0, 0, 0], hash_all_rows=hash_all)
     st = run(A, None, ops.Predictor(ops.PRED_UPPER, cap_scale=1e-9), cfg=cfg)
     assert st.cap_total == 0
     assert st.arena_entries > 0 and st.retry_rows > 0
