@@ -100,10 +100,11 @@ __device__ __forceinline__ void lrn_done(const Learn &L, int64_t row, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
-// bin 0: GL lanes per row; rank counting over the packed keys
+// bin 0: GL lanes per row (eight waves per SIMD requested: the
+// occupancy is otherwise capped at seven by scalar registers); rank counting over the packed keys
 // ---------------------------------------------------------------------------
 template <int GL, int T, bool LRN>
-__global__ __launch_bounds__(256) void k_num_group(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_num_group(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
@@ -321,7 +322,9 @@ __device__ __forceinline__ int team_excl_scan(int x, int &total, int *red) {
 // entries are ranked by counting over the table.
 // ---------------------------------------------------------------------------
 template <int W, int T, bool LRN>
-__global__ __launch_bounds__(W == 64 ? 256 : W) void k_num_row(
+// wave teams: eight waves per SIMD requested (scalar registers would
+// otherwise cap the occupancy at seven)
+__global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu(W == 64 ? 8 : 1))) void k_num_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,

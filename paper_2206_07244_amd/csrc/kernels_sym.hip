@@ -62,10 +62,11 @@ __device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, in
 }
 
 // ---------------------------------------------------------------------------
-// bin 0: GL lanes per row
+// bin 0: GL lanes per row (eight waves per SIMD requested: the
+// occupancy is otherwise capped at seven by scalar registers)
 // ---------------------------------------------------------------------------
 template <int GL, int T>
-__global__ __launch_bounds__(256) void k_sym_group(RowSrc src, const int64_t *__restrict__ arpt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_sym_group(RowSrc src, const int64_t *__restrict__ arpt,
                                                    const int32_t *__restrict__ acol,
                                                    const int64_t *__restrict__ brpt,
                                                    const int32_t *__restrict__ bcol,
@@ -107,7 +108,9 @@ __global__ __launch_bounds__(256) void k_sym_group(RowSrc src, const int64_t *__
 // bins 1-7: one team (a wave for W == 64, else the workgroup) per row
 // ---------------------------------------------------------------------------
 template <int W, int T, bool ABORT, bool PERSIST>
-__global__ __launch_bounds__(W == 64 ? 256 : W) void k_sym_row(
+// wave teams: eight waves per SIMD requested (scalar registers would
+// otherwise cap the occupancy at seven)
+__global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu(W == 64 ? 8 : 1))) void k_sym_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list,
