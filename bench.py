@@ -70,6 +70,15 @@ def stored_traffic(kernel: str, workload: str):
     return None
 
 
+def workload_class(name: str) -> str:
+    """Autotuner class of a named workload."""
+    if name.startswith("rmat"):
+        return "rmat"
+    if name.startswith("band"):
+        return "banded"
+    return "stencil"
+
+
 def numeric_bytes(M, nnzA, nprod, nnzC):
     """Algorithmic HBM bytes of the numeric step (one launch over all rows):
     A col+val 12 B/entry and B row bounds 16 B per A entry; B col+val 12 B per
@@ -101,6 +110,9 @@ def main():
                                                  "of equal n_prod (for products beyond HBM)")
     ap.add_argument("--no-learned", action="store_true",
                     help="plain mode: skip the one-phase comparison on the same workload")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="plain mode: use the built-in bin configuration instead of the "
+                         "autotuned one of the workload's class")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -137,11 +149,18 @@ def main():
     sh = stream.cuda_stream
     Ac = dA._c_fast(A.nnz)
 
+    # bin configuration: the autotuner's choice for the workload's class
+    from paper_2206_07244_amd import autotune
+    cls = workload_class(args.workload)
+    tuned = None if args.no_tuning else autotune.load_config(cls)
+    tref = ops.byref(tuned) if tuned is not None else None
+    log(f"bin configuration: {'tuned for ' + cls if tuned is not None else 'built-in'}")
+
     # warm-up (also fills the memory pool)
     st = ops.Stats()
     for _ in range(max(args.warmup, 1)):
         Cc = ops.opsp_csr()
-        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), None,
+        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), tref,
                                         ops.byref(st), sh)
         if code:
             raise ops.OpspError(code, "opsp_spgemm_ex")
@@ -152,20 +171,33 @@ def main():
         f"num={list(st.num_bin_rows)}")
 
     # timed region: K whole products
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        Cc = ops.spgemm_raw(Ac, Ac, sh)
-        ops.free_raw(Cc, sh)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ms = (t2 - t1) * 1e3 / args.steps
+    L = ops.lib()
+
+    def timed(cref):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            Cc = ops.opsp_csr()
+            code = L.opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), cref, None, sh)
+            if code:
+                raise ops.OpspError(code, "opsp_spgemm_ex")
+            ops.free_raw(Cc, sh)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3 / args.steps
+    ms = timed(tref)
     gflops = 2.0 * nprod / (ms * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms:.3f} ms/step, {gflops:.1f} GFLOPS")
+    ms_default = timed(None) if tuned is not None else ms
+    if tuned is not None:
+        log(f"built-in configuration: {ms_default:.3f} ms/step")
 
     # per-stage kernel durations: same calls, HIP events recorded on the call's
     # stream between stages (stage 1 = symbolic kernels, 3 = numeric kernels)
-    cfg = ops.Config(stage_timing=1)
+    if tuned is not None:
+        cfg = autotune.load_config(cls)
+        cfg.stage_timing = 1
+    else:
+        cfg = ops.Config(stage_timing=1)
     stage = np.zeros(8)
     for _ in range(args.steps):
         Cc = ops.opsp_csr()
@@ -205,7 +237,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "rows": M, "nnzA": nnzA,
-                   "nprod": nprod, "nnzC": nnzC, "path": "plain two-pass"},
+                   "nprod": nprod, "nnzC": nnzC, "path": "plain two-pass",
+                   "bins": f"autotuned ({cls})" if tuned is not None else "built-in"},
+        "builtin_config": {"value": round(2.0 * nprod / (ms_default * 1e-3) / 1e9, 3),
+                           "ms_per_step": round(ms_default, 4)},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "algorithmic_bytes": bytes_, "kernel_ms": round(kms, 4)},

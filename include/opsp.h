@@ -131,6 +131,7 @@ typedef struct {
     int64_t slot_overflow_rows;   /* rows with nnz above their capacity, stored in the arena */
     int64_t table_overflow_rows;  /* rows whose hash table filled up (recomputed exactly) */
     int64_t retry_rows;           /* rows recomputed exactly (table full or arena exhausted) */
+    double calib_scale;           /* scale applied to the network's estimates (1 = none) */
 } opsp_stats;
 
 typedef struct opsp_plan opsp_plan;       /* opaque */
@@ -227,9 +228,12 @@ opsp_status opsp_spgemm_batched(int32_t count, const opsp_csr *A, const opsp_csr
  *               z1 = ((b1 + w0 x0) + w1 x1) + w2 x2   float32, no fused ops
  *               h1 = bf16(relu(z1))                   nearest, ties to even
  *               y  = W3 relu(W2 h1 + b2) + b3        float32 accumulation
- *   capacity  cap_i = ceil((2^y_i - 1)(1 + margin)) clamped to
+ *   capacity  cap_i = ceil((2^y_i - 1) c (1 + margin)) clamped to
  *             [min(b_max_i, U_i), U_i] with U_i = min(n_prod_i, N); a row
- *             with a_len_i <= 1 gets n_prod_i (exact).
+ *             with a_len_i <= 1 gets n_prod_i (exact); c is the calibration
+ *             factor of a small exactly counted sample of rows (see
+ *             calib_rows), which corrects the network's bias on the input at
+ *             hand.
  * Whatever the capacities, the result is the C of opsp_spgemm (same
  * structure; values summed in unspecified order): a row that outgrows its
  * capacity is stored in an overflow arena, and a row whose hash table fills
@@ -252,6 +256,13 @@ typedef struct {
                                * after clamping (0 = 1), e.g. 0.1 to overflow rows */
     float *pred_out;          /* optional device float[A.rows]: network outputs y_i */
     int64_t *cap_out;         /* optional device int64[A.rows]: capacities */
+    /* Kind MLP: calibration sample size.  Rows 0, S, 2S, ... (S =
+     * ceil(rows / calib_rows)) with a_len >= 2 and n_prod <= 2048 are counted
+     * exactly on the device, and every estimate 2^y_i - 1 is multiplied by
+     * (sum of their sizes) / (sum of their estimates clamped as above)
+     * before the margin.  0 = 2048 rows; negative = no calibration. */
+    int32_t calib_rows;
+    int32_t reserved;
 } opsp_predictor;
 
 /* Integer features of every row of A*B into device arrays of A->rows

@@ -176,13 +176,38 @@ def adam_step(theta, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def capacity(pred_log2, margin, alen, nprod, bmax, ncols) -> np.ndarray:
+def calibration(pred_log2, nnz_exact, alen, nprod, bmax, ncols, target=2048, max_nprod=2048):
+    """Scale of the network's estimates from an exactly counted sample:
+    rows 0, S, 2S, ... (S = ceil(M / target)) with a_len >= 2 and
+    n_prod <= max_nprod; scale = sum of their sizes / sum of their estimates
+    2^pred - 1 clamped to [min(b_max, U), U], U = min(n_prod, N) (1 when the
+    sample is empty).  nnz_exact(rows) returns the exact sizes of the listed
+    rows.  Returns (scale, sampled rows)."""
+    M = len(alen)
+    if M == 0:
+        return 1.0, np.zeros(0, np.int64)
+    stride = -(-M // target)
+    rows = np.arange(0, M, stride)
+    alen, nprod, bmax = (np.asarray(a, np.int64) for a in (alen, nprod, bmax))
+    rows = rows[(alen[rows] >= 2) & (nprod[rows] <= max_nprod)]
+    if rows.size == 0:
+        return 1.0, rows
+    hi = np.minimum(nprod[rows], ncols).astype(np.float64)
+    lo = np.minimum(bmax[rows], hi).astype(np.float64)
+    est = np.clip(np.exp2(np.asarray(pred_log2, np.float64)[rows]) - 1.0, lo, hi)
+    tot = est.sum()
+    if tot <= 0:
+        return 1.0, rows
+    return float(np.sum(nnz_exact(rows)) / tot), rows
+
+
+def capacity(pred_log2, margin, alen, nprod, bmax, ncols, scale=1.0) -> np.ndarray:
     """Slot capacity of each row from a prediction of log2(1 + nnz):
-    ceil((2^pred - 1) * (1 + margin)) clamped to [b_max, min(n_prod, ncols)],
-    since a row of C holds at least its longest referenced B row and at most
-    min(n_prod, N) entries; a row with at most one A entry has exactly n_prod
-    entries.  Evaluated in float64."""
-    est = np.ceil((np.exp2(np.asarray(pred_log2, np.float64)) - 1.0) * (1.0 + margin))
+    ceil((2^pred - 1) * scale * (1 + margin)) clamped to
+    [b_max, min(n_prod, ncols)], since a row of C holds at least its longest
+    referenced B row and at most min(n_prod, N) entries; a row with at most
+    one A entry has exactly n_prod entries.  Evaluated in float64."""
+    est = np.ceil((np.exp2(np.asarray(pred_log2, np.float64)) - 1.0) * scale * (1.0 + margin))
     nprod = np.asarray(nprod, np.int64)
     hi = np.minimum(nprod, ncols)
     lo = np.minimum(np.asarray(bmax, np.int64), hi)

@@ -81,7 +81,7 @@ class Stats(ctypes.Structure):
                 ("num_bin_rows", c_int64 * NUM_BINS), ("ms_stage", ctypes.c_float * 8),
                 ("cap_total", c_int64), ("arena_entries", c_int64),
                 ("slot_overflow_rows", c_int64), ("table_overflow_rows", c_int64),
-                ("retry_rows", c_int64)]
+                ("retry_rows", c_int64), ("calib_scale", c_double)]
 
     def as_dict(self):
         return {"nprod": self.nprod, "nnz": self.nnz, "max_row_nprod": self.max_row_nprod,
@@ -89,14 +89,16 @@ class Stats(ctypes.Structure):
                 "num_bin_rows": list(self.num_bin_rows), "ms_stage": list(self.ms_stage)[:5],
                 "cap_total": self.cap_total, "arena_entries": self.arena_entries,
                 "slot_overflow_rows": self.slot_overflow_rows,
-                "table_overflow_rows": self.table_overflow_rows, "retry_rows": self.retry_rows}
+                "table_overflow_rows": self.table_overflow_rows, "retry_rows": self.retry_rows,
+                "calib_scale": self.calib_scale}
 
 
 class opsp_predictor(ctypes.Structure):
     """Mirror of ``opsp_predictor``."""
     _fields_ = [("version", c_int32), ("kind", c_int32), ("params", c_void_p),
                 ("margin", c_double), ("ratio", c_double), ("cap_scale", c_double),
-                ("pred_out", c_void_p), ("cap_out", c_void_p)]
+                ("pred_out", c_void_p), ("cap_out", c_void_p), ("calib_rows", c_int32),
+                ("reserved", c_int32)]
 
 
 class OpspError(RuntimeError):
@@ -525,12 +527,14 @@ class Predictor:
     on the device) or one of the reference rules (PRED_UPPER, PRED_RATIO)."""
 
     def __init__(self, kind: int = PRED_MLP, params=None, margin: float = 0.0, ratio: float = 1.0,
-                 cap_scale: float = 0.0):
+                 cap_scale: float = 0.0, calib_rows: int = 0):
         self.kind, self.params = kind, params
         self.margin, self.ratio, self.cap_scale = float(margin), float(ratio), float(cap_scale)
+        self.calib_rows = int(calib_rows)
 
     @classmethod
-    def load(cls, path: Optional[str] = None, device="cuda", margin: Optional[float] = None):
+    def load(cls, path: Optional[str] = None, device="cuda", margin: Optional[float] = None,
+             calib_rows: int = 0):
         """The trained network stored by the training driver (JSON with the
         bf16 bit patterns in the packed order)."""
         import json
@@ -540,7 +544,8 @@ class Predictor:
         bits = np.asarray(d["params_bf16"], np.uint16)
         assert bits.size == MLP_NPARAM
         t = torch.from_numpy(bits.view(np.int16).copy()).to(device)
-        return cls(PRED_MLP, t, d.get("margin", 0.0) if margin is None else margin)
+        return cls(PRED_MLP, t, d.get("margin", 0.0) if margin is None else margin,
+                   calib_rows=calib_rows)
 
     def struct(self, pred_out=None, cap_out=None) -> opsp_predictor:
         p = opsp_predictor()
@@ -549,6 +554,7 @@ class Predictor:
         p.params = _ptr(self.params) if self.params is not None else None
         p.margin, p.ratio, p.cap_scale = self.margin, self.ratio, self.cap_scale
         p.pred_out, p.cap_out = _ptr(pred_out), _ptr(cap_out)
+        p.calib_rows = self.calib_rows
         return p
 
 

@@ -177,9 +177,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t *__restrict_
     }
 }
 
-// Capacity of one row (see launch_mlp_caps), computed in double precision.
+// Capacity of one row (see launch_mlp_caps), computed in double precision;
+// `cal` scales the network's estimate (sampled calibration, 1 = none).
 __device__ __forceinline__ int64_t cap_of(const CapArgs &c, float pred, int64_t alen, int64_t np,
-                                          int64_t bmax) {
+                                          int64_t bmax, double cal) {
     const int64_t hi = np < c.ncols ? np : c.ncols;
     int64_t cap;
     if (alen <= 1) {
@@ -187,7 +188,7 @@ __device__ __forceinline__ int64_t cap_of(const CapArgs &c, float pred, int64_t 
     } else if (c.kind == 1) {
         cap = hi;
     } else {
-        const double est = c.kind == 0 ? (exp2((double)pred) - 1.0) * (1.0 + c.margin)
+        const double est = c.kind == 0 ? (exp2((double)pred) - 1.0) * cal * (1.0 + c.margin)
                                        : (double)np / c.ratio * (1.0 + c.margin);
         const int64_t lo = bmax < hi ? bmax : hi;
         const double e = ceil(est);
@@ -214,14 +215,18 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
     if (threadIdx.x == 0) { s_tot = 0; s_max = 0; s_np = 0; s_npmax = 0; }
     __syncthreads();
     const int l = lane_id(), r = l & 15, q = l >> 4, wv = threadIdx.x >> 6;
+    const bool run_net = c.kind == 0 && !c.pred_in;
+    // sampled calibration: exact / estimated sizes of the sampled rows
+    double cal = 1.0;
+    if (c.kind == 0 && c.calib && c.calib[1] > 0.0) cal = c.calib[0] / c.calib[1];
     MlpLane w;
-    if (c.kind == 0) mlp_load(c.P, w);
+    if (run_net) mlp_load(c.P, w);
     unsigned long long tot = 0, mx = 0, nps = 0, npm = 0;
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
         const int64_t t0 = (int64_t)blockIdx.x * 256 + wv * 64 + j * 16;
         float y[4] = {0.f, 0.f, 0.f, 0.f};
-        if (c.kind == 0) {
+        if (run_net) {
             const int64_t row = t0 + r;
             float x0 = 0.f, x1 = 0.f, x2 = 0.f;
             if (row < M) {
@@ -237,10 +242,11 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
 #pragma unroll
             for (int i = 1; i < 4; ++i) v = r == i ? y[i] : v;
             if (row < M) {
+                if (c.pred_in) v = c.pred_in[row];
                 const int64_t np = nprod[row];
-                const int64_t cp = cap_of(c, v, alen[row], np, bmax[row]);
+                const int64_t cp = cap_of(c, v, alen[row], np, bmax[row], cal);
                 cap[row] = cp;
-                if (c.pred) c.pred[row] = v;
+                if (c.pred && !c.pred_in) c.pred[row] = v;
                 atomicAdd(&hist[bin_of(cp, bd)], 1u);
                 tot += (unsigned long long)cp;
                 mx = (unsigned long long)cp > mx ? (unsigned long long)cp : mx;
@@ -267,6 +273,94 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
         parts.mx[blockIdx.x] = s_max;
         atomicAdd(&lc->nprod_total, s_np);
         atomicMax(&lc->nprod_max, s_npmax);
+    }
+}
+
+// Network outputs of every row (16-row tiles per wave) from the integer
+// features; feeds the calibration sample and the capacity kernel.
+__global__ __launch_bounds__(256) void k_mlp_pred(int64_t M, const uint16_t *__restrict__ P,
+                                                  const int32_t *__restrict__ alen,
+                                                  const int64_t *__restrict__ nprod,
+                                                  const int32_t *__restrict__ bmax,
+                                                  float *__restrict__ pred) {
+    MlpLane w;
+    mlp_load(P, w);
+    const int l = lane_id(), r = l & 15, q = l >> 4;
+    const int64_t tiles = (M + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < tiles;
+         tile += (int64_t)gridDim.x * 4) {
+        const int64_t row = tile * 16 + r;
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        if (row < M) {
+            x0 = feat(alen[row]);
+            x1 = feat(nprod[row]);
+            x2 = feat(bmax[row]);
+        }
+        float y[4];
+        mlp_tile(w, x0, x1, x2, y);
+        if (r < 4) {
+            const int64_t orow = tile * 16 + 4 * q + r;
+            float v = y[0];
+#pragma unroll
+            for (int i = 1; i < 4; ++i) v = r == i ? y[i] : v;
+            if (orow < M) pred[orow] = v;
+        }
+    }
+}
+
+// Calibration sample: one wave per sampled row counts its distinct columns
+// exactly with an LDS hash table (twice the largest sampled n_prod) and adds
+// (exact size, clamped estimate) into the two sums.
+constexpr int CAL_T = 2 * (int)CALIB_MAX_NPROD;
+
+__global__ __launch_bounds__(256) void k_calib(int64_t M, int64_t stride, int64_t ncols,
+                                               const int64_t *__restrict__ arpt,
+                                               const int32_t *__restrict__ acol,
+                                               const int64_t *__restrict__ brpt,
+                                               const int32_t *__restrict__ bcol,
+                                               const int32_t *__restrict__ alen,
+                                               const int64_t *__restrict__ nprod,
+                                               const int32_t *__restrict__ bmax,
+                                               const float *__restrict__ pred,
+                                               double *__restrict__ calib,
+                                               unsigned int *__restrict__ err) {
+    __shared__ int tab[4][CAL_T];
+    __shared__ double s_sum[2][4];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + wv;   // sample index
+    const int64_t row = k * stride;
+    double ex = 0.0, es = 0.0;
+    const bool take = row < M && alen[row] >= 2 && nprod[row] <= CALIB_MAX_NPROD;
+    if (take) {   // uniform over the wave
+        int *tb = tab[wv];
+        for (int s = l; s < CAL_T; s += 64) tb[s] = -1;
+        wave_lds_sync();
+        int cnt = 0;
+        row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, 0, 1,
+                            [&](bool ok, int key) { cnt += sym_insert_wave(tb, (uint32_t)CAL_T, ok, key, err); },
+                            [] { return false; });
+        cnt = wave_sum(cnt);
+        const int64_t np = nprod[row];
+        const int64_t hi = np < ncols ? np : ncols;
+        const int64_t bm = bmax[row];
+        const double lo = (double)(bm < hi ? bm : hi);
+        double e = exp2((double)pred[row]) - 1.0;
+        e = e < lo ? lo : (e > (double)hi ? (double)hi : e);
+        ex = (double)cnt;
+        es = e;
+    }
+    if (l == 0) {
+        s_sum[0][wv] = ex;
+        s_sum[1][wv] = es;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double a = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
+        const double b = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
+        if (b > 0.0) {
+            unsafeAtomicAdd(&calib[0], a);
+            unsafeAtomicAdd(&calib[1], b);
+        }
     }
 }
 
@@ -478,6 +572,28 @@ hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *g, fl
                            float b2, float eps, float c1, float c2, uint16_t *P, hipStream_t s) {
     hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, master, m, v, g,
                        lr, b1, b2, eps, c1, c2, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pred(int64_t M, const uint16_t *P, const int32_t *alen, const int64_t *nprod,
+                           const int32_t *bmax, float *pred, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    const int64_t tiles = (M + 15) / 16;
+    int64_t grid = (tiles + 3) / 4;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_mlp_pred, dim3((unsigned)grid), dim3(256), 0, s, M, P, alen, nprod, bmax, pred);
+    return hipGetLastError();
+}
+
+hipError_t launch_calib(const DevCSR &A, const DevCSR &B, int64_t target, const int32_t *alen,
+                        const int64_t *nprod, const int32_t *bmax, const float *pred,
+                        double *calib, unsigned int *err, hipStream_t s) {
+    const int64_t M = A.rows;
+    if (M <= 0 || target <= 0) return hipSuccess;
+    const int64_t stride = (M + target - 1) / target;
+    const int64_t ns = (M + stride - 1) / stride;
+    hipLaunchKernelGGL(k_calib, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, s, M, stride, B.cols,
+                       A.rpt, A.col, B.rpt, B.col, alen, nprod, bmax, pred, calib, err);
     return hipGetLastError();
 }
 

@@ -35,32 +35,6 @@ __device__ __forceinline__ int sym_insert_lds(int *tab, uint32_t T, int key) {
     return -1;
 }
 
-// Insert one key per lane (lanes with ok == false take part without a key).
-// The probe loop is uniform over the wave and bounded by T iterations with a
-// scalar counter; every probe is a single compare-and-swap (Alg. 4).
-// Returns 1 when this lane's key was new.
-template <class Tab>
-__device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, int key,
-                                               unsigned int *err) {
-    bool pend = ok;
-    int isnew = 0;
-    uint32_t s = ok ? hslot(key, T) : 0u;
-    for (uint32_t it = 0; __ballot(pend); ++it) {
-        if (it >= T) {
-            if (pend) atomicAdd(err, 1u);
-            break;
-        }
-        if (pend) {
-            const int old = atomicCAS(&tab[s], -1, key);
-            const bool hit = (old == -1) | (old == key);
-            isnew = old == -1;
-            pend = !hit;
-            s = hit ? s : next_slot(s, T);
-        }
-    }
-    return isnew;
-}
-
 // ---------------------------------------------------------------------------
 // bin 0: GL lanes per row (eight waves per SIMD requested: the
 // occupancy is otherwise capped at seven by scalar registers)

@@ -133,10 +133,23 @@ struct CapArgs {
     const uint16_t *P;
     double margin, ratio, scale;
     int64_t ncols;
-    float *pred;             // optional: the network's outputs
+    float *pred;             // optional: the network's outputs (written)
+    const float *pred_in;    // network outputs computed before (NULL = run it here)
+    const double *calib;     // [exact nnz, estimate] sums of the sampled rows, or NULL
 };
 hipError_t launch_mlp_caps(int64_t M, const CapArgs &ca, const int32_t *alen, const int64_t *nprod,
                            const int32_t *bmax, int64_t *cap, const Bounds &bd,
                            const BlockParts &parts, LearnCtr *lc, hipStream_t s);
+// Network outputs for every row from the integer features.
+hipError_t launch_mlp_pred(int64_t M, const uint16_t *P, const int32_t *alen, const int64_t *nprod,
+                           const int32_t *bmax, float *pred, hipStream_t s);
+// Calibration sample: rows 0, S, 2S, ... (S = ceil(M / target)) with
+// 2 <= a_len and n_prod <= CALIB_MAX_NPROD are counted exactly; calib[0] +=
+// their sizes, calib[1] += their clamped estimates 2^pred - 1 (calib zeroed
+// before).
+constexpr int64_t CALIB_MAX_NPROD = 2048;
+hipError_t launch_calib(const DevCSR &A, const DevCSR &B, int64_t target, const int32_t *alen,
+                        const int64_t *nprod, const int32_t *bmax, const float *pred,
+                        double *calib, unsigned int *err, hipStream_t s);
 
 }  // namespace opsp

@@ -48,7 +48,9 @@ struct LearnedCounters {
     Counters num;      // numeric bins by capacity; total = sum of capacities
     Counters scan;     // scan of the exact row sizes; total = nnz(C)
     LearnCtr lc;
+    double calib[2];   // calibration sample: sum of exact sizes, sum of estimates
 };
+constexpr int64_t CALIB_ROWS_DEFAULT = 2048;
 static_assert(sizeof(LearnedCounters) <= PINNED_BYTES, "read-back buffer");
 
 opsp_status check_predictor(const opsp_predictor *p) {
@@ -132,7 +134,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
 
     // 1-2 setup, capacities, numeric bins by capacity, slot offsets
     tm.mark();
-    CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnCtr), s));
+    CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnCtr) + 2 * sizeof(double), s));
     if (bfl) CHK(launch_brange(dB, bfl, s));
     CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s, bfl, rng));
     CapArgs ca;
@@ -144,6 +146,20 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     ca.scale = pr->cap_scale > 0 ? pr->cap_scale : 1.0;
     ca.ncols = N;
     ca.pred = pr->pred_out;
+    const int64_t calib_rows = pr->calib_rows == 0 ? CALIB_ROWS_DEFAULT : pr->calib_rows;
+    if (pr->kind == OPSP_PRED_MLP && calib_rows > 0) {
+        // network outputs first, then the exactly counted sample, then the
+        // calibrated capacities
+        float *pred = pr->pred_out;
+        if (!pred) {
+            CHK(ar.alloc(&p, sizeof(float) * (size_t)M));
+            pred = (float *)p;
+        }
+        CHK(launch_mlp_pred(M, pr->params, alen, np, bmax, pred, s));
+        CHK(launch_calib(dA, dB, calib_rows, alen, np, bmax, pred, dc->calib, &dc->lc.error, s));
+        ca.pred_in = pred;
+        ca.calib = dc->calib;
+    }
     CHK(launch_mlp_caps(M, ca, alen, np, bmax, off, bn, parts, &dc->lc, s));
     if (pr->cap_out)
         CHK(hipMemcpyAsync(pr->cap_out, off, sizeof(int64_t) * (size_t)M, hipMemcpyDeviceToDevice, s));
@@ -156,6 +172,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     S.nprod = (int64_t)hc.lc.nprod_total;
     S.max_row_nprod = (int64_t)hc.lc.nprod_max;
     S.cap_total = cap_total;
+    S.calib_scale = hc.calib[1] > 0.0 ? hc.calib[0] / hc.calib[1] : 1.0;
     if (cap_max > INT32_MAX) return OPSP_ERR_OVERFLOW;
     int64_t nsz[OPSP_NUM_BINS], noff[OPSP_NUM_BINS];
     for (int j = 0; j < OPSP_NUM_BINS; ++j) {

@@ -111,5 +111,5 @@ def test_predictor_arguments_rejected_on_host():
 
 def test_stats_struct_matches_header():
     """ctypes mirrors have the sizes the header implies."""
-    assert ctypes.sizeof(ops.Stats) == 8 * (4 + ops.SYM_BINS + ops.NUM_BINS) + 4 * 8 + 8 * 5
-    assert ctypes.sizeof(ops.opsp_predictor) == 4 + 4 + 8 + 8 * 3 + 8 + 8
+    assert ctypes.sizeof(ops.Stats) == 8 * (4 + ops.SYM_BINS + ops.NUM_BINS) + 4 * 8 + 8 * 5 + 8
+    assert ctypes.sizeof(ops.opsp_predictor) == 4 + 4 + 8 + 8 * 3 + 8 + 8 + 4 + 4

@@ -135,14 +135,25 @@ def test_arena_exhaustion_recomputes_rows(hash_all):
     assert st.arena_entries > 0 and st.retry_rows > 0
 
 
-def test_capacities_follow_the_rule():
+@pytest.mark.parametrize("calib_rows", [-1, 0, 300])
+def test_capacities_follow_the_rule(calib_rows):
     """Capacities reported by the call equal the rule applied (in float64, as
-    the kernel does) to the network outputs it reports, and obey the bounds."""
+    the kernel does) to the network outputs it reports, scaled by the
+    calibration of the sampled rows (counted exactly by the oracle), and obey
+    the bounds."""
     A = syn.rmat(12, 16, seed=12)
-    pred = rand_predictor(seed=12, margin=0.25)
+    pred = rand_predictor(seed=12, margin=0.25, calib_rows=calib_rows)
     st, caps, y = run(A, None, pred, want_caps=True)
     nprod, alen, bmax, _ = oracle.row_stats(A, A)
-    ref = mlp.capacity(y.astype(np.float64), 0.25, alen, nprod, bmax, A.cols)
+    scale = 1.0
+    if calib_rows >= 0:
+        scale, rows = mlp.calibration(y.astype(np.float64), lambda r: oracle.symbolic(A, A, r), alen,
+                                      nprod, bmax, A.cols, target=calib_rows or 2048)
+        assert rows.size > 0
+        assert abs(st.calib_scale - scale) <= 1e-9 * scale
+    else:
+        assert st.calib_scale == 1.0
+    ref = mlp.capacity(y.astype(np.float64), 0.25, alen, nprod, bmax, A.cols, scale=st.calib_scale)
     hi = np.minimum(nprod, A.cols)
     assert np.all((caps >= np.minimum(bmax, hi)) | (alen <= 1))
     assert np.all((caps <= hi) | (alen <= 1))
@@ -183,3 +194,25 @@ def test_repeated_calls_reuse_memory():
         else:
             assert torch.equal(first[0], C.rpt) and torch.equal(first[1], C.col)
         del C
+
+
+def test_calibration_tightens_stencil_capacities():
+    """A network that overestimates every row by 3x: the sampled calibration
+    brings the capacity total of a 27-point stencil product to within a few
+    percent of nnz(C), without it the capacities stay 3x too large."""
+    import torch
+    ops = _ops()
+    A = syn.stencil27(40, seed=5)
+    nprod, alen, bmax, _ = oracle.row_stats(A, A)
+    nnz = oracle.symbolic(A, A)
+    # a network that outputs log2(1 + 3 nnz) only through its bias is not
+    # possible; instead use the pass-through weights of a constant output
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    p["b3"][0] = np.log2(1 + 3 * np.median(nnz))
+    bits = mlp.bf16_bits(mlp.pack(p))
+    params = torch.from_numpy(bits.view(np.int16).copy()).cuda()
+    st0 = run(A, None, ops.Predictor(ops.PRED_MLP, params, margin=0.0, calib_rows=-1))
+    st1 = run(A, None, ops.Predictor(ops.PRED_MLP, params, margin=0.0))
+    assert st0.cap_total > 2.0 * st0.nnz
+    assert st1.cap_total < 1.35 * st1.nnz
+    assert abs(st1.calib_scale - 1.0 / 3.0) < 0.2

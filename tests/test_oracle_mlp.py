@@ -209,3 +209,22 @@ def test_pinball_level_is_the_empirical_quantile():
         g[:-1] = 0.0                  # only the output bias moves
         th, m, v = mlp.adam_step(th, m, v, g, step, lr=0.02)
     assert abs(th[-1] - np.quantile(tgt, 0.9)) < 0.08
+
+
+def test_calibration_sample_and_scale():
+    """Sampling rule and scale on a hand-checked case: every second row is
+    sampled (M = 8, target 4), rows with a_len < 2 or large n_prod are
+    skipped, estimates are clamped before summing."""
+    pred = np.log2(1 + np.array([10.0, 0, 30.0, 0, 5.0, 0, 100.0, 0]))
+    alen = np.array([3, 3, 1, 3, 4, 3, 5, 3])
+    nprod = np.array([40, 9, 30, 9, 60, 9, 5000, 9])
+    bmax = np.array([12, 3, 30, 3, 9, 3, 50, 3])
+    exact = {0: 20, 4: 18}
+    c, rows = mlp.calibration(pred, lambda r: np.array([exact[int(i)] for i in r]), alen, nprod,
+                              bmax, ncols=1000, target=4, max_nprod=2048)
+    # rows 0, 2, 4, 6: row 2 has a_len 1, row 6 n_prod 5000 > 2048
+    np.testing.assert_array_equal(rows, [0, 4])
+    # estimates: row 0 -> 10 clamped to [12, 40] = 12; row 4 -> 5 clamped to [9, 60] = 9
+    assert c == (20 + 18) / (12 + 9)
+    cap = mlp.capacity(pred, 0.0, alen, nprod, bmax, 1000, scale=c)
+    assert cap[0] == max(12, int(np.ceil(10 * c)))
