@@ -213,6 +213,8 @@ __global__ __launch_bounds__(1024) void k_finalize(int64_t nblk, int nslots, Blo
     if (t == 0) {
         ctr->fail = 0u;
         ctr->error = 0u;
+        ctr->sched[0] = 0ull;
+        ctr->sched[1] = 0ull;
     }
     if (t < NV) carry[t] = 0;
     unsigned long long mx = 0;

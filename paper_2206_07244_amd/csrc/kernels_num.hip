@@ -806,6 +806,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
     __shared__ unsigned int off[BK_NB + 1];
     __shared__ unsigned int red[16];
     __shared__ long long s_base;
+    __shared__ long long s_r;
 
     src.resolve();
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
@@ -813,9 +814,17 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
     double *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
     for (int i = t; i < BK_CW; i += 1024) dense[i] = 0.0;
     for (int i = t; i < BK_CW / 32; i += 1024) bits[i] = 0u;
-    __syncthreads();
 
-    for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
+    // rows from the launch's counter: row lengths here vary by orders of
+    // magnitude, and a round-robin assignment leaves a few workgroups with
+    // most of the work
+    auto fetch = [&]() -> int64_t {
+        __syncthreads();   // every thread is done with the previous s_r
+        if (t == 0) s_r = (long long)take_row(ctr->sched, src.nrows);
+        __syncthreads();
+        return (int64_t)s_r;
+    };
+    for (int64_t r = fetch(); r < src.nrows; r = fetch()) {
         const int64_t row = src.row(r);
         const int64_t a0 = arpt[row], a1 = arpt[row + 1];
         const int2 rg = rng[row];

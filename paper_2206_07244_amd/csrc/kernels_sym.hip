@@ -210,38 +210,92 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
 }
 
 // ---------------------------------------------------------------------------
-// bin 8: global-memory tables, one slab per persistent workgroup
+// bin 8: rows too long for the LDS tables.  With the row's column range
+// known, the distinct columns are counted in an LDS bitmap of 2^20 columns,
+// one pass over the row's products per 2^20-column window of the range
+// (a product is a bit set; no probing, no global table).  Rows whose range
+// needs more than SW_MAXPASS windows, and every row when no ranges were
+// computed, use a global-memory hash table, one slab per workgroup.  Rows
+// are taken from a counter (the longest rows would otherwise pile up on a
+// few workgroups of a round-robin assignment).
 // ---------------------------------------------------------------------------
+constexpr int SW_WORDS = 1 << (SW_LG - 5);
+
 __global__ __launch_bounds__(1024) void k_sym_global(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
-    int64_t ncols, int *slabs, int64_t slab_entries, Counters *__restrict__ ctr) {
+    int64_t ncols, int *slabs, int64_t slab_entries, const int2 *__restrict__ rng,
+    unsigned long long *sched, Counters *__restrict__ ctr) {
+    __shared__ unsigned int bm[SW_WORDS];
     __shared__ int red[16];
+    __shared__ long long s_r;
     src.resolve();
-    int *tb = slabs + (int64_t)blockIdx.x * slab_entries;
-    const int t = threadIdx.x;
-    for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
+    int *tb = slabs ? slabs + (int64_t)blockIdx.x * slab_entries : nullptr;
+    const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+    int64_t r = blockIdx.x;
+    while (true) {
+        if (sched) {
+            if (t == 0) s_r = (long long)take_row(sched, src.nrows);
+            __syncthreads();
+            r = (int64_t)s_r;
+        }
+        if (r >= src.nrows) break;   // uniform
         const int64_t row = src.row(r);
-        // C.rpt[row] still holds n_prod for rows that reach this kernel
-        const int64_t np = nnz[row];
-        const int64_t bound = np < ncols ? np : ncols;
-        uint32_t T = pow2_at_least((uint64_t)(2 * bound > 64 ? 2 * bound : 64));
-        if ((int64_t)T > slab_entries) T = (uint32_t)slab_entries;
-        for (uint32_t s = t; s < T; s += 1024) tb[s] = -1;
-        __syncthreads();
-        int cnt = 0;
-        auto ins = [&](bool ok, int key) { cnt += sym_insert_wave(tb, T, ok, key, &ctr->error); };
-        row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, t >> 6, 16,
-                            ins, [] { return false; });
-        cnt = wave_sum(cnt);
-        if ((t & 63) == 0) red[t >> 6] = cnt;
-        __syncthreads();
-        if (t == 0) {
-            int64_t sum = 0;
-            for (int i = 0; i < 16; ++i) sum += red[i];
-            nnz[row] = sum;
+        const int64_t a0 = arpt[row], a1 = arpt[row + 1];
+        int64_t lo = 0, span = -1;
+        if (rng) {
+            const int2 rg = rng[row];
+            lo = rg.x;
+            span = (int64_t)rg.y - rg.x + 1;
+        }
+        if (rng && span <= ((int64_t)SW_MAXPASS << SW_LG)) {
+            int64_t total = 0;
+            for (int64_t w0 = 0; w0 < span; w0 += (1 << SW_LG)) {
+                const int64_t rest = span - w0;
+                const uint32_t wlen = rest < (1 << SW_LG) ? (uint32_t)rest : (1u << SW_LG);
+                const uint32_t words = (wlen + 31) >> 5;
+                for (uint32_t i = t; i < words; i += 1024) bm[i] = 0u;
+                __syncthreads();
+                const uint32_t base = (uint32_t)(lo + w0);
+                row_products<false>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
+                                    [&](bool ok, int key) {
+                                        const uint32_t o = (uint32_t)key - base;
+                                        if (ok && o < wlen) atomicOr(&bm[o >> 5], 1u << (o & 31));
+                                    },
+                                    [] { return false; });
+                __syncthreads();
+                unsigned int c = 0;
+                for (uint32_t i = t; i < words; i += 1024) c += __popc(bm[i]);
+                c = wave_sum(c);
+                if (l == 0) red[wv] = (int)c;
+                __syncthreads();
+                for (int i = 0; i < 16; ++i) total += red[i];
+                __syncthreads();
+            }
+            if (t == 0) nnz[row] = total < 0 ? 0 : total;
+        } else {
+            // C.rpt[row] still holds n_prod for rows that reach this kernel
+            const int64_t np = nnz[row];
+            const int64_t bound = np < ncols ? np : ncols;
+            uint32_t T = pow2_at_least((uint64_t)(2 * bound > 64 ? 2 * bound : 64));
+            if ((int64_t)T > slab_entries) T = (uint32_t)slab_entries;
+            for (uint32_t s = t; s < T; s += 1024) tb[s] = -1;
+            __syncthreads();
+            int cnt = 0;
+            auto ins = [&](bool ok, int key) { cnt += sym_insert_wave(tb, T, ok, key, &ctr->error); };
+            row_products<false>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16, ins,
+                                [] { return false; });
+            cnt = wave_sum(cnt);
+            if (l == 0) red[wv] = cnt;
+            __syncthreads();
+            if (t == 0) {
+                int64_t sum = 0;
+                for (int i = 0; i < 16; ++i) sum += red[i];
+                nnz[row] = sum;
+            }
         }
         __syncthreads();
+        if (!sched) r += gridDim.x;
     }
 }
 
@@ -289,7 +343,7 @@ hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
             if (a.grid <= 0) return hipSuccess;
             hipLaunchKernelGGL(k_sym_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
                                a.A.col, a.B.rpt, a.B.col, a.nnz, a.B.cols, a.slab, a.slab_entries,
-                               a.ctr);
+                               a.rng, a.sched, a.ctr);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

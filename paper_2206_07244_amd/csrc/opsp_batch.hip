@@ -218,6 +218,7 @@ opsp_status capture_g1(opsp_batch *b, hipStream_t s) {
                 gl.slab = b->slab8;
                 gl.slab_entries = b->slab8_entries;
                 gl.grid = b->slab8_grid;
+                gl.sched = b->ctr[0].sched;
                 if ((e = launch_symbolic_bin(SYM_GLOBAL_BIN, gl, s)) != hipSuccess) return e;
             }
         }

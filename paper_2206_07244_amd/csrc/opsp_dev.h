@@ -50,7 +50,8 @@ struct Counters {
     unsigned long long maxv;        // largest row value
     unsigned int fail;              // rows abandoned by the LDS table (symbolic)
     unsigned int error;             // internal consistency failures
-    unsigned long long pad[6];
+    unsigned long long sched[2];    // row counter, finished workgroups (take_row)
+    unsigned long long pad[4];
 };
 
 // Counters of the one-phase (predicted-capacity) numeric step, zeroed
@@ -123,6 +124,24 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t n) {
     const int64_t q = n / NUM_XCD, r = n % NUM_XCD;
     const int64_t x = bid % NUM_XCD, local = bid / NUM_XCD;
     return x * q + (x < r ? x : r) + local;
+}
+
+// Dynamic row assignment of a persistent launch (called by thread 0 of a
+// workgroup): sched[0] hands out row indices, sched[1] counts workgroups
+// that found no row left.  The last workgroup of the grid to finish resets
+// both to zero, so that the next launch on the stream starts from zero; by
+// then every other workgroup has left its loop.  Every workgroup of the
+// grid must call this until it returns a value >= nrows.
+__device__ __forceinline__ int64_t take_row(unsigned long long *sched, int64_t nrows) {
+    const unsigned long long r = atomicAdd(&sched[0], 1ull);
+    if ((int64_t)r >= nrows) {
+        const unsigned long long d = atomicAdd(&sched[1], 1ull);
+        if (d == (unsigned long long)gridDim.x - 1ull) {
+            atomicExch(&sched[0], 0ull);
+            atomicExch(&sched[1], 0ull);
+        }
+    }
+    return (int64_t)r;
 }
 
 // Wave helpers ---------------------------------------------------------------

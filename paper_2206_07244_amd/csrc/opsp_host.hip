@@ -308,8 +308,12 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
             CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)ssz[7]));
             fail_list = (int32_t *)p;
         }
-        const int64_t bound = (int64_t)hS.maxv < N ? (int64_t)hS.maxv : N;
-        slab_entries = pow2_host(2 * bound > 64 ? 2 * bound : 64);
+        // global hash tables only where a row's range can exceed the
+        // bitmap windows (every row's range lies within [0, N))
+        if (!rng || N > ((int64_t)SW_MAXPASS << SW_LG)) {
+            const int64_t bound = (int64_t)hS.maxv < N ? (int64_t)hS.maxv : N;
+            slab_entries = pow2_host(2 * bound > 64 ? 2 * bound : 64);
+        }
         sgrid = big < (int64_t)cus * SYM_GLOBAL_WG_PER_CU ? big : (int64_t)cus * SYM_GLOBAL_WG_PER_CU;
     }
     for (int b = 7; b >= 0; --b) {
@@ -328,19 +332,22 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
         CHK(launch_symbolic_bin(b, sa, s));
         if (b == 7) {
             // the global-table allocation overlaps the bin-7 kernel (Section 5.4)
-            CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
-            slab = (int *)p;
+            if (slab_entries > 0) {
+                CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
+                slab = (int *)p;
+            }
             SymArgs g = sa;
             g.src = host_rows(fail_list, 0, ssz[7]);
             g.src.count = &ctrS->fail;
             g.slab = slab;
             g.slab_entries = slab_entries;
+            g.sched = ctrS->sched;
             g.grid = ssz[7] < sgrid ? ssz[7] : sgrid;
             CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
         }
     }
     if (ssz[SYM_GLOBAL_BIN] > 0) {
-        if (!slab) {
+        if (!slab && slab_entries > 0) {
             CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
             slab = (int *)p;
         }
@@ -349,6 +356,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
                           (sym_identity == SYM_GLOBAL_BIN) ? 0 : soff[SYM_GLOBAL_BIN], ssz[SYM_GLOBAL_BIN]);
         g.slab = slab;
         g.slab_entries = slab_entries;
+        g.sched = ctrS->sched;
         g.grid = g.src.nrows < sgrid ? g.src.nrows : sgrid;
         CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
     }

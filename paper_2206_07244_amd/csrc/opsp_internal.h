@@ -77,6 +77,8 @@ struct SymArgs {
     int64_t grid;            // fixed grid (persistent launch); 0 = one team per row
     const int2 *rng;         // optional column range of each row (setup step): rows
                              // with a narrow range are counted with a bitmap
+    unsigned long long *sched;  // bin 8: Counters::sched of the launch, zero on entry
+                                // (null: rows assigned round-robin)
 };
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
 

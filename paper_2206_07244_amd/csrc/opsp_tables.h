@@ -32,7 +32,13 @@ constexpr int NUM_W[NUM_NLDS] = {NUM_GL, 64, 128, 256, 512, 1024, 1024};
 constexpr int NUM_GLOBAL_BIN = 7;
 
 // Workgroups per CU that the global-table kernels are sized for.
-constexpr int SYM_GLOBAL_WG_PER_CU = 2;
+constexpr int SYM_GLOBAL_WG_PER_CU = 1;
+
+// Symbolic rows of the global bin with a known column range are counted in
+// an LDS bitmap of 2^SW_LG columns, one pass per window of the range, when
+// the range needs at most SW_MAXPASS windows.
+constexpr int SW_LG = 20;
+constexpr int SW_MAXPASS = 8;
 constexpr int NUM_GLOBAL_WG_PER_CU = 1;
 
 // Columns per LDS bitmap chunk used to order a global-table row.

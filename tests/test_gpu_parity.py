@@ -248,3 +248,39 @@ def test_narrow_and_wide_rows_mixed():
     M = syn.CSR(n, n, np.array(rpt, np.int64), np.concatenate(col).astype(np.int32),
                 np.concatenate(val))
     check(M)
+
+
+def _stack_rows(parts, n_cols):
+    """Rows of several CSR matrices, one after the other, as one matrix with
+    n_cols columns (each part shifted right by its column offset)."""
+    rpt, col, val = [np.zeros(1, np.int64)], [], []
+    for M, shift in parts:
+        rpt.append(rpt[-1][-1] + M.rpt[1:])
+        col.append(M.col.astype(np.int64) + shift)
+        val.append(M.val)
+    rows = sum(M.rows for M, _ in parts)
+    return syn.CSR(rows, n_cols, np.concatenate(rpt), np.concatenate(col).astype(np.int32),
+                   np.concatenate(val))
+
+
+@pytest.mark.parametrize("n_cols", [3 * (1 << 20) + 12345, 9 * (1 << 20) + 7])
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_global_symbolic_bin_wide_ranges(n_cols, hash_all):
+    """Every row forced into the global symbolic bin, with output ranges of
+    a few thousand columns (one bitmap window), of several windows, and (at
+    more than 8 * 2^20 columns) wider than the bitmap takes, which go to the
+    global hash tables; numeric in its own bins and forced to the bucketed
+    kernel."""
+    ops = _ops()
+    Bn = syn.poisson_uniform(1500, 70000, 40.0, seed=1)        # narrow rows of B
+    Bw = syn.poisson_uniform(1500, n_cols, 40.0, seed=2)       # rows over all columns
+    B = _stack_rows([(Bn, n_cols // 2), (Bw, 0)], n_cols)
+    An = syn.poisson_uniform(120, 1500, 50.0, seed=3)          # references narrow rows only
+    Aw = syn.poisson_uniform(120, 3000, 50.0, seed=4)
+    A = _stack_rows([(An, 0), (Aw, 0)], 3000)
+    for force_num in (-1, 7):
+        st = ops.Stats()
+        cfg = ops.Config(force_sym_bin=8, force_num_bin=force_num, validate=1,
+                         hash_all_rows=hash_all)
+        check(A, B, cfg=cfg, stats=st)
+        assert st.sym_bin_rows[8] == A.rows
