@@ -791,6 +791,8 @@ __global__ __launch_bounds__(1024) void k_num_global(
 constexpr int BK_LG = 14;
 constexpr int BK_CW = 1 << BK_LG;   // columns per chunk
 constexpr int BK_NB = 1024;         // chunks per row at most
+constexpr int BK_U = 4;             // staged products in flight per thread
+constexpr int BK_D = 2;             // windows of B loads in flight per wave (beyond the current)
 
 template <bool LRN>
 __global__ __launch_bounds__(1024) void k_num_bucket(
@@ -800,9 +802,12 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
     const int2 *__restrict__ rng, int *stage_keys, double *stage_vals, int64_t stage_cap,
     Counters *__restrict__ ctr, Learn L) {
+    // dense accumulator of one chunk; while the products are counted and
+    // scattered (before any chunk is accumulated) its first BK_NB / 2 words
+    // hold the chunk counters
     __shared__ double dense[BK_CW];
     __shared__ unsigned int bits[BK_CW / 32];
-    __shared__ unsigned int cnt[BK_NB];
+    __shared__ unsigned int wpre[BK_CW / 32];
     __shared__ unsigned int off[BK_NB + 1];
     __shared__ unsigned int red[16];
     __shared__ long long s_base;
@@ -810,6 +815,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
 
     src.resolve();
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+    unsigned int *cc = reinterpret_cast<unsigned int *>(dense);
     int *sk = stage_keys + (int64_t)blockIdx.x * stage_cap;
     double *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
     for (int i = t; i < BK_CW; i += 1024) dense[i] = 0.0;
@@ -840,19 +846,19 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
             continue;
         }
         const int nb = (int)((span + BK_CW - 1) >> BK_LG);
-        for (int b = t; b < nb; b += 1024) cnt[b] = 0u;
+        for (int i = t; i < nb; i += 1024) cc[i] = 0u;
         __syncthreads();
         // 1. products per chunk
-        row_products<false>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
-                            [&](bool ok, int key) {
-                                const uint32_t o = (uint32_t)(key - lo);
-                                if (ok && o < (uint64_t)span) atomicAdd(&cnt[o >> BK_LG], 1u);
-                            },
-                            [] { return false; });
+        row_products<false, BK_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
+                                  [&](bool ok, int key) {
+                                      const uint32_t o = (uint32_t)(key - lo);
+                                      if (ok && o < (uint64_t)span) atomicAdd(&cc[o >> BK_LG], 1u);
+                                  },
+                                  [] { return false; });
         __syncthreads();
         // 2. chunk offsets (exclusive scan, nb <= 1024: one chunk per thread)
         {
-            const unsigned int x = t < nb ? cnt[t] : 0u;
+            const unsigned int x = t < nb ? cc[t] : 0u;
             const unsigned int incl = wave_incl_scan(x);
             if (l == 63) red[wv] = incl;
             __syncthreads();
@@ -863,24 +869,31 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
             }
             if (t < nb) {
                 off[t] = pre + incl - x;
-                cnt[t] = pre + incl - x;   // running fill position of the chunk
+                cc[t] = pre + incl - x;   // running fill position of the chunk
             }
             if (t == 0) off[nb] = tot;
             __syncthreads();
         }
-        // 3. scatter the products into their chunks
-        row_products<true>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
-                           [&](bool ok, int key, double v) {
-                               const uint32_t o = (uint32_t)(key - lo);
-                               if (ok && o < (uint64_t)span) {
-                                   const unsigned int p = atomicAdd(&cnt[o >> BK_LG], 1u);
-                                   sk[p] = key;
-                                   sv[p] = v;
-                               }
-                           },
-                           [] { return false; });
+        // 3. scatter the products into their chunks; lanes of a wave that
+        //    hit one chunk take consecutive positions (coalesced stores)
+        row_products<true, BK_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
+                                 [&](bool ok, int key, double v) {
+                                     const uint32_t o = (uint32_t)(key - lo);
+                                     if (ok && o < (uint64_t)span) {
+                                         const unsigned int p = atomicAdd(&cc[o >> BK_LG], 1u);
+                                         sk[p] = key;
+                                         sv[p] = v;
+                                     }
+                                 },
+                                 [] { return false; });
+        // once every wave has scattered, the counters lent by the dense array
+        // are zeroed, and the staging writes of every wave are visible to the
+        // reads below (plain loads, so that several are in flight per thread)
         __threadfence();
         __syncthreads();
+        for (int i = t; i < BK_NB / 2; i += 1024) dense[i] = 0.0;
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if constexpr (LRN) {
             // the row's size decides where it goes: count the distinct
             // columns chunk by chunk first
@@ -889,9 +902,19 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
                 const unsigned int p0 = off[b], p1 = off[b + 1];
                 if (p0 == p1) continue;   // uniform
                 const int c0 = lo + (b << BK_LG);
-                for (unsigned int p = p0 + t; p < p1; p += 1024) {
-                    const uint32_t o = (uint32_t)(ld_coherent(&sk[p]) - c0);
-                    atomicOr(&bits[o >> 5], 1u << (o & 31));
+                for (unsigned int p = p0 + t; p < p1; p += 1024 * BK_U) {
+                    int kk[BK_U];
+#pragma unroll
+                    for (int u = 0; u < BK_U; ++u) {
+                        const unsigned int q = p + 1024u * u;
+                        kk[u] = q < p1 ? sk[q] : -1;
+                    }
+#pragma unroll
+                    for (int u = 0; u < BK_U; ++u) {
+                        if (kk[u] < 0) continue;
+                        const uint32_t o = (uint32_t)(kk[u] - c0);
+                        atomicOr(&bits[o >> 5], 1u << (o & 31));
+                    }
                 }
                 __syncthreads();
                 unsigned int c = t < BK_CW / 32 ? __popc(bits[t]) : 0u;
@@ -913,21 +936,54 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
             base = (int64_t)s_base;
             if (base < 0) continue;   // uniform; no barrier pending
         }
-        // 4. per chunk: dense accumulation, popcount prefix, emission
+        // 4. per chunk: dense accumulation, popcount prefix, emission.  The
+        //    first staged products of the next nonempty chunk are loaded
+        //    while the current chunk is emitted (chunks of long sparse rows
+        //    hold a few hundred products: their load latency would dominate).
+        //    Outputs are emitted by rank (thread i takes ranks i, i + 1024,
+        //    ...), so that stores to C are coalesced.
         int64_t run = 0;
-        for (int b = 0; b < nb; ++b) {
+        int kk[BK_U];
+        double vv[BK_U];
+        auto preload = [&](int bb) {
+            const unsigned int q0 = off[bb], q1 = off[bb + 1];
+#pragma unroll
+            for (int u = 0; u < BK_U; ++u) {
+                const unsigned int q = q0 + t + 1024u * u;
+                kk[u] = q < q1 ? sk[q] : -1;
+                vv[u] = q < q1 ? sv[q] : 0.0;
+            }
+        };
+        int b = 0;
+        while (b < nb && off[b] == off[b + 1]) ++b;   // uniform
+        if (b < nb) preload(b);
+        while (b < nb) {
             const unsigned int p0 = off[b], p1 = off[b + 1];
-            if (p0 == p1) continue;   // empty chunk (uniform)
             const int c0 = lo + (b << BK_LG);
-            for (unsigned int p = p0 + t; p < p1; p += 1024) {
-                const int key = ld_coherent(&sk[p]);
-                const double v = ld_coherent(&sv[p]);
-                const uint32_t o = (uint32_t)(key - c0);
-                atomicAdd(&dense[o], v);
-                atomicOr(&bits[o >> 5], 1u << (o & 31));
+            auto accumulate = [&]() {
+#pragma unroll
+                for (int u = 0; u < BK_U; ++u) {
+                    if (kk[u] < 0) continue;
+                    const uint32_t o = (uint32_t)(kk[u] - c0);
+                    atomicAdd(&dense[o], vv[u]);
+                    atomicOr(&bits[o >> 5], 1u << (o & 31));
+                }
+            };
+            accumulate();
+            for (unsigned int p = p0 + 1024u * BK_U; p < p1; p += 1024u * BK_U) {
+#pragma unroll
+                for (int u = 0; u < BK_U; ++u) {
+                    const unsigned int q = p + t + 1024u * u;
+                    kk[u] = q < p1 ? sk[q] : -1;
+                    vv[u] = q < p1 ? sv[q] : 0.0;
+                }
+                accumulate();
             }
             __syncthreads();
-            // threads 0..511 own one bitmap word each
+            int bn = b + 1;
+            while (bn < nb && off[bn] == off[bn + 1]) ++bn;   // uniform
+            if (bn < nb) preload(bn);
+            // exclusive popcount prefix over the chunk's words
             const unsigned int wd = t < BK_CW / 32 ? bits[t] : 0u;
             const unsigned int c = __popc(wd);
             const unsigned int incl = wave_incl_scan(c);
@@ -938,24 +994,41 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
                 if (i < wv) pre += red[i];
                 tot += red[i];
             }
-            if (wd) {
-                unsigned int m = wd;
-                int64_t k = run + pre + incl - c;
-                while (m) {
-                    const int bit = __ffs(m) - 1;
-                    m &= m - 1u;
-                    const int o = (t << 5) + bit;
-                    if (k < n) {
-                        ccol[base + k] = c0 + o;
-                        cval[base + k] = dense[o];
-                    }
-                    dense[o] = 0.0;
-                    ++k;
+            if (t < BK_CW / 32) wpre[t] = pre + incl - c;
+            __syncthreads();
+            for (unsigned int k = t; k < tot; k += 1024) {
+                // the word holding rank k: the last word whose prefix is <= k
+                int wlo = 0, whi = BK_CW / 32 - 1;
+                while (wlo < whi) {
+                    const int mid = (wlo + whi + 1) >> 1;
+                    if (wpre[mid] <= k) wlo = mid;
+                    else whi = mid - 1;
                 }
-                bits[t] = 0u;
+                unsigned int m = bits[wlo];
+                int rr = (int)(k - wpre[wlo]);
+                int pos = 0;
+#pragma unroll
+                for (int h = 16; h >= 1; h >>= 1) {
+                    const int ch = __popc(m & ((1u << h) - 1u));
+                    if (rr >= ch) {
+                        rr -= ch;
+                        m >>= h;
+                        pos += h;
+                    }
+                }
+                const int o = (wlo << 5) + pos;
+                const int64_t kr = run + k;
+                if (kr < n) {
+                    ccol[base + kr] = c0 + o;
+                    cval[base + kr] = dense[o];
+                }
+                dense[o] = 0.0;
             }
+            __syncthreads();
+            if (wd) bits[t] = 0u;
             run += tot;
             __syncthreads();
+            b = bn;
         }
         if (t == 0 && run != n) atomicAdd(&ctr->error, 1u);
         __syncthreads();

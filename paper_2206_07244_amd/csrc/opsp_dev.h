@@ -288,19 +288,20 @@ __device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, in
 //    entry by walking (with scalar readlanes) the entries that start inside
 //    the window, after taking the entry that covers the window's first
 //    product.  Used for long or irregular B rows.
-// Windows go round-robin to the waves.  B loads of the next window are issued
-// before the current window's products are handed to `f(ok, key, a * b)`
+// Windows go round-robin to the waves.  B loads of the next D windows are
+// issued before the current window's products are handed to `f(ok, key, a * b)`
 // (`f(ok, key)` for the symbolic step); every lane calls f once per window,
 // `ok` says whether it holds a product.  `stop()` is polled once per window
 // and ends the enumeration for the whole wave.
-template <bool NUMERIC, class F, class Stop>
+template <bool NUMERIC, int D = 1, class F, class Stop>
 __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32_t *__restrict__ acol,
                                              const double *__restrict__ aval,
                                              const int64_t *__restrict__ brpt,
                                              const int32_t *__restrict__ bcol,
-                                             const double *__restrict__ bval, int wv, int nwaves,
+                                             const double *__restrict__ bval, int wv_in, int nwaves,
                                              F &&f, Stop &&stop) {
     const int l = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(wv_in);   // wave-uniform: window indices in SGPRs
     for (int64_t c0 = a0; c0 < a1; c0 += 64) {
         const int64_t j = c0 + l;
         const bool v = j < a1;
@@ -323,6 +324,38 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         const int64_t win_flat = (total + 63) / 64;
         // a flat window costs about twice a grouped one (entry walk)
         const bool grouped = lg <= 6 && win_grouped <= 2 * win_flat;
+        // windows wv, wv + nwaves, ... of nwin with D + 1 windows of loads in
+        // flight: slot d is consumed, then refilled with the window D + 1
+        // places ahead.  Returns true when stop() ended the row.
+        auto pipelined = [&](int64_t nwin, auto &&fetchw) -> bool {
+            constexpr int S = D + 1;
+            int key[S];
+            double bv[S], a[S];
+            bool ok[S];
+#pragma unroll
+            for (int d = 0; d < S; ++d) {
+                key[d] = -1;
+                bv[d] = 0.0;
+                a[d] = 0.0;
+                ok[d] = false;
+                const int64_t w = wv + (int64_t)nwaves * d;
+                if (w < nwin) fetchw(w, key[d], bv[d], a[d], ok[d]);
+            }
+            for (int64_t w = wv; w < nwin; w += (int64_t)nwaves * S) {
+#pragma unroll
+                for (int d = 0; d < S; ++d) {
+                    const int64_t wd = w + (int64_t)nwaves * d;
+                    if (wd < nwin) {
+                        if constexpr (NUMERIC) f(ok[d], key[d], a[d] * bv[d]);
+                        else f(ok[d], key[d]);
+                        if (stop()) return true;
+                        const int64_t wn = wd + (int64_t)nwaves * S;
+                        if (wn < nwin) fetchw(wn, key[d], bv[d], a[d], ok[d]);
+                    }
+                }
+            }
+            return false;
+        };
 
         if (grouped) {
             const int g = l >> lg, r = l & ((1 << lg) - 1);
@@ -338,6 +371,10 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             };
             int64_t w = wv;
             if (w >= win_grouped) continue;
+            if constexpr (D > 1) {
+                if (pipelined(win_grouped, fetch)) break;
+                continue;
+            }
             int key, key1;
             double bv = 0.0, bv1 = 0.0, a = 0.0, a1v = 0.0;
             bool ok, ok1;
@@ -385,6 +422,13 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             const int64_t stride = (int64_t)nwaves * 64;
             int64_t w0 = (int64_t)wv * 64;
             if (w0 >= total) continue;
+            if constexpr (D > 1) {
+                auto fetch_w = [&](int64_t w, int &key, double &bv, double &a, bool &ok) {
+                    fetch(w * 64, key, bv, a, ok);
+                };
+                if (pipelined(win_flat, fetch_w)) break;
+                continue;
+            }
             int key, key1;
             double bv = 0.0, bv1 = 0.0, a = 0.0, a1v = 0.0;
             bool ok, ok1;
@@ -406,5 +450,6 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         if (stop()) break;
     }
 }
+
 
 }  // namespace opsp
