@@ -419,7 +419,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                     atomicAdd(&tv[o], v);
                 }
             };
-            row_products<true>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, acc, [] { return false; });
+            row_products<true, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, acc,
+                                                          [] { return false; });
         }
         team_sync<WT>();
         // exclusive popcount prefix per bitmap word, after the words
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
             if constexpr (LRN) return *(volatile int *)&s_cnt[team] > THR;
             else return false;
         };
-        row_products<true>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
+        row_products<true, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
     }
     team_sync<WT>();
     if constexpr (LRN) {
@@ -700,7 +701,7 @@ __global__ __launch_bounds__(1024) void k_num_global(
             if constexpr (LRN) return *(volatile unsigned int *)&s_cnt > thr;
             else return false;
         };
-        row_products<true>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, 16, ins, stop);
+        row_products<true, WIDE_D>(arpt[row], arpt[row + 1], acol, aval, brpt, bcol, bval, wv, 16, ins, stop);
         kmin = wave_min(kmin);
         kmax = wave_max(kmax);
         if (l == 0) {
@@ -792,7 +793,6 @@ constexpr int BK_LG = 14;
 constexpr int BK_CW = 1 << BK_LG;   // columns per chunk
 constexpr int BK_NB = 1024;         // chunks per row at most
 constexpr int BK_U = 4;             // staged products in flight per thread
-constexpr int BK_D = 2;             // windows of B loads in flight per wave (beyond the current)
 
 template <bool LRN>
 __global__ __launch_bounds__(1024) void k_num_bucket(
@@ -849,7 +849,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         for (int i = t; i < nb; i += 1024) cc[i] = 0u;
         __syncthreads();
         // 1. products per chunk
-        row_products<false, BK_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
+        row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
                                   [&](bool ok, int key) {
                                       const uint32_t o = (uint32_t)(key - lo);
                                       if (ok && o < (uint64_t)span) atomicAdd(&cc[o >> BK_LG], 1u);
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         }
         // 3. scatter the products into their chunks; lanes of a wave that
         //    hit one chunk take consecutive positions (coalesced stores)
-        row_products<true, BK_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
+        row_products<true, WIDE_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
                                  [&](bool ok, int key, double v) {
                                      const uint32_t o = (uint32_t)(key - lo);
                                      if (ok && o < (uint64_t)span) {

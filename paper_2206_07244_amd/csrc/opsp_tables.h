@@ -38,6 +38,11 @@ constexpr int SYM_GLOBAL_WG_PER_CU = 1;
 // an LDS bitmap of 2^SW_LG columns, one pass per window of the range, when
 // the range needs at most SW_MAXPASS windows.
 constexpr int SW_LG = 20;
+
+// Windows of B loads in flight per wave beyond the current one in the
+// kernels that give a row 512 or more threads (long rows: few waves per CU
+// to hide the load latency).
+constexpr int WIDE_D = 2;
 constexpr int SW_MAXPASS = 8;
 constexpr int NUM_GLOBAL_WG_PER_CU = 1;
 
