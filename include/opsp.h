@@ -131,7 +131,8 @@ typedef struct {
     int64_t slot_overflow_rows;   /* rows with nnz above their capacity, stored in the arena */
     int64_t table_overflow_rows;  /* rows whose hash table filled up (recomputed exactly) */
     int64_t retry_rows;           /* rows recomputed exactly (table full or arena exhausted) */
-    double calib_scale;           /* scale applied to the network's estimates (1 = none) */
+    double calib_scale;           /* calibration sample: sum of exact sizes / sum of the
+                                   * estimates over all counted rows (1 = none) */
 } opsp_stats;
 
 typedef struct opsp_plan opsp_plan;       /* opaque */
@@ -231,9 +232,9 @@ opsp_status opsp_spgemm_batched(int32_t count, const opsp_csr *A, const opsp_csr
  *   capacity  cap_i = ceil((2^y_i - 1) c (1 + margin)) clamped to
  *             [min(b_max_i, U_i), U_i] with U_i = min(n_prod_i, N); a row
  *             with a_len_i <= 1 gets n_prod_i (exact); c is the calibration
- *             factor of a small exactly counted sample of rows (see
- *             calib_rows), which corrects the network's bias on the input at
- *             hand.
+ *             factor of the row's n_prod octave from a small exactly counted
+ *             sample of rows (see calib_rows), which corrects the network's
+ *             bias on the input at hand (1 where the sample has too few rows).
  * Whatever the capacities, the result is the C of opsp_spgemm (same
  * structure; values summed in unspecified order): a row that outgrows its
  * capacity is stored in an overflow arena, and a row whose hash table fills
@@ -256,11 +257,16 @@ typedef struct {
                                * after clamping (0 = 1), e.g. 0.1 to overflow rows */
     float *pred_out;          /* optional device float[A.rows]: network outputs y_i */
     int64_t *cap_out;         /* optional device int64[A.rows]: capacities */
-    /* Kind MLP: calibration sample size.  Rows 0, S, 2S, ... (S =
-     * ceil(rows / calib_rows)) with a_len >= 2 and n_prod <= 2048 are counted
-     * exactly on the device, and every estimate 2^y_i - 1 is multiplied by
-     * (sum of their sizes) / (sum of their estimates clamped as above)
-     * before the margin.  0 = 2048 rows; negative = no calibration. */
+    /* Kind MLP: calibration, the most rows sampled per octave of n_prod.
+     * Rows with a_len >= 2, 1 <= n_prod < 2^21 and an output column range
+     * of at most 2^23 columns are grouped by o = floor(log2 n_prod); of an octave's
+     * c rows, about K = min(c, clamp(2^24 >> o, 4, calib_rows)) are picked
+     * (row i when h(i) mod ceil(c / K) == 0, h the high 32 bits of
+     * i * 0x9E3779B97F4A7C15) and counted exactly on the device.  In an
+     * octave with at least 4 counted rows every row's estimate 2^y_i - 1 is
+     * multiplied by (sum of the counted sizes) / (sum of their estimates
+     * clamped as above) before the margin; other rows are not scaled.
+     * 0 = 64; negative = no calibration. */
     int32_t calib_rows;
     int32_t reserved;
 } opsp_predictor;

@@ -176,38 +176,92 @@ def adam_step(theta, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def calibration(pred_log2, nnz_exact, alen, nprod, bmax, ncols, target=2048, max_nprod=2048):
-    """Scale of the network's estimates from an exactly counted sample:
-    rows 0, S, 2S, ... (S = ceil(M / target)) with a_len >= 2 and
-    n_prod <= max_nprod; scale = sum of their sizes / sum of their estimates
-    2^pred - 1 clamped to [min(b_max, U), U], U = min(n_prod, N) (1 when the
-    sample is empty).  nnz_exact(rows) returns the exact sizes of the listed
-    rows.  Returns (scale, sampled rows)."""
-    M = len(alen)
-    if M == 0:
-        return 1.0, np.zeros(0, np.int64)
-    stride = -(-M // target)
-    rows = np.arange(0, M, stride)
+CAL_SPAN_MAX = 8 << 20     # widest column range a sampled row may have
+CAL_OCT_PRODUCTS = 1 << 24 # products sampled per octave (about)
+CAL_MIN_ROWS = 4           # sampled rows an octave needs to be scaled
+CAL_MAX_OCT = 20           # rows of larger octaves (n_prod >= 2^21) are not sampled
+
+
+def row_ranges(A, B):
+    """(lo, hi) column range of every row of A*B: the smallest first and the
+    largest last column of the B rows it references (lo > hi when the row
+    has no products)."""
+    blen = np.diff(B.rpt)
+    bcol = np.asarray(B.col, np.int64)
+    if bcol.size == 0:
+        bcol = np.zeros(1, np.int64)
+    first = np.where(blen > 0, bcol[np.minimum(B.rpt[:-1], bcol.size - 1)], np.iinfo(np.int64).max)
+    last = np.where(blen > 0, bcol[np.maximum(B.rpt[1:] - 1, 0)], -1)
+    lo = np.full(A.rows, np.iinfo(np.int64).max)
+    hi = np.full(A.rows, -1)
+    rows = np.repeat(np.arange(A.rows), np.diff(A.rpt))
+    if rows.size:
+        np.minimum.at(lo, rows, first[A.col])
+        np.maximum.at(hi, rows, last[A.col])
+    return lo, hi
+
+
+def calibration_pick(alen, nprod, span, per_octave=64):
+    """Rows counted exactly for the calibration, by a rule both sides apply
+    in integer arithmetic.  Eligible rows have a_len >= 2,
+    1 <= n_prod < 2^(CAL_MAX_OCT + 1) and a column range of at most
+    CAL_SPAN_MAX columns; they are grouped by octave o = floor(log2 n_prod).  An octave with c eligible rows takes
+    K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)) of
+    them on average: row i is picked when h(i) mod ceil(c / K) == 0, with
+    h(i) the high 32 bits of the 64-bit product i * 0x9E3779B97F4A7C15
+    (Fibonacci hashing, so the picks spread over the octave's rows).
+    Returns the picked rows (ascending) and every row's octave."""
+    alen, nprod, span = (np.asarray(a, np.int64) for a in (alen, nprod, span))
+    M = nprod.size
+    octave = np.where(nprod >= 1, np.floor(np.log2(np.maximum(nprod, 1))).astype(np.int64), -1)
+    elig = (alen >= 2) & (nprod >= 1) & (octave <= CAL_MAX_OCT) & (span <= CAL_SPAN_MAX)
+    picked = np.zeros(M, bool)
+    idx = np.arange(M, dtype=np.uint64)
+    h = ((idx * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(32)).astype(np.int64)
+    for o in np.unique(octave[elig]):
+        sel = elig & (octave == o)
+        c = int(sel.sum())
+        k = min(c, min(max(CAL_OCT_PRODUCTS >> int(o), CAL_MIN_ROWS), per_octave))
+        stride = -(-c // k)
+        picked |= sel & (h % stride == 0)
+    return np.nonzero(picked)[0], octave
+
+
+def calibration(pred_log2, nnz_exact, alen, nprod, bmax, ncols, span, per_octave=64):
+    """Per-octave scales of the network's estimates from the rows of
+    calibration_pick, counted exactly by nnz_exact(rows).  An octave with at
+    least CAL_MIN_ROWS picked rows gets the scale (sum of their sizes) / (sum
+    of their estimates 2^pred - 1 clamped to [min(b_max, U), U],
+    U = min(n_prod, N)), and every row of that octave (n_prod >= 1) is scaled
+    by it; other rows keep 1.  Returns (scale of every row, overall ratio over
+    all picked rows (1 when none), picked rows)."""
     alen, nprod, bmax = (np.asarray(a, np.int64) for a in (alen, nprod, bmax))
-    rows = rows[(alen[rows] >= 2) & (nprod[rows] <= max_nprod)]
+    scale = np.ones(nprod.size)
+    rows, octave = calibration_pick(alen, nprod, span, per_octave)
     if rows.size == 0:
-        return 1.0, rows
+        return scale, 1.0, rows
     hi = np.minimum(nprod[rows], ncols).astype(np.float64)
     lo = np.minimum(bmax[rows], hi).astype(np.float64)
     est = np.clip(np.exp2(np.asarray(pred_log2, np.float64)[rows]) - 1.0, lo, hi)
-    tot = est.sum()
-    if tot <= 0:
-        return 1.0, rows
-    return float(np.sum(nnz_exact(rows)) / tot), rows
+    ex = np.asarray(nnz_exact(rows), np.float64)
+    o_rows = octave[rows]
+    for o in np.unique(o_rows):
+        sel = o_rows == o
+        if sel.sum() >= CAL_MIN_ROWS and est[sel].sum() > 0:
+            scale[(octave == o) & (nprod >= 1)] = ex[sel].sum() / est[sel].sum()
+    overall = float(ex.sum() / est.sum()) if est.sum() > 0 else 1.0
+    return scale, overall, rows
 
 
 def capacity(pred_log2, margin, alen, nprod, bmax, ncols, scale=1.0) -> np.ndarray:
     """Slot capacity of each row from a prediction of log2(1 + nnz):
-    ceil((2^pred - 1) * scale * (1 + margin)) clamped to
+    ceil((2^pred - 1) * scale * (1 + margin)) (scale a number or one per
+    row) clamped to
     [b_max, min(n_prod, ncols)], since a row of C holds at least its longest
     referenced B row and at most min(n_prod, N) entries; a row with at most
     one A entry has exactly n_prod entries.  Evaluated in float64."""
-    est = np.ceil((np.exp2(np.asarray(pred_log2, np.float64)) - 1.0) * scale * (1.0 + margin))
+    est = np.ceil((np.exp2(np.asarray(pred_log2, np.float64)) - 1.0) * np.asarray(scale, np.float64)
+                  * (1.0 + margin))
     nprod = np.asarray(nprod, np.int64)
     hi = np.minimum(nprod, ncols)
     lo = np.minimum(np.asarray(bmax, np.int64), hi)

@@ -197,7 +197,7 @@ def class_inputs(cls: str):
         A = syn.stencil27(60, seed=60)
         return [(A, A)]
     if cls == "rmat":
-        A = syn.rmat(16, 16, seed=16)
+        A = syn.rmat(18, 16, seed=18)
         return [(A, A)]
     if cls == "banded":
         A = syn.banded(1 << 19, 64, 12, seed=19)

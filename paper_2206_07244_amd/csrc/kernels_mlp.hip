@@ -216,9 +216,18 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
     __syncthreads();
     const int l = lane_id(), r = l & 15, q = l >> 4, wv = threadIdx.x >> 6;
     const bool run_net = c.kind == 0 && !c.pred_in;
-    // sampled calibration: exact / estimated sizes of the sampled rows
-    double cal = 1.0;
-    if (c.kind == 0 && c.calib && c.calib[1] > 0.0) cal = c.calib[0] / c.calib[1];
+    // sampled calibration: exact / estimated sizes of the sampled rows of
+    // each n_prod octave that has enough of them
+    __shared__ double s_cal[CAL_OCT];
+    if (threadIdx.x < CAL_OCT) {
+        const int o = threadIdx.x;
+        double v = 1.0;
+        if (c.kind == 0 && c.calib && c.calib[2 * CAL_OCT + o] >= (double)CAL_MIN_ROWS &&
+            c.calib[CAL_OCT + o] > 0.0)
+            v = c.calib[o] / c.calib[CAL_OCT + o];
+        s_cal[o] = v;
+    }
+    __syncthreads();
     MlpLane w;
     if (run_net) mlp_load(c.P, w);
     unsigned long long tot = 0, mx = 0, nps = 0, npm = 0;
@@ -244,6 +253,7 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
             if (row < M) {
                 if (c.pred_in) v = c.pred_in[row];
                 const int64_t np = nprod[row];
+                const double cal = np >= 1 ? s_cal[63 - __clzll(np)] : 1.0;
                 const int64_t cp = cap_of(c, v, alen[row], np, bmax[row], cal);
                 cap[row] = cp;
                 if (c.pred && !c.pred_in) c.pred[row] = v;
@@ -308,59 +318,80 @@ __global__ __launch_bounds__(256) void k_mlp_pred(int64_t M, const uint16_t *__r
     }
 }
 
-// Calibration sample: one wave per sampled row counts its distinct columns
-// exactly with an LDS hash table (twice the largest sampled n_prod) and adds
-// (exact size, clamped estimate) into the two sums.
-constexpr int CAL_T = 2 * (int)CALIB_MAX_NPROD;
+// Calibration sample (rule of launch_cal_hist / launch_cal_pick).
+__device__ __forceinline__ bool cal_eligible(int32_t alen, int64_t np, int2 rg) {
+    return alen >= 2 && np >= 1 && np < ((int64_t)2 << CAL_MAX_OCT) &&
+           (int64_t)rg.y - rg.x + 1 <= CAL_SPAN_MAX;
+}
 
-__global__ __launch_bounds__(256) void k_calib(int64_t M, int64_t stride, int64_t ncols,
-                                               const int64_t *__restrict__ arpt,
-                                               const int32_t *__restrict__ acol,
-                                               const int64_t *__restrict__ brpt,
-                                               const int32_t *__restrict__ bcol,
-                                               const int32_t *__restrict__ alen,
-                                               const int64_t *__restrict__ nprod,
-                                               const int32_t *__restrict__ bmax,
-                                               const float *__restrict__ pred,
-                                               double *__restrict__ calib,
-                                               unsigned int *__restrict__ err) {
-    __shared__ int tab[4][CAL_T];
-    __shared__ double s_sum[2][4];
-    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t k = (int64_t)blockIdx.x * 4 + wv;   // sample index
-    const int64_t row = k * stride;
-    double ex = 0.0, es = 0.0;
-    const bool take = row < M && alen[row] >= 2 && nprod[row] <= CALIB_MAX_NPROD;
-    if (take) {   // uniform over the wave
-        int *tb = tab[wv];
-        for (int s = l; s < CAL_T; s += 64) tb[s] = -1;
-        wave_lds_sync();
-        int cnt = 0;
-        row_products<false>(arpt[row], arpt[row + 1], acol, nullptr, brpt, bcol, nullptr, 0, 1,
-                            [&](bool ok, int key) { cnt += sym_insert_wave(tb, (uint32_t)CAL_T, ok, key, err); },
-                            [] { return false; });
-        cnt = wave_sum(cnt);
+// Rows per n_prod octave among the eligible rows.
+__global__ __launch_bounds__(256) void k_cal_hist(int64_t M, const int32_t *__restrict__ alen,
+                                                  const int64_t *__restrict__ nprod,
+                                                  const int2 *__restrict__ rng,
+                                                  unsigned long long *__restrict__ hist) {
+    __shared__ unsigned int h[CAL_OCT];
+    if (threadIdx.x < CAL_OCT) h[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
+        const int64_t np = nprod[i];
+        if (cal_eligible(alen[i], np, rng[i])) atomicAdd(&h[63 - __clzll(np)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < CAL_OCT && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// Stride of every octave from its count c: ceil(c / K) with
+// K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)).
+__global__ void k_cal_strides(const unsigned long long *__restrict__ hist, int64_t per_octave,
+                              unsigned long long *__restrict__ stride) {
+    const int o = threadIdx.x;
+    if (o >= CAL_OCT) return;
+    const int64_t c = (int64_t)hist[o];
+    int64_t k = o < 62 ? (CAL_OCT_PRODUCTS >> o) : 0;
+    k = k < CAL_MIN_ROWS ? CAL_MIN_ROWS : (k > per_octave ? per_octave : k);
+    k = k < c ? k : c;
+    stride[o] = c > 0 ? (unsigned long long)((c + k - 1) / k) : 0ull;
+}
+
+// Eligible row i of octave o is picked when h(i) mod stride[o] == 0, h(i)
+// the high half of i * 0x9E3779B97F4A7C15 (Fibonacci hashing); picked rows
+// are appended to `list` (which holds M entries, so it cannot overflow).
+__global__ __launch_bounds__(256) void k_cal_pick(int64_t M, const int32_t *__restrict__ alen,
+                                                  const int64_t *__restrict__ nprod,
+                                                  const int2 *__restrict__ rng,
+                                                  const unsigned long long *__restrict__ stride,
+                                                  int32_t *__restrict__ list,
+                                                  unsigned int *__restrict__ count) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
+        const int64_t np = nprod[i];
+        if (!cal_eligible(alen[i], np, rng[i])) continue;
+        const unsigned long long sd = stride[63 - __clzll(np)];
+        const unsigned long long h = ((unsigned long long)i * 0x9E3779B97F4A7C15ull) >> 32;
+        if (sd && h % sd == 0) list[atomicAdd(count, 1u)] = (int32_t)i;
+    }
+}
+
+// Sums of the picked rows per octave: exact size, clamped estimate, 1.
+__global__ __launch_bounds__(256) void k_cal_sum(const int32_t *__restrict__ list,
+                                                 const unsigned int *__restrict__ count,
+                                                 const int64_t *__restrict__ nprod,
+                                                 const int32_t *__restrict__ bmax,
+                                                 const float *__restrict__ pred,
+                                                 const int64_t *__restrict__ exact, int64_t ncols,
+                                                 double *__restrict__ calib) {
+    const int64_t n = (int64_t)*count;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        const int64_t row = list[k];
         const int64_t np = nprod[row];
         const int64_t hi = np < ncols ? np : ncols;
         const int64_t bm = bmax[row];
         const double lo = (double)(bm < hi ? bm : hi);
         double e = exp2((double)pred[row]) - 1.0;
         e = e < lo ? lo : (e > (double)hi ? (double)hi : e);
-        ex = (double)cnt;
-        es = e;
-    }
-    if (l == 0) {
-        s_sum[0][wv] = ex;
-        s_sum[1][wv] = es;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double a = s_sum[0][0] + s_sum[0][1] + s_sum[0][2] + s_sum[0][3];
-        const double b = s_sum[1][0] + s_sum[1][1] + s_sum[1][2] + s_sum[1][3];
-        if (b > 0.0) {
-            unsafeAtomicAdd(&calib[0], a);
-            unsafeAtomicAdd(&calib[1], b);
-        }
+        const int o = 63 - __clzll(np);
+        unsafeAtomicAdd(&calib[o], (double)exact[row]);
+        unsafeAtomicAdd(&calib[CAL_OCT + o], e);
+        unsafeAtomicAdd(&calib[2 * CAL_OCT + o], 1.0);
     }
 }
 
@@ -585,15 +616,31 @@ hipError_t launch_mlp_pred(int64_t M, const uint16_t *P, const int32_t *alen, co
     return hipGetLastError();
 }
 
-hipError_t launch_calib(const DevCSR &A, const DevCSR &B, int64_t target, const int32_t *alen,
-                        const int64_t *nprod, const int32_t *bmax, const float *pred,
-                        double *calib, unsigned int *err, hipStream_t s) {
-    const int64_t M = A.rows;
-    if (M <= 0 || target <= 0) return hipSuccess;
-    const int64_t stride = (M + target - 1) / target;
-    const int64_t ns = (M + stride - 1) / stride;
-    hipLaunchKernelGGL(k_calib, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, s, M, stride, B.cols,
-                       A.rpt, A.col, B.rpt, B.col, alen, nprod, bmax, pred, calib, err);
+hipError_t launch_cal_hist(int64_t M, const int32_t *alen, const int64_t *nprod, const int2 *rng,
+                           unsigned long long *hist, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    const int64_t g = (M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_cal_hist, dim3((unsigned)g), dim3(256), 0, s, M, alen, nprod, rng, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_cal_pick(int64_t M, const int32_t *alen, const int64_t *nprod, const int2 *rng,
+                           const unsigned long long *hist, int64_t per_octave,
+                           unsigned long long *stride, int32_t *list, unsigned int *count,
+                           hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cal_strides, dim3(1), dim3(CAL_OCT), 0, s, hist, per_octave, stride);
+    const int64_t g = (M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_cal_pick, dim3((unsigned)g), dim3(256), 0, s, M, alen, nprod, rng, stride, list,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t launch_cal_sum(const int32_t *list, const unsigned int *count, const int64_t *nprod,
+                          const int32_t *bmax, const float *pred, const int64_t *exact, int64_t ncols,
+                          double *calib, hipStream_t s) {
+    hipLaunchKernelGGL(k_cal_sum, dim3(64), dim3(256), 0, s, list, count, nprod, bmax, pred, exact, ncols,
+                       calib);
     return hipGetLastError();
 }
 

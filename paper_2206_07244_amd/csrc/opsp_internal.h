@@ -137,7 +137,7 @@ struct CapArgs {
     int64_t ncols;
     float *pred;             // optional: the network's outputs (written)
     const float *pred_in;    // network outputs computed before (NULL = run it here)
-    const double *calib;     // [exact nnz, estimate] sums of the sampled rows, or NULL
+    const double *calib;     // calibration sums [3][CAL_OCT] (launch_cal_sum), or NULL
 };
 hipError_t launch_mlp_caps(int64_t M, const CapArgs &ca, const int32_t *alen, const int64_t *nprod,
                            const int32_t *bmax, int64_t *cap, const Bounds &bd,
@@ -145,13 +145,33 @@ hipError_t launch_mlp_caps(int64_t M, const CapArgs &ca, const int32_t *alen, co
 // Network outputs for every row from the integer features.
 hipError_t launch_mlp_pred(int64_t M, const uint16_t *P, const int32_t *alen, const int64_t *nprod,
                            const int32_t *bmax, float *pred, hipStream_t s);
-// Calibration sample: rows 0, S, 2S, ... (S = ceil(M / target)) with
-// 2 <= a_len and n_prod <= CALIB_MAX_NPROD are counted exactly; calib[0] +=
-// their sizes, calib[1] += their clamped estimates 2^pred - 1 (calib zeroed
-// before).
-constexpr int64_t CALIB_MAX_NPROD = 2048;
-hipError_t launch_calib(const DevCSR &A, const DevCSR &B, int64_t target, const int32_t *alen,
-                        const int64_t *nprod, const int32_t *bmax, const float *pred,
-                        double *calib, unsigned int *err, hipStream_t s);
+// Calibration sample of the predicted sizes.  Eligible rows have a_len >= 2,
+// 1 <= n_prod < 2^(CAL_MAX_OCT + 1) and a column range of at most
+// CAL_SPAN_MAX columns (so that the bin-8 bitmap kernel counts them); they
+// are grouped by the octave o = floor(log2 n_prod).  launch_cal_hist adds
+// the number of eligible rows of each octave into hist[CAL_OCT];
+// launch_cal_pick turns an octave's count c into stride[o] = ceil(c / K),
+// K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)), and
+// appends the eligible rows with h(i) mod stride[o] == 0 to `list` (h:
+// Fibonacci hash of the row index); after the picked rows are counted exactly into exact[row],
+// launch_cal_sum adds, per octave, their sizes into calib[o], their estimates
+// 2^pred - 1 clamped to [min(b_max, U), U] into calib[CAL_OCT + o] and 1 into
+// calib[2 CAL_OCT + o] (calib zeroed before).  The capacity kernel scales
+// the rows of an octave with at least CAL_MIN_ROWS counted rows by
+// calib[o] / calib[CAL_OCT + o]; other rows are not scaled.
+constexpr int CAL_OCT = 64;
+constexpr int64_t CAL_SPAN_MAX = (int64_t)SW_MAXPASS << SW_LG;
+constexpr int64_t CAL_OCT_PRODUCTS = (int64_t)1 << 24;
+constexpr int CAL_MIN_ROWS = 4;
+constexpr int CAL_MAX_OCT = 20;
+hipError_t launch_cal_hist(int64_t M, const int32_t *alen, const int64_t *nprod, const int2 *rng,
+                           unsigned long long *hist, hipStream_t s);
+hipError_t launch_cal_pick(int64_t M, const int32_t *alen, const int64_t *nprod, const int2 *rng,
+                           const unsigned long long *hist, int64_t per_octave,
+                           unsigned long long *stride, int32_t *list, unsigned int *count,
+                           hipStream_t s);
+hipError_t launch_cal_sum(const int32_t *list, const unsigned int *count, const int64_t *nprod,
+                          const int32_t *bmax, const float *pred, const int64_t *exact, int64_t ncols,
+                          double *calib, hipStream_t s);
 
 }  // namespace opsp

@@ -21,6 +21,7 @@
 //                 the scan again (a third read-back);
 //   6 copy        C allocated, rows copied from slots / arenas into C.
 #include <cmath>
+#include <cstddef>
 #include <new>
 #include <string.h>
 
@@ -48,9 +49,13 @@ struct LearnedCounters {
     Counters num;      // numeric bins by capacity; total = sum of capacities
     Counters scan;     // scan of the exact row sizes; total = nnz(C)
     LearnCtr lc;
-    double calib[2];   // calibration sample: sum of exact sizes, sum of estimates
+    double calib[3 * CAL_OCT];            // calibration sums per n_prod octave
+    unsigned long long cal_hist[CAL_OCT];  // eligible rows per octave
+    unsigned long long cal_stride[CAL_OCT];
+    unsigned long long cal_sched[2];       // row counter of the exact count
+    unsigned int cal_n;                    // picked rows
 };
-constexpr int64_t CALIB_ROWS_DEFAULT = 2048;
+constexpr int64_t CAL_PER_OCTAVE_DEFAULT = 64;
 static_assert(sizeof(LearnedCounters) <= PINNED_BYTES, "read-back buffer");
 
 opsp_status check_predictor(const opsp_predictor *p) {
@@ -111,9 +116,11 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M * 4));
     int32_t *alen = (int32_t *)p, *bmax = alen + M, *bins = alen + 2 * M, *retry = alen + 3 * M;
     const bool ranges = !(cfg && cfg->version >= 2 && cfg->hash_all_rows);
+    const int64_t cal_k = pr->calib_rows == 0 ? CAL_PER_OCTAVE_DEFAULT : pr->calib_rows;
+    const bool calib = pr->kind == OPSP_PRED_MLP && cal_k > 0;
     int2 *rng = nullptr;
     int4 *bfl = nullptr;   // output column range per row, B's row bounds
-    if (ranges) {
+    if (ranges || calib) {   // the calibration needs the ranges too
         CHK(ar.alloc(&p, sizeof(int2) * (size_t)M));
         rng = (int2 *)p;
         CHK(ar.alloc(&p, sizeof(int4) * (size_t)(B->rows > 0 ? B->rows : 1)));
@@ -134,7 +141,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
 
     // 1-2 setup, capacities, numeric bins by capacity, slot offsets
     tm.mark();
-    CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnCtr) + 2 * sizeof(double), s));
+    CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnedCounters) - offsetof(LearnedCounters, lc), s));
     if (bfl) CHK(launch_brange(dB, bfl, s));
     CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s, bfl, rng));
     CapArgs ca;
@@ -146,17 +153,36 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     ca.scale = pr->cap_scale > 0 ? pr->cap_scale : 1.0;
     ca.ncols = N;
     ca.pred = pr->pred_out;
-    const int64_t calib_rows = pr->calib_rows == 0 ? CALIB_ROWS_DEFAULT : pr->calib_rows;
-    if (pr->kind == OPSP_PRED_MLP && calib_rows > 0) {
-        // network outputs first, then the exactly counted sample, then the
-        // calibrated capacities
+    if (calib) {
+        // network outputs first, then the exactly counted sample (picked
+        // per octave of n_prod), then the calibrated capacities
         float *pred = pr->pred_out;
         if (!pred) {
             CHK(ar.alloc(&p, sizeof(float) * (size_t)M));
             pred = (float *)p;
         }
         CHK(launch_mlp_pred(M, pr->params, alen, np, bmax, pred, s));
-        CHK(launch_calib(dA, dB, calib_rows, alen, np, bmax, pred, dc->calib, &dc->lc.error, s));
+        CHK(launch_cal_hist(M, alen, np, rng, dc->cal_hist, s));
+        CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M));
+        int32_t *list = (int32_t *)p;
+        CHK(ar.alloc(&p, sizeof(int64_t) * (size_t)M));
+        int64_t *exact = (int64_t *)p;
+        CHK(launch_cal_pick(M, alen, np, rng, dc->cal_hist, cal_k, dc->cal_stride, list, &dc->cal_n, s));
+        // exact sizes of the picked rows: the bin-8 bitmap windows (every
+        // picked range fits them), one row per workgroup from a counter
+        SymArgs g;
+        memset(&g, 0, sizeof(g));
+        g.A = dA;
+        g.B = dB;
+        g.nnz = exact;
+        g.src.bins = list;
+        g.src.count = &dc->cal_n;
+        g.ctr = &dc->num;
+        g.rng = rng;
+        g.sched = dc->cal_sched;
+        g.grid = cus;
+        CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
+        CHK(launch_cal_sum(list, &dc->cal_n, np, bmax, pred, exact, N, dc->calib, s));
         ca.pred_in = pred;
         ca.calib = dc->calib;
     }
@@ -172,7 +198,14 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     S.nprod = (int64_t)hc.lc.nprod_total;
     S.max_row_nprod = (int64_t)hc.lc.nprod_max;
     S.cap_total = cap_total;
-    S.calib_scale = hc.calib[1] > 0.0 ? hc.calib[0] / hc.calib[1] : 1.0;
+    {
+        double ex = 0.0, es = 0.0;
+        for (int o = 0; o < CAL_OCT; ++o) {
+            ex += hc.calib[o];
+            es += hc.calib[CAL_OCT + o];
+        }
+        S.calib_scale = es > 0.0 ? ex / es : 1.0;   // the sample's overall ratio
+    }
     if (cap_max > INT32_MAX) return OPSP_ERR_OVERFLOW;
     int64_t nsz[OPSP_NUM_BINS], noff[OPSP_NUM_BINS];
     for (int j = 0; j < OPSP_NUM_BINS; ++j) {
@@ -195,7 +228,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     na.ccol = tcol;
     na.cval = tval;
     na.ctr = &dc->num;
-    na.rng = rng;
+    na.rng = ranges ? rng : nullptr;
     na.lrn.mode = 1;
     na.lrn.off = off;
     na.lrn.nprod = np;
@@ -211,7 +244,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         if (nsz[b] == 0) continue;
         na.src = host_rows(bins, noff[b], nsz[b]);
         na.grid = 0;
-        if (b == NUM_GLOBAL_BIN && rng && N <= BUCKET_MAX_COLS) {
+        if (b == NUM_GLOBAL_BIN && ranges && N <= BUCKET_MAX_COLS) {
             // long rows: bucketed dense accumulation (never overflows)
             void *pk = nullptr, *pv = nullptr;
             const int64_t grid = bucket_grid(nsz[b], cus, S.max_row_nprod);
@@ -272,7 +305,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         ra.lrn.arena_cap = ub;
         // the second arena starts empty: count its use from zero
         CHK(hipMemsetAsync(&dc->lc.arena_used, 0, sizeof(unsigned long long), s));
-        if (rng && N <= BUCKET_MAX_COLS) {
+        if (ranges && N <= BUCKET_MAX_COLS) {
             // bucketed dense accumulation: staging for the longest row
             const int64_t sc = S.max_row_nprod > 1 ? S.max_row_nprod : 1;
             const int64_t g2 = bucket_grid(nretry, cus, sc);

@@ -135,25 +135,29 @@ def test_arena_exhaustion_recomputes_rows(hash_all):
     assert st.arena_entries > 0 and st.retry_rows > 0
 
 
-@pytest.mark.parametrize("calib_rows", [-1, 0, 300])
+@pytest.mark.parametrize("calib_rows", [-1, 0, 5])
 def test_capacities_follow_the_rule(calib_rows):
     """Capacities reported by the call equal the rule applied (in float64, as
-    the kernel does) to the network outputs it reports, scaled by the
-    calibration of the sampled rows (counted exactly by the oracle), and obey
-    the bounds."""
+    the kernel does) to the network outputs it reports, scaled per n_prod
+    octave by the calibration of the rows the oracle's rule picks (counted
+    exactly by the oracle), and obey the bounds."""
     A = syn.rmat(12, 16, seed=12)
     pred = rand_predictor(seed=12, margin=0.25, calib_rows=calib_rows)
     st, caps, y = run(A, None, pred, want_caps=True)
     nprod, alen, bmax, _ = oracle.row_stats(A, A)
     scale = 1.0
     if calib_rows >= 0:
-        scale, rows = mlp.calibration(y.astype(np.float64), lambda r: oracle.symbolic(A, A, r), alen,
-                                      nprod, bmax, A.cols, target=calib_rows or 2048)
-        assert rows.size > 0
-        assert abs(st.calib_scale - scale) <= 1e-9 * scale
+        lo, hi = mlp.row_ranges(A, A)
+        scale, overall, rows = mlp.calibration(y.astype(np.float64), lambda r: oracle.symbolic(A, A, r),
+                                               alen, nprod, bmax, A.cols, span=hi - lo + 1,
+                                               per_octave=calib_rows or 64)
+        assert rows.size > 0 and np.any(scale != 1.0)
+        # octaves of long rows are sampled too
+        assert nprod[rows].max() > 4096
+        assert abs(st.calib_scale - overall) <= 1e-9 * overall
     else:
         assert st.calib_scale == 1.0
-    ref = mlp.capacity(y.astype(np.float64), 0.25, alen, nprod, bmax, A.cols, scale=st.calib_scale)
+    ref = mlp.capacity(y.astype(np.float64), 0.25, alen, nprod, bmax, A.cols, scale=scale)
     hi = np.minimum(nprod, A.cols)
     assert np.all((caps >= np.minimum(bmax, hi)) | (alen <= 1))
     assert np.all((caps <= hi) | (alen <= 1))

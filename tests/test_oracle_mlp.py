@@ -211,20 +211,62 @@ def test_pinball_level_is_the_empirical_quantile():
     assert abs(th[-1] - np.quantile(tgt, 0.9)) < 0.08
 
 
-def test_calibration_sample_and_scale():
-    """Sampling rule and scale on a hand-checked case: every second row is
-    sampled (M = 8, target 4), rows with a_len < 2 or large n_prod are
-    skipped, estimates are clamped before summing."""
-    pred = np.log2(1 + np.array([10.0, 0, 30.0, 0, 5.0, 0, 100.0, 0]))
-    alen = np.array([3, 3, 1, 3, 4, 3, 5, 3])
-    nprod = np.array([40, 9, 30, 9, 60, 9, 5000, 9])
-    bmax = np.array([12, 3, 30, 3, 9, 3, 50, 3])
-    exact = {0: 20, 4: 18}
-    c, rows = mlp.calibration(pred, lambda r: np.array([exact[int(i)] for i in r]), alen, nprod,
-                              bmax, ncols=1000, target=4, max_nprod=2048)
-    # rows 0, 2, 4, 6: row 2 has a_len 1, row 6 n_prod 5000 > 2048
-    np.testing.assert_array_equal(rows, [0, 4])
-    # estimates: row 0 -> 10 clamped to [12, 40] = 12; row 4 -> 5 clamped to [9, 60] = 9
-    assert c == (20 + 18) / (12 + 9)
-    cap = mlp.capacity(pred, 0.0, alen, nprod, bmax, 1000, scale=c)
-    assert cap[0] == max(12, int(np.ceil(10 * c)))
+def test_row_ranges_brute_force():
+    import synthetic as syn
+    A = syn.random_csr(60, 50, 0.08, seed=3)
+    B = syn.random_csr(50, 70, 0.06, seed=4)
+    lo, hi = mlp.row_ranges(A, B)
+    for i in range(A.rows):
+        cols = [c for k in A.col[A.rpt[i]:A.rpt[i + 1]] for c in B.col[B.rpt[k]:B.rpt[k + 1]]]
+        if cols:
+            assert (lo[i], hi[i]) == (min(cols), max(cols))
+        else:
+            assert lo[i] > hi[i]
+
+
+def test_calibration_pick_rule():
+    """Hand-checked picks: octave sizes, the per-octave quota and the hash
+    stride; ineligible rows (a_len < 2, no products, wide range) never."""
+    M = 1000
+    alen = np.full(M, 3)
+    alen[5] = 1
+    nprod = np.full(M, 40)                 # octave 5: quota min(64, 2^24 >> 5) = 64
+    nprod[:10] = 0
+    nprod[900:] = 1 << 19                  # octave 19: quota 2^24 >> 19 = 32
+    nprod[990:] = 1 << 21                  # octave 21: never sampled
+    span = np.full(M, 100)
+    span[950] = (8 << 20) + 1
+    rows, octave = mlp.calibration_pick(alen, nprod, span)
+    elig5 = [i for i in range(10, 900) if i != 5]
+    elig19 = [i for i in range(900, 990) if i != 950]
+    h = lambda i: ((i * 0x9E3779B97F4A7C15) % (1 << 64)) >> 32
+    s5 = -(-len(elig5) // 64)
+    s19 = -(-len(elig19) // 32)
+    want = sorted([i for i in elig5 if h(i) % s5 == 0] + [i for i in elig19 if h(i) % s19 == 0])
+    np.testing.assert_array_equal(rows, want)
+    assert 40 <= sum(1 for r in rows if r < 900) <= 90
+    assert octave[0] == -1 and octave[20] == 5 and octave[999] == 21
+
+
+def test_calibration_scales_per_octave():
+    """Two octaves with opposite biases get their own scales; the exact
+    sizes used are those of the picked rows only."""
+    M = 4000
+    nprod = np.where(np.arange(M) < M // 2, 100, 1500)          # octaves 6 and 10
+    alen = np.full(M, 4)
+    bmax = np.full(M, 10)
+    true = np.where(nprod == 100, 50, 1000)
+    pred = np.log2(1 + np.where(nprod == 100, 25.0, 1200.0))    # 2x under, 1.2x over
+    seen = []
+    sc, overall, rows = mlp.calibration(pred, lambda r: (seen.append(r), true[r])[1], alen, nprod, bmax,
+                                        ncols=10 ** 6, span=np.full(M, 5000))
+    np.testing.assert_array_equal(seen[0], rows)
+    assert 64 <= rows.size <= 256
+    np.testing.assert_allclose(sc[nprod == 100], 2.0)
+    np.testing.assert_allclose(sc[nprod == 1500], 1000 / 1200)
+    n6 = np.sum(nprod[rows] == 100)
+    n10 = rows.size - n6
+    assert abs(overall - (n6 * 50 + n10 * 1000) / (n6 * 25 + n10 * 1200)) < 1e-12
+    # estimates clamped to [min(b_max, U), U] before the ratio; a capacity uses the row's scale
+    cap = mlp.capacity(pred, 0.0, alen, nprod, bmax, 10 ** 6, scale=sc)
+    assert cap[0] == 50 and cap[-1] == 1000
