@@ -326,32 +326,24 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         const bool grouped = lg <= 6 && win_grouped <= 2 * win_flat;
         // windows wv, wv + nwaves, ... of nwin with D + 1 windows of loads in
         // flight: slot d is consumed, then refilled with the window D + 1
-        // places ahead.  Returns true when stop() ended the row.
+        // places ahead.  Windows past the last hold no products (every lane
+        // has ok false) and are fetched and consumed like the others, so the
+        // loop body has no branch around its loads.  Returns true when
+        // stop() ended the row.
         auto pipelined = [&](int64_t nwin, auto &&fetchw) -> bool {
             constexpr int S = D + 1;
             int key[S];
             double bv[S], a[S];
             bool ok[S];
 #pragma unroll
-            for (int d = 0; d < S; ++d) {
-                key[d] = -1;
-                bv[d] = 0.0;
-                a[d] = 0.0;
-                ok[d] = false;
-                const int64_t w = wv + (int64_t)nwaves * d;
-                if (w < nwin) fetchw(w, key[d], bv[d], a[d], ok[d]);
-            }
+            for (int d = 0; d < S; ++d) fetchw(wv + (int64_t)nwaves * d, key[d], bv[d], a[d], ok[d]);
             for (int64_t w = wv; w < nwin; w += (int64_t)nwaves * S) {
 #pragma unroll
                 for (int d = 0; d < S; ++d) {
-                    const int64_t wd = w + (int64_t)nwaves * d;
-                    if (wd < nwin) {
-                        if constexpr (NUMERIC) f(ok[d], key[d], a[d] * bv[d]);
-                        else f(ok[d], key[d]);
-                        if (stop()) return true;
-                        const int64_t wn = wd + (int64_t)nwaves * S;
-                        if (wn < nwin) fetchw(wn, key[d], bv[d], a[d], ok[d]);
-                    }
+                    if constexpr (NUMERIC) f(ok[d], key[d], a[d] * bv[d]);
+                    else f(ok[d], key[d]);
+                    if (stop()) return true;
+                    fetchw(w + (int64_t)nwaves * (d + S), key[d], bv[d], a[d], ok[d]);
                 }
             }
             return false;
@@ -366,8 +358,16 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                 const int elen = bpermute(len, src);
                 if constexpr (NUMERIC) a = __longlong_as_double(bpermute64(__double_as_longlong(av), src));
                 ok = e < nent && r < elen;
-                key = ok ? bcol[eb0 + r] : -1;
-                if constexpr (NUMERIC) bv = ok ? bval[eb0 + r] : 0.0;
+                // every lane loads (index 0 when it holds no product): no
+                // divergent branch around the loads, so that the wait before
+                // a window's use leaves the next windows' loads in flight
+                const int64_t ix = ok ? eb0 + r : 0;
+                const int kv = bcol[ix];
+                key = ok ? kv : -1;
+                if constexpr (NUMERIC) {
+                    const double bw = bval[ix];
+                    bv = ok ? bw : 0.0;
+                }
             };
             int64_t w = wv;
             if (w >= win_grouped) continue;
@@ -382,7 +382,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             while (true) {
                 const int64_t wn = w + nwaves;
                 const bool more = wn < win_grouped;
-                if (more) fetch(wn, key1, bv1, a1v, ok1);
+                fetch(wn, key1, bv1, a1v, ok1);   // past the last window: no products
                 if constexpr (NUMERIC) f(ok, key, a * bv);
                 else f(ok, key);
                 if (!more || stop()) break;
@@ -415,8 +415,13 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                     }
                 }
                 ok = p < total;
-                key = ok ? bcol[cb + p] : -1;
-                if constexpr (NUMERIC) bv = ok ? bval[cb + p] : 0.0;
+                const int64_t ix = ok ? cb + p : 0;
+                const int kv = bcol[ix];
+                key = ok ? kv : -1;
+                if constexpr (NUMERIC) {
+                    const double bw = bval[ix];
+                    bv = ok ? bw : 0.0;
+                }
                 a = ca;
             };
             const int64_t stride = (int64_t)nwaves * 64;
@@ -436,7 +441,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             while (true) {
                 const int64_t wn = w0 + stride;
                 const bool more = wn < total;
-                if (more) fetch(wn, key1, bv1, a1v, ok1);
+                fetch(wn, key1, bv1, a1v, ok1);   // past the last window: no products
                 if constexpr (NUMERIC) f(ok, key, a * bv);
                 else f(ok, key);
                 if (!more || stop()) break;
