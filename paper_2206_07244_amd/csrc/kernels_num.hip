@@ -876,16 +876,19 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         }
         // 3. scatter the products into their chunks; lanes of a wave that
         //    hit one chunk take consecutive positions (coalesced stores)
+        //    (every lane stores: one without a product writes the
+        //    workgroup's spare last entry, so that no branch sits around the
+        //    stores, which count with the loads in flight)
         row_products<true, WIDE_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
-                                 [&](bool ok, int key, double v) {
-                                     const uint32_t o = (uint32_t)(key - lo);
-                                     if (ok && o < (uint64_t)span) {
-                                         const unsigned int p = atomicAdd(&cc[o >> BK_LG], 1u);
-                                         sk[p] = key;
-                                         sv[p] = v;
-                                     }
-                                 },
-                                 [] { return false; });
+                                   [&](bool ok, int key, double v) {
+                                       const uint32_t o = (uint32_t)(key - lo);
+                                       const bool in = ok && o < (uint64_t)span;
+                                       unsigned int p = (unsigned int)(stage_cap - 1);
+                                       if (in) p = atomicAdd(&cc[o >> BK_LG], 1u);
+                                       sk[p] = key;
+                                       sv[p] = v;
+                                   },
+                                   [] { return false; });
         // once every wave has scattered, the counters lent by the dense array
         // are zeroed, and the staging writes of every wave are visible to the
         // reads below (plain loads, so that several are in flight per thread)

@@ -101,8 +101,9 @@ struct NumArgs {
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 // Bin 7 by bucketed dense accumulation (rows with a column range in `rng`;
 // the matrix must have at most BUCKET_MAX_COLS columns).  slab_keys /
-// slab_vals / slab_entries are the staging buffers: slab_entries >= the
-// largest n_prod of the bin's rows, one per workgroup of the grid.
+// slab_vals / slab_entries are the staging buffers, one per workgroup of
+// the grid: slab_entries >= the largest n_prod of the bin's rows + 1 (the
+// last entry takes the stores of lanes without a product).
 constexpr int64_t BUCKET_MAX_COLS = (int64_t)1 << 24;
 hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s);
 

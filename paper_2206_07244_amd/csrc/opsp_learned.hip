@@ -248,7 +248,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
             // long rows: bucketed dense accumulation (never overflows)
             void *pk = nullptr, *pv = nullptr;
             const int64_t grid = bucket_grid(nsz[b], cus, S.max_row_nprod);
-            const int64_t sc = S.max_row_nprod > 1 ? S.max_row_nprod : 1;
+            const int64_t sc = (S.max_row_nprod > 1 ? S.max_row_nprod : 1) + 1;   // + spare entry
             CHK(ar.alloc(&pk, sizeof(int) * (size_t)(sc * grid)));
             CHK(ar.alloc(&pv, sizeof(double) * (size_t)(sc * grid)));
             NumArgs ba = na;
@@ -307,7 +307,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         CHK(hipMemsetAsync(&dc->lc.arena_used, 0, sizeof(unsigned long long), s));
         if (ranges && N <= BUCKET_MAX_COLS) {
             // bucketed dense accumulation: staging for the longest row
-            const int64_t sc = S.max_row_nprod > 1 ? S.max_row_nprod : 1;
+            const int64_t sc = (S.max_row_nprod > 1 ? S.max_row_nprod : 1) + 1;   // + spare entry
             const int64_t g2 = bucket_grid(nretry, cus, sc);
             void *sk = nullptr, *sv = nullptr;
             CHK(ar.alloc(&sk, sizeof(int) * (size_t)(sc * g2)));
