@@ -789,13 +789,17 @@ __global__ __launch_bounds__(1024) void k_num_global(
 // staging writes and reads) instead of one random global atomic per product.
 // The dense array and the bitmap are re-zeroed only where written.
 // ---------------------------------------------------------------------------
-constexpr int BK_LG = 14;
+constexpr int BK_T = 512;           // threads per workgroup (two workgroups per CU)
+constexpr int BK_NW = BK_T / 64;    // waves per workgroup
+constexpr int BK_LG = 13;
 constexpr int BK_CW = 1 << BK_LG;   // columns per chunk
-constexpr int BK_NB = 1024;         // chunks per row at most
+constexpr int BK_NB = 2048;         // chunks per row at most
+static_assert(BK_NB >= (int)(BUCKET_MAX_COLS >> BK_LG), "chunk counters");
+static_assert(BK_NB % BK_T == 0, "chunk scan");
 constexpr int BK_U = 4;             // staged products in flight per thread
 
 template <bool LRN>
-__global__ __launch_bounds__(1024) void k_num_bucket(
+__global__ __launch_bounds__(BK_T) void k_num_bucket(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const double *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
@@ -809,7 +813,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
     __shared__ unsigned int bits[BK_CW / 32];
     __shared__ unsigned int wpre[BK_CW / 32];
     __shared__ unsigned int off[BK_NB + 1];
-    __shared__ unsigned int red[16];
+    __shared__ unsigned int red[BK_NW];
     __shared__ long long s_base;
     __shared__ long long s_r;
 
@@ -818,8 +822,8 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
     unsigned int *cc = reinterpret_cast<unsigned int *>(dense);
     int *sk = stage_keys + (int64_t)blockIdx.x * stage_cap;
     double *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
-    for (int i = t; i < BK_CW; i += 1024) dense[i] = 0.0;
-    for (int i = t; i < BK_CW / 32; i += 1024) bits[i] = 0u;
+    for (int i = t; i < BK_CW; i += BK_T) dense[i] = 0.0;
+    for (int i = t; i < BK_CW / 32; i += BK_T) bits[i] = 0u;
 
     // rows from the launch's counter: row lengths here vary by orders of
     // magnitude, and a round-robin assignment leaves a few workgroups with
@@ -846,30 +850,44 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
             continue;
         }
         const int nb = (int)((span + BK_CW - 1) >> BK_LG);
-        for (int i = t; i < nb; i += 1024) cc[i] = 0u;
+        for (int i = t; i < nb; i += BK_T) cc[i] = 0u;
         __syncthreads();
         // 1. products per chunk
-        row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
+        row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, BK_NW,
                                   [&](bool ok, int key) {
                                       const uint32_t o = (uint32_t)(key - lo);
                                       if (ok && o < (uint64_t)span) atomicAdd(&cc[o >> BK_LG], 1u);
                                   },
                                   [] { return false; });
         __syncthreads();
-        // 2. chunk offsets (exclusive scan, nb <= 1024: one chunk per thread)
+        // 2. chunk offsets (exclusive scan, BK_NB / BK_T consecutive chunks
+        //    per thread)
         {
-            const unsigned int x = t < nb ? cc[t] : 0u;
-            const unsigned int incl = wave_incl_scan(x);
+            constexpr int PT = BK_NB / BK_T;
+            unsigned int x[PT], sum = 0;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                const int q = t * PT + u;
+                x[u] = q < nb ? cc[q] : 0u;
+                sum += x[u];
+            }
+            const unsigned int incl = wave_incl_scan(sum);
             if (l == 63) red[wv] = incl;
             __syncthreads();
             unsigned int pre = 0, tot = 0;
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < BK_NW; ++i) {
                 if (i < wv) pre += red[i];
                 tot += red[i];
             }
-            if (t < nb) {
-                off[t] = pre + incl - x;
-                cc[t] = pre + incl - x;   // running fill position of the chunk
+            pre += incl - sum;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                const int q = t * PT + u;
+                if (q < nb) {
+                    off[q] = pre;
+                    cc[q] = pre;   // running fill position of the chunk
+                }
+                pre += x[u];
             }
             if (t == 0) off[nb] = tot;
             __syncthreads();
@@ -879,7 +897,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         //    (every lane stores: one without a product writes the
         //    workgroup's spare last entry, so that no branch sits around the
         //    stores, which count with the loads in flight)
-        row_products<true, WIDE_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, 16,
+        row_products<true, WIDE_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, BK_NW,
                                    [&](bool ok, int key, double v) {
                                        const uint32_t o = (uint32_t)(key - lo);
                                        const bool in = ok && o < (uint64_t)span;
@@ -894,7 +912,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         // reads below (plain loads, so that several are in flight per thread)
         __threadfence();
         __syncthreads();
-        for (int i = t; i < BK_NB / 2; i += 1024) dense[i] = 0.0;
+        for (int i = t; i < BK_NB / 2; i += BK_T) dense[i] = 0.0;
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if constexpr (LRN) {
@@ -905,11 +923,11 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
                 const unsigned int p0 = off[b], p1 = off[b + 1];
                 if (p0 == p1) continue;   // uniform
                 const int c0 = lo + (b << BK_LG);
-                for (unsigned int p = p0 + t; p < p1; p += 1024 * BK_U) {
+                for (unsigned int p = p0 + t; p < p1; p += BK_T * BK_U) {
                     int kk[BK_U];
 #pragma unroll
                     for (int u = 0; u < BK_U; ++u) {
-                        const unsigned int q = p + 1024u * u;
+                        const unsigned int q = p + (unsigned int)BK_T * u;
                         kk[u] = q < p1 ? sk[q] : -1;
                     }
 #pragma unroll
@@ -925,7 +943,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
                 c = wave_sum(c);
                 if (l == 0) red[wv] = c;
                 __syncthreads();
-                for (int i = 0; i < 16; ++i) tot_n += red[i];
+                for (int i = 0; i < BK_NW; ++i) tot_n += red[i];
                 __syncthreads();
             }
             n = tot_n;
@@ -943,7 +961,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
         //    first staged products of the next nonempty chunk are loaded
         //    while the current chunk is emitted (chunks of long sparse rows
         //    hold a few hundred products: their load latency would dominate).
-        //    Outputs are emitted by rank (thread i takes ranks i, i + 1024,
+        //    Outputs are emitted by rank (thread i takes ranks i, i + BK_T,
         //    ...), so that stores to C are coalesced.
         int64_t run = 0;
         int kk[BK_U];
@@ -952,7 +970,7 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
             const unsigned int q0 = off[bb], q1 = off[bb + 1];
 #pragma unroll
             for (int u = 0; u < BK_U; ++u) {
-                const unsigned int q = q0 + t + 1024u * u;
+                const unsigned int q = q0 + t + (unsigned int)BK_T * u;
                 kk[u] = q < q1 ? sk[q] : -1;
                 vv[u] = q < q1 ? sv[q] : 0.0;
             }
@@ -973,10 +991,10 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
                 }
             };
             accumulate();
-            for (unsigned int p = p0 + 1024u * BK_U; p < p1; p += 1024u * BK_U) {
+            for (unsigned int p = p0 + (unsigned int)(BK_T * BK_U); p < p1; p += (unsigned int)(BK_T * BK_U)) {
 #pragma unroll
                 for (int u = 0; u < BK_U; ++u) {
-                    const unsigned int q = p + t + 1024u * u;
+                    const unsigned int q = p + t + (unsigned int)BK_T * u;
                     kk[u] = q < p1 ? sk[q] : -1;
                     vv[u] = q < p1 ? sv[q] : 0.0;
                 }
@@ -993,13 +1011,13 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
             if (l == 63) red[wv] = incl;
             __syncthreads();
             unsigned int pre = 0, tot = 0;
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < BK_NW; ++i) {
                 if (i < wv) pre += red[i];
                 tot += red[i];
             }
             if (t < BK_CW / 32) wpre[t] = pre + incl - c;
             __syncthreads();
-            for (unsigned int k = t; k < tot; k += 1024) {
+            for (unsigned int k = t; k < tot; k += BK_T) {
                 // the word holding rank k: the last word whose prefix is <= k
                 int wlo = 0, whi = BK_CW / 32 - 1;
                 while (wlo < whi) {
@@ -1041,11 +1059,11 @@ __global__ __launch_bounds__(1024) void k_num_bucket(
 hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s) {
     if (a.grid <= 0 || !a.rng) return hipSuccess;
     if (a.lrn.mode > 0)
-        hipLaunchKernelGGL(k_num_bucket<true>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
+        hipLaunchKernelGGL(k_num_bucket<true>, dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
                            a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng,
                            a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
     else
-        hipLaunchKernelGGL(k_num_bucket<false>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
+        hipLaunchKernelGGL(k_num_bucket<false>, dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
                            a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng,
                            a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
     return hipGetLastError();

@@ -429,7 +429,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
             // workgroup, at most 32 GB of staging in total
             // (+1: the spare entry of lanes without a product)
             const int64_t cap = (plan->stats.max_row_nprod > 1 ? plan->stats.max_row_nprod : 1) + 1;
-            int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
+            int64_t grid = rows < (int64_t)cus * BUCKET_WG_PER_CU ? rows : (int64_t)cus * BUCKET_WG_PER_CU;
             const int64_t budget = (int64_t)32 << 30;
             const int64_t fit = budget / (cap * 12);
             if (grid > fit) grid = fit > 1 ? fit : 1;

@@ -105,6 +105,7 @@ hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 // the grid: slab_entries >= the largest n_prod of the bin's rows + 1 (the
 // last entry takes the stores of lanes without a product).
 constexpr int64_t BUCKET_MAX_COLS = (int64_t)1 << 24;
+constexpr int BUCKET_WG_PER_CU = 2;   // workgroups of the bucketed kernel per CU
 hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s);
 
 // Copy the rows of the one-phase step from the temporary arrays (entries

@@ -35,10 +35,10 @@ namespace {
 
 constexpr int64_t ARENA_MIN = 1 << 16;
 
-// Workgroups of the bucketed kernel: one per CU at most, staging (12 bytes
-// per product of the longest row, per workgroup) under 32 GB.
+// Workgroups of the bucketed kernel: BUCKET_WG_PER_CU per CU at most,
+// staging (12 bytes per product of the longest row, per workgroup) under 32 GB.
 int64_t bucket_grid(int64_t rows, int cus, int64_t max_nprod) {
-    int64_t g = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
+    int64_t g = rows < (int64_t)cus * BUCKET_WG_PER_CU ? rows : (int64_t)cus * BUCKET_WG_PER_CU;
     const int64_t per = (max_nprod > 1 ? max_nprod : 1) * 12;
     const int64_t fit = ((int64_t)32 << 30) / per;
     if (g > fit) g = fit > 1 ? fit : 1;
