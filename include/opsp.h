@@ -264,8 +264,8 @@ typedef struct {
      * (row i when h(i) mod ceil(c / K) == 0, h the high 32 bits of
      * i * 0x9E3779B97F4A7C15) and counted exactly on the device.  In an
      * octave with at least 4 counted rows every row's estimate 2^y_i - 1 is
-     * multiplied by (sum of the counted sizes) / (sum of their estimates
-     * clamped as above) before the margin; other rows are not scaled.
+     * multiplied by the largest size / estimate (clamped as above) of the
+     * counted rows before the margin; other rows are not scaled.
      * 0 = 64; negative = no calibration. */
     int32_t calib_rows;
     int32_t reserved;

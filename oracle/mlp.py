@@ -230,11 +230,13 @@ def calibration_pick(alen, nprod, span, per_octave=64):
 def calibration(pred_log2, nnz_exact, alen, nprod, bmax, ncols, span, per_octave=64):
     """Per-octave scales of the network's estimates from the rows of
     calibration_pick, counted exactly by nnz_exact(rows).  An octave with at
-    least CAL_MIN_ROWS picked rows gets the scale (sum of their sizes) / (sum
-    of their estimates 2^pred - 1 clamped to [min(b_max, U), U],
-    U = min(n_prod, N)), and every row of that octave (n_prod >= 1) is scaled
-    by it; other rows keep 1.  Returns (scale of every row, overall ratio over
-    all picked rows (1 when none), picked rows)."""
+    least CAL_MIN_ROWS picked rows gets the scale max(size / estimate) over
+    them (the estimate 2^pred - 1 clamped to [min(b_max, U), U],
+    U = min(n_prod, N), at least 1 for a row with products), so that most of
+    the octave's rows fit even when its rows are biased differently; every
+    row of that octave (n_prod >= 1) is scaled by it, other rows keep 1.
+    Returns (scale of every row, overall ratio sum(sizes) / sum(estimates)
+    over all picked rows (1 when none), picked rows)."""
     alen, nprod, bmax = (np.asarray(a, np.int64) for a in (alen, nprod, bmax))
     scale = np.ones(nprod.size)
     rows, octave = calibration_pick(alen, nprod, span, per_octave)
@@ -247,8 +249,8 @@ def calibration(pred_log2, nnz_exact, alen, nprod, bmax, ncols, span, per_octave
     o_rows = octave[rows]
     for o in np.unique(o_rows):
         sel = o_rows == o
-        if sel.sum() >= CAL_MIN_ROWS and est[sel].sum() > 0:
-            scale[(octave == o) & (nprod >= 1)] = ex[sel].sum() / est[sel].sum()
+        if sel.sum() >= CAL_MIN_ROWS:
+            scale[(octave == o) & (nprod >= 1)] = np.max(ex[sel] / est[sel])
     overall = float(ex.sum() / est.sum()) if est.sum() > 0 else 1.0
     return scale, overall, rows
 

@@ -222,9 +222,8 @@ __global__ __launch_bounds__(256) void k_mlp_caps(int64_t M, CapArgs c,
     if (threadIdx.x < CAL_OCT) {
         const int o = threadIdx.x;
         double v = 1.0;
-        if (c.kind == 0 && c.calib && c.calib[2 * CAL_OCT + o] >= (double)CAL_MIN_ROWS &&
-            c.calib[CAL_OCT + o] > 0.0)
-            v = c.calib[o] / c.calib[CAL_OCT + o];
+        if (c.kind == 0 && c.calib && c.calmax && c.calib[2 * CAL_OCT + o] >= (double)CAL_MIN_ROWS)
+            v = __longlong_as_double((long long)c.calmax[o]);
         s_cal[o] = v;
     }
     __syncthreads();
@@ -371,14 +370,16 @@ __global__ __launch_bounds__(256) void k_cal_pick(int64_t M, const int32_t *__re
     }
 }
 
-// Sums of the picked rows per octave: exact size, clamped estimate, 1.
+// Sums of the picked rows per octave (exact size, clamped estimate, 1) and
+// the largest exact / estimate ratio.
 __global__ __launch_bounds__(256) void k_cal_sum(const int32_t *__restrict__ list,
                                                  const unsigned int *__restrict__ count,
                                                  const int64_t *__restrict__ nprod,
                                                  const int32_t *__restrict__ bmax,
                                                  const float *__restrict__ pred,
                                                  const int64_t *__restrict__ exact, int64_t ncols,
-                                                 double *__restrict__ calib) {
+                                                 double *__restrict__ calib,
+                                                 unsigned long long *__restrict__ calmax) {
     const int64_t n = (int64_t)*count;
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
         const int64_t row = list[k];
@@ -392,6 +393,9 @@ __global__ __launch_bounds__(256) void k_cal_sum(const int32_t *__restrict__ lis
         unsafeAtomicAdd(&calib[o], (double)exact[row]);
         unsafeAtomicAdd(&calib[CAL_OCT + o], e);
         unsafeAtomicAdd(&calib[2 * CAL_OCT + o], 1.0);
+        // largest ratio: positive doubles order like their bit patterns
+        const double ratio = (double)exact[row] / e;
+        atomicMax(&calmax[o], (unsigned long long)__double_as_longlong(ratio));
     }
 }
 
@@ -638,9 +642,9 @@ hipError_t launch_cal_pick(int64_t M, const int32_t *alen, const int64_t *nprod,
 
 hipError_t launch_cal_sum(const int32_t *list, const unsigned int *count, const int64_t *nprod,
                           const int32_t *bmax, const float *pred, const int64_t *exact, int64_t ncols,
-                          double *calib, hipStream_t s) {
+                          double *calib, unsigned long long *calmax, hipStream_t s) {
     hipLaunchKernelGGL(k_cal_sum, dim3(64), dim3(256), 0, s, list, count, nprod, bmax, pred, exact, ncols,
-                       calib);
+                       calib, calmax);
     return hipGetLastError();
 }
 

@@ -200,6 +200,7 @@ hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipSt
     return read_back(dst, src, sizeof(Counters) * count, s);
 }
 
+
 RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows) {
     RowSrc r;
     memset(&r, 0, sizeof(r));
@@ -426,12 +427,11 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
         if (plan->fixed_grid > 0 && b == 0) na.grid = plan->fixed_grid < rows ? plan->fixed_grid : rows;
         if (b == gb && plan->range && plan->N <= BUCKET_MAX_COLS) {
             // bucketed dense accumulation: staging for the largest n_prod per
-            // workgroup, at most 32 GB of staging in total
+            // workgroup, within the staging budget
             // (+1: the spare entry of lanes without a product)
             const int64_t cap = (plan->stats.max_row_nprod > 1 ? plan->stats.max_row_nprod : 1) + 1;
             int64_t grid = rows < (int64_t)cus * BUCKET_WG_PER_CU ? rows : (int64_t)cus * BUCKET_WG_PER_CU;
-            const int64_t budget = (int64_t)32 << 30;
-            const int64_t fit = budget / (cap * 12);
+            const int64_t fit = STAGING_BUDGET / (cap * 12);
             if (grid > fit) grid = fit > 1 ? fit : 1;
             CHK(ar.alloc(&pk, sizeof(int) * (size_t)(cap * grid)));
             CHK(ar.alloc(&pv, sizeof(double) * (size_t)(cap * grid)));

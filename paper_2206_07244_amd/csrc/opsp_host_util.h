@@ -32,6 +32,11 @@ opsp_status check_config(const opsp_config *c);
 hipError_t read_back(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipStream_t s);
 RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows);
+// Bytes the bucketed long-row kernel may take for staging.  Fixed, so that
+// repeated products request the same block from the allocation cache (a
+// budget following the free memory made the request size drift between
+// calls and the cache free and re-map tens of GB each time).
+constexpr int64_t STAGING_BUDGET = (int64_t)64 << 30;
 
 // Stream-ordered allocations released on every exit path unless kept.
 struct Arena {

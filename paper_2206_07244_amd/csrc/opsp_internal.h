@@ -140,6 +140,7 @@ struct CapArgs {
     float *pred;             // optional: the network's outputs (written)
     const float *pred_in;    // network outputs computed before (NULL = run it here)
     const double *calib;     // calibration sums [3][CAL_OCT] (launch_cal_sum), or NULL
+    const unsigned long long *calmax;   // largest ratio per octave, double bits
 };
 hipError_t launch_mlp_caps(int64_t M, const CapArgs &ca, const int32_t *alen, const int64_t *nprod,
                            const int32_t *bmax, int64_t *cap, const Bounds &bd,
@@ -158,9 +159,10 @@ hipError_t launch_mlp_pred(int64_t M, const uint16_t *P, const int32_t *alen, co
 // Fibonacci hash of the row index); after the picked rows are counted exactly into exact[row],
 // launch_cal_sum adds, per octave, their sizes into calib[o], their estimates
 // 2^pred - 1 clamped to [min(b_max, U), U] into calib[CAL_OCT + o] and 1 into
-// calib[2 CAL_OCT + o] (calib zeroed before).  The capacity kernel scales
-// the rows of an octave with at least CAL_MIN_ROWS counted rows by
-// calib[o] / calib[CAL_OCT + o]; other rows are not scaled.
+// calib[2 CAL_OCT + o], and keeps the largest size / estimate in calmax[o]
+// (bit pattern of the double; both zeroed before).  The capacity kernel
+// scales the rows of an octave with at least CAL_MIN_ROWS counted rows by
+// calmax[o]; other rows are not scaled.
 constexpr int CAL_OCT = 64;
 constexpr int64_t CAL_SPAN_MAX = (int64_t)SW_MAXPASS << SW_LG;
 constexpr int64_t CAL_OCT_PRODUCTS = (int64_t)1 << 24;
@@ -174,6 +176,6 @@ hipError_t launch_cal_pick(int64_t M, const int32_t *alen, const int64_t *nprod,
                            hipStream_t s);
 hipError_t launch_cal_sum(const int32_t *list, const unsigned int *count, const int64_t *nprod,
                           const int32_t *bmax, const float *pred, const int64_t *exact, int64_t ncols,
-                          double *calib, hipStream_t s);
+                          double *calib, unsigned long long *calmax, hipStream_t s);
 
 }  // namespace opsp

@@ -36,11 +36,12 @@ namespace {
 constexpr int64_t ARENA_MIN = 1 << 16;
 
 // Workgroups of the bucketed kernel: BUCKET_WG_PER_CU per CU at most,
-// staging (12 bytes per product of the longest row, per workgroup) under 32 GB.
+// staging (12 bytes per product of the longest row, per workgroup) within
+// the staging budget.
 int64_t bucket_grid(int64_t rows, int cus, int64_t max_nprod) {
     int64_t g = rows < (int64_t)cus * BUCKET_WG_PER_CU ? rows : (int64_t)cus * BUCKET_WG_PER_CU;
     const int64_t per = (max_nprod > 1 ? max_nprod : 1) * 12;
-    const int64_t fit = ((int64_t)32 << 30) / per;
+    const int64_t fit = STAGING_BUDGET / per;
     if (g > fit) g = fit > 1 ? fit : 1;
     return g;
 }
@@ -52,6 +53,7 @@ struct LearnedCounters {
     double calib[3 * CAL_OCT];            // calibration sums per n_prod octave
     unsigned long long cal_hist[CAL_OCT];  // eligible rows per octave
     unsigned long long cal_stride[CAL_OCT];
+    unsigned long long cal_max[CAL_OCT];   // largest exact / estimate per octave (bits)
     unsigned long long cal_sched[2];       // row counter of the exact count
     unsigned int cal_n;                    // picked rows
 };
@@ -182,9 +184,10 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         g.sched = dc->cal_sched;
         g.grid = cus;
         CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
-        CHK(launch_cal_sum(list, &dc->cal_n, np, bmax, pred, exact, N, dc->calib, s));
+        CHK(launch_cal_sum(list, &dc->cal_n, np, bmax, pred, exact, N, dc->calib, dc->cal_max, s));
         ca.pred_in = pred;
         ca.calib = dc->calib;
+        ca.calmax = dc->cal_max;
     }
     CHK(launch_mlp_caps(M, ca, alen, np, bmax, off, bn, parts, &dc->lc, s));
     if (pr->cap_out)

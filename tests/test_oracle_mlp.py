@@ -250,7 +250,8 @@ def test_calibration_pick_rule():
 
 def test_calibration_scales_per_octave():
     """Two octaves with opposite biases get their own scales; the exact
-    sizes used are those of the picked rows only."""
+    sizes used are those of the picked rows only; within an octave the scale
+    is the largest size / estimate ratio of its picked rows."""
     M = 4000
     nprod = np.where(np.arange(M) < M // 2, 100, 1500)          # octaves 6 and 10
     alen = np.full(M, 4)
@@ -270,3 +271,9 @@ def test_calibration_scales_per_octave():
     # estimates clamped to [min(b_max, U), U] before the ratio; a capacity uses the row's scale
     cap = mlp.capacity(pred, 0.0, alen, nprod, bmax, 10 ** 6, scale=sc)
     assert cap[0] == 50 and cap[-1] == 1000
+    # a spread inside one octave: the scale is the largest ratio of the picked rows
+    true2 = np.where(np.arange(M) % 3 == 0, 60, 50) * (nprod == 100) + true * (nprod == 1500)
+    sc2, _, rows2 = mlp.calibration(pred, lambda r: true2[r], alen, nprod, bmax, ncols=10 ** 6,
+                                    span=np.full(M, 5000))
+    r6 = rows2[nprod[rows2] == 100]
+    assert abs(sc2[0] - 60 / 25.0) < 1e-12 and np.all(sc2[nprod == 100] == sc2[0])
