@@ -92,7 +92,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;  // waves per team
-    __shared__ int tab[R * T];
+    __shared__ __align__(16) int tab[R * T];
     __shared__ int s_cnt[R];
     __shared__ int s_abort[R];
     __shared__ int red[NW];
@@ -142,10 +142,19 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
             }
         }
         team_sync<WT>();   // the previous row of this team is done with the table
+        // 16-byte LDS stores where the sizes allow (T and the bitmap's
+        // power-of-two word count are multiples of 4 words)
+        static_assert(T % 4 == 0, "vector clears");
         if (bm) {
-            for (int s = t; s < nwords; s += W) tb[s] = 0;
+            if (nwords >= 4) {
+                uint4 *p4 = reinterpret_cast<uint4 *>(tb);
+                for (int s = t; s < (nwords >> 2); s += W) p4[s] = make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                for (int s = t; s < nwords; s += W) tb[s] = 0;
+            }
         } else {
-            for (int s = t; s < T; s += W) tb[s] = -1;
+            int4 *p4 = reinterpret_cast<int4 *>(tb);
+            for (int s = t; s < T / 4; s += W) p4[s] = make_int4(-1, -1, -1, -1);
         }
         if (t == 0) { s_cnt[team] = 0; s_abort[team] = 0; }
         team_sync<WT>();
@@ -180,7 +189,15 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
         }
         if (bm) {   // uniform over the team
             team_sync<WT>();
-            for (int s = t; s < nwords; s += W) cnt += __popc((unsigned int)tb[s]);
+            if (nwords >= 4) {
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(tb);
+                for (int s = t; s < (nwords >> 2); s += W) {
+                    const uint4 v = p4[s];
+                    cnt += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                }
+            } else {
+                for (int s = t; s < nwords; s += W) cnt += __popc((unsigned int)tb[s]);
+            }
         }
         if (ABORT && !bm) {
             team_sync<WT>();
