@@ -454,24 +454,29 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
         return;
     }
 
+    // one-phase: distinct keys inserted so far.  A one-wave team keeps the
+    // count in a scalar register; larger teams add into LDS.
+    int wcnt = 0;
     if (active) {
         auto ins = [&](bool ok, int key, double v) {
             const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
                                            [](double *p, double x) { atomicAdd(p, x); });
             if constexpr (LRN) {
                 const int nm = (int)__popcll(__ballot(nw));
-                if (nm && lane_id() == 0) atomicAdd(&s_cnt[team], nm);
+                if constexpr (WT) wcnt += nm;
+                else if (nm && lane_id() == 0) atomicAdd(&s_cnt[team], nm);
             }
         };
         auto stop = [&]() -> bool {
-            if constexpr (LRN) return *(volatile int *)&s_cnt[team] > THR;
+            if constexpr (LRN && WT) return wcnt > THR;
+            else if constexpr (LRN) return *(volatile int *)&s_cnt[team] > THR;
             else return false;
         };
         row_products<true, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
     }
     team_sync<WT>();
     if constexpr (LRN) {
-        if (s_cnt[team] > THR) {   // uniform over the team
+        if ((WT ? wcnt : s_cnt[team]) > THR) {   // uniform over the team
             if (active && t == 0) lrn_retry(L, row, true);
             return;
         }
