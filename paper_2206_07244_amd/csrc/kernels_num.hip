@@ -786,13 +786,15 @@ __global__ __launch_bounds__(1024) void k_num_global(
 
 // ---------------------------------------------------------------------------
 // bin 7, rows with a known column range: bucketed dense accumulation.
-// A long row's products are partitioned by 16384-column chunk of its output
+// A long row's products are partitioned by BK_CW-column chunk of its output
 // range into a per-workgroup staging buffer (a counting pass, a scan over
 // the chunks, a scatter pass), then each chunk is accumulated densely in
 // LDS (an FP64 add and an occupancy bit per product) and emitted in column
 // order through a popcount prefix.  Global traffic is sequential (the
 // staging writes and reads) instead of one random global atomic per product.
-// The dense array and the bitmap are re-zeroed only where written.
+// The dense array and the bitmap are re-zeroed only where written.  Two
+// workgroups share a CU, so that one's barriers and LDS round trips overlap
+// the other's work.
 // ---------------------------------------------------------------------------
 constexpr int BK_T = 512;           // threads per workgroup (two workgroups per CU)
 constexpr int BK_NW = BK_T / 64;    // waves per workgroup
