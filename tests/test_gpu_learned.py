@@ -135,15 +135,16 @@ def test_arena_exhaustion_recomputes_rows(hash_all):
     assert st.arena_entries > 0 and st.retry_rows > 0
 
 
-@pytest.mark.parametrize("calib_rows", [-1, 0, 5])
-def test_capacities_follow_the_rule(calib_rows):
+@pytest.mark.parametrize("calib_rows,hash_all", [(-1, 0), (0, 0), (5, 0), (0, 1)])
+def test_capacities_follow_the_rule(calib_rows, hash_all):
     """Capacities reported by the call equal the rule applied (in float64, as
     the kernel does) to the network outputs it reports, scaled per n_prod
     octave by the calibration of the rows the oracle's rule picks (counted
     exactly by the oracle), and obey the bounds."""
     A = syn.rmat(12, 16, seed=12)
     pred = rand_predictor(seed=12, margin=0.25, calib_rows=calib_rows)
-    st, caps, y = run(A, None, pred, want_caps=True)
+    # hashing every row: the column ranges are still computed for the sample
+    st, caps, y = run(A, None, pred, cfg=_ops().Config(hash_all_rows=hash_all), want_caps=True)
     nprod, alen, bmax, _ = oracle.row_stats(A, A)
     scale = 1.0
     if calib_rows >= 0:
