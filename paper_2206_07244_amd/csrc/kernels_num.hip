@@ -859,11 +859,30 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         const int nb = (int)((span + BK_CW - 1) >> BK_LG);
         for (int i = t; i < nb; i += BK_T) cc[i] = 0u;
         __syncthreads();
+        // Lanes of a window that hold consecutive products of one sorted B
+        // row mostly fall in one chunk: runs of equal chunks in consecutive
+        // lanes are found with one lane shuffle and a ballot, and the run's
+        // first lane updates the chunk's counter for the whole run (the
+        // same-address LDS atomics of many lanes are what serialise).
+        auto runs = [&](bool in, int c, int &head_lane, int &run_len) {
+            const int l = lane_id();
+            const int cp = __builtin_amdgcn_ds_bpermute((l > 0 ? l - 1 : 0) << 2, c);
+            const unsigned long long bnd = __ballot(l == 0 || cp != c);
+            const unsigned long long le = l == 63 ? ~0ull : ((2ull << l) - 1ull);
+            head_lane = 63 - __clzll((long long)(bnd & le));
+            const unsigned long long after = bnd & ~le;
+            const int next = after ? __ffsll((long long)after) - 1 : 64;
+            run_len = in ? next - head_lane : 0;
+        };
         // 1. products per chunk
         row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, BK_NW,
                                   [&](bool ok, int key) {
                                       const uint32_t o = (uint32_t)(key - lo);
-                                      if (ok && o < (uint64_t)span) atomicAdd(&cc[o >> BK_LG], 1u);
+                                      const bool in = ok && o < (uint64_t)span;
+                                      const int c = in ? (int)(o >> BK_LG) : -1;
+                                      int h, n;
+                                      runs(in, c, h, n);
+                                      if (in && h == lane_id()) atomicAdd(&cc[c], (unsigned int)n);
                                   },
                                   [] { return false; });
         __syncthreads();
@@ -908,8 +927,15 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                                    [&](bool ok, int key, double v) {
                                        const uint32_t o = (uint32_t)(key - lo);
                                        const bool in = ok && o < (uint64_t)span;
-                                       unsigned int p = (unsigned int)(stage_cap - 1);
-                                       if (in) p = atomicAdd(&cc[o >> BK_LG], 1u);
+                                       const int c = in ? (int)(o >> BK_LG) : -1;
+                                       int h, n;
+                                       runs(in, c, h, n);
+                                       const int l = lane_id();
+                                       unsigned int b = 0u;
+                                       if (in && h == l) b = atomicAdd(&cc[c], (unsigned int)n);
+                                       b = (unsigned int)__builtin_amdgcn_ds_bpermute(h << 2, (int)b);
+                                       const unsigned int p = in ? b + (unsigned int)(l - h)
+                                                                 : (unsigned int)(stage_cap - 1);
                                        sk[p] = key;
                                        sv[p] = v;
                                    },
