@@ -127,23 +127,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         for (int s = g; s < T; s += GL) { tk[s] = -1; tv[s] = 0.0; }
         if (LRN && g == 0) s_full[slot] = 0;
         __syncthreads();
-        int64_t row = 0;
+        int64_t row = 0, c0 = 0, c1 = 0;
         if (active) {
             row = src.row(idx);
             const int64_t a1 = arpt[row + 1];
+            if constexpr (!LRN) {   // the row's place in C, used at the end
+                c0 = crpt[row];
+                c1 = crpt[row + 1];
+            }
             for (int64_t p = arpt[row] + g; p < a1; p += GL) {
                 const int k = acol[p];
                 const double a = aval[p];
                 const int64_t b1 = brpt[k + 1];
                 bool full = false;
-                for (int64_t q = brpt[k]; q < b1; ++q) {
-                    if (!num_insert_lds(tk, tv, T, bcol[q], a * bval[q])) {
-                        if constexpr (LRN) {
-                            s_full[slot] = 1;
-                            full = true;
-                            break;
-                        } else {
-                            atomicAdd(&ctr->error, 1u);
+                // GRP_U entries of the B row are loaded before any is
+                // inserted (indices past the row end re-read its first entry,
+                // unused)
+                for (int64_t q = brpt[k]; q < b1 && !full; q += GRP_U) {
+                    int kk[GRP_U];
+                    double vv[GRP_U];
+#pragma unroll
+                    for (int u = 0; u < GRP_U; ++u) {
+                        const int64_t qq = q + u < b1 ? q + u : q;
+                        kk[u] = bcol[qq];
+                        vv[u] = bval[qq];
+                    }
+#pragma unroll
+                    for (int u = 0; u < GRP_U; ++u) {
+                        if (q + u < b1 && !full && !num_insert_lds(tk, tv, T, kk[u], a * vv[u])) {
+                            if constexpr (LRN) {
+                                s_full[slot] = 1;
+                                full = true;
+                            } else {
+                                atomicAdd(&ctr->error, 1u);
+                            }
                         }
                     }
                 }
@@ -186,8 +203,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 base = __shfl(b, 0, GL);
                 cap = base < 0 ? 0 : n;
             } else {
-                base = crpt[row];
-                cap = crpt[row + 1] - base;
+                base = c0;
+                cap = c1 - c0;
                 if (g == 0 && cap != n) atomicAdd(&ctr->error, 1u);
             }
         }
@@ -362,13 +379,17 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     // A row whose output columns span at most T positions accumulates into a
     // dense array of that range (values) plus a bitmap (occupancy): no
     // probing, and the rank of a column is a popcount.
-    int64_t row = 0, a0 = 0, a1 = 0;
+    int64_t row = 0, a0 = 0, a1 = 0, c0 = 0, c1 = 0;
     bool dn = false;
     int lo = 0, dspan = 0;
     if (active) {
         row = src.row(idx);
         a0 = arpt[row];   // issued together with the range load
         a1 = arpt[row + 1];
+        if constexpr (!LRN) {   // and the row's place in C, used at the end
+            c0 = crpt[row];
+            c1 = crpt[row + 1];
+        }
         if (rng) {
             const int2 r = rng[row];
             lo = r.x;
@@ -403,8 +424,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
             base = active ? (int64_t)s_base[team] : -1;
             cap = n;
         } else {
-            base = active ? crpt[row] : -1;
-            cap = active ? crpt[row + 1] - base : 0;
+            base = active ? c0 : -1;
+            cap = active ? c1 - c0 : 0;
             if (active && t == 0 && cap != n) atomicAdd(&ctr->error, 1u);
         }
     };

@@ -64,10 +64,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             for (int64_t p = arpt[row] + g; p < a1; p += GL) {
                 const int k = acol[p];
                 const int64_t b1 = brpt[k + 1];
-                for (int64_t q = brpt[k]; q < b1; ++q) {
-                    const int r = sym_insert_lds(t, T, bcol[q]);
-                    if (r < 0) atomicAdd(&ctr->error, 1u);
-                    else cnt += r;
+                // GRP_U keys of the B row are loaded before any is inserted
+                // (indices past the row end re-read its first key, unused)
+                for (int64_t q = brpt[k]; q < b1; q += GRP_U) {
+                    int kk[GRP_U];
+#pragma unroll
+                    for (int u = 0; u < GRP_U; ++u) kk[u] = bcol[q + u < b1 ? q + u : q];
+#pragma unroll
+                    for (int u = 0; u < GRP_U; ++u) {
+                        if (q + u < b1) {
+                            const int r = sym_insert_lds(t, T, kk[u]);
+                            if (r < 0) atomicAdd(&ctr->error, 1u);
+                            else cnt += r;
+                        }
+                    }
                 }
             }
         }

@@ -34,6 +34,10 @@ constexpr int NUM_GLOBAL_BIN = 7;
 // Workgroups per CU that the global-table kernels are sized for.
 constexpr int SYM_GLOBAL_WG_PER_CU = 1;
 
+// B-row entries each lane of a several-rows-per-wave kernel loads before it
+// inserts them (loads in flight per lane).
+constexpr int GRP_U = 8;
+
 // Symbolic rows of the global bin with a known column range are counted in
 // an LDS bitmap of 2^SW_LG columns, one pass per window of the range, when
 // the range needs at most SW_MAXPASS windows.
