@@ -193,19 +193,22 @@ __global__ __launch_bounds__(256) void k_hist(int64_t M, const int64_t *__restri
 
 // ---------------------------------------------------------------------------
 // Finalize (one workgroup of 1024 threads): blocks are taken 1024 at a time,
-// one per thread.  Each thread loads its block's record (16 bin counts with
-// four 16-byte loads, the total and the maximum); the workgroup scans every
-// bin slot and the totals (wave scans, per-wave sums in LDS, a running carry
-// across chunks) and writes the exclusive offsets back in place: per bin slot
-// the block's offset inside the bin, and with SCAN the block's row-pointer
-// offset.  Bin sizes, grand total and maximum go to `ctr`.
+// one per thread, and the next 1024 blocks' records are loaded while the
+// current ones are scanned.  Each thread loads its block's record (16 bin
+// counts with four 16-byte loads, the total and the maximum); the workgroup
+// scans every bin slot and the totals (wave scans; then, per value, a
+// 16-lane scan of the 16 wave sums, which also advances a running carry
+// across chunks) and writes the exclusive offsets back in place: per bin
+// slot the block's offset inside the bin, and with SCAN the block's
+// row-pointer offset.  Bin sizes, grand total and maximum go to `ctr`.
 // ---------------------------------------------------------------------------
 template <bool SCAN>
 __global__ __launch_bounds__(1024) void k_finalize(int64_t nblk, int nslots, BlockParts parts,
                                                    Counters *__restrict__ ctr,
                                                    int64_t *__restrict__ total_out) {
     constexpr int NV = BIN_SLOTS + 1;               // bin slots + totals
-    __shared__ unsigned long long wred[NV][16];
+    __shared__ unsigned long long wred[NV][16];     // per-wave inclusive sums
+    __shared__ unsigned long long wpre[NV][16];     // carry + exclusive prefix of wred
     __shared__ unsigned long long carry[NV];
     __shared__ unsigned long long wmx[16];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
@@ -218,56 +221,73 @@ __global__ __launch_bounds__(1024) void k_finalize(int64_t nblk, int nslots, Blo
     }
     if (t < NV) carry[t] = 0;
     unsigned long long mx = 0;
+    // block b's record (zeros past the last block; the index is clamped so
+    // that the loads need no branch)
+    unsigned int h[BIN_SLOTS];
+    unsigned long long tt, m;
+    auto load = [&](int64_t b, unsigned int *hh, unsigned long long &t_, unsigned long long &m_) {
+        const bool ok = b < nblk;
+        const int64_t bb = ok ? b : nblk - 1;
+        const uint4 *src = reinterpret_cast<const uint4 *>(parts.hist + bb * BIN_SLOTS);
+#pragma unroll
+        for (int q = 0; q < BIN_SLOTS / 4; ++q) {
+            const uint4 v4 = src[q];
+            hh[4 * q] = ok ? v4.x : 0u;
+            hh[4 * q + 1] = ok ? v4.y : 0u;
+            hh[4 * q + 2] = ok ? v4.z : 0u;
+            hh[4 * q + 3] = ok ? v4.w : 0u;
+        }
+        const unsigned long long tv = parts.tot[bb], mv = parts.mx[bb];
+        t_ = ok ? tv : 0ull;
+        m_ = ok ? mv : 0ull;
+    };
+    load(t, h, tt, m);
     __syncthreads();
     for (int64_t c = 0; c < nblk; c += 1024) {
         const int64_t b = c + t;
         const bool ok = b < nblk;
-        unsigned int h[BIN_SLOTS];
-        if (ok) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(parts.hist + b * BIN_SLOTS);
-#pragma unroll
-            for (int q = 0; q < BIN_SLOTS / 4; ++q) {
-                const uint4 v4 = src[q];
-                h[4 * q] = v4.x; h[4 * q + 1] = v4.y; h[4 * q + 2] = v4.z; h[4 * q + 3] = v4.w;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < BIN_SLOTS; ++j) h[j] = 0u;
-        }
-        const unsigned long long tt = ok ? parts.tot[b] : 0ull;
-        const unsigned long long m = ok ? parts.mx[b] : 0ull;
+        unsigned int hn[BIN_SLOTS];
+        unsigned long long ttn, mn;
+        load(b + 1024, hn, ttn, mn);   // next chunk, in flight during this one
         mx = m > mx ? m : mx;
-        unsigned long long incl[NV];
+        unsigned int incl[BIN_SLOTS];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const unsigned long long x = j < BIN_SLOTS ? (unsigned long long)h[j] : tt;
-            incl[j] = (j < nslots || j == BIN_SLOTS) ? wave_incl_scan(x) : 0ull;
+        for (int j = 0; j < BIN_SLOTS; ++j) {
+            incl[j] = j < nslots ? wave_incl_scan(h[j]) : 0u;
             if (l == 63) wred[j][w] = incl[j];
         }
+        const unsigned long long inclt = wave_incl_scan(tt);
+        if (l == 63) wred[BIN_SLOTS][w] = inclt;
         __syncthreads();
-        unsigned long long outv[NV];
+        if (t < NV * 16) {   // value j = t / 16, wave ww = t % 16: lanes of one wave
+            const int j = t >> 4, ww = t & 15;
+            const unsigned long long v = wred[j][ww];
+            const unsigned long long cj = carry[j];
+            unsigned long long inc = v;
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const unsigned long long x = j < BIN_SLOTS ? (unsigned long long)h[j] : tt;
-            unsigned long long pre = carry[j];
-            for (int ww = 0; ww < w; ++ww) pre += wred[j][ww];
-            outv[j] = pre + incl[j] - x;
+            for (int o = 1; o < 16; o <<= 1) {
+                const unsigned long long y = __shfl_up(inc, o, 16);
+                if (ww >= o) inc += y;
+            }
+            wpre[j][ww] = cj + inc - v;
+            if (ww == 15) carry[j] = cj + inc;   // after every lane of the group read cj
         }
+        __syncthreads();
         if (ok) {
+            unsigned int outv[BIN_SLOTS];
+#pragma unroll
+            for (int j = 0; j < BIN_SLOTS; ++j)
+                outv[j] = (unsigned)(wpre[j][w] + incl[j] - h[j]);
             uint4 *dst = reinterpret_cast<uint4 *>(parts.hist + b * BIN_SLOTS);
 #pragma unroll
             for (int q = 0; q < BIN_SLOTS / 4; ++q)
-                dst[q] = make_uint4((unsigned)outv[4 * q], (unsigned)outv[4 * q + 1],
-                                    (unsigned)outv[4 * q + 2], (unsigned)outv[4 * q + 3]);
-            if (SCAN) parts.tot[b] = outv[BIN_SLOTS];
+                dst[q] = make_uint4(outv[4 * q], outv[4 * q + 1], outv[4 * q + 2], outv[4 * q + 3]);
+            if (SCAN) parts.tot[b] = wpre[BIN_SLOTS][w] + inclt - tt;
         }
-        __syncthreads();
-        if (t < NV) {
-            unsigned long long sum = 0;
-            for (int ww = 0; ww < 16; ++ww) sum += wred[t][ww];
-            carry[t] += sum;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < BIN_SLOTS; ++j) h[j] = hn[j];
+        tt = ttn;
+        m = mn;
     }
     mx = wave_max(mx);
     if (l == 0) wmx[w] = mx;
