@@ -94,8 +94,11 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
         chi[w][l] = mx;
     } else if (nrows > 0) {
         const int64_t e0 = rs[w][0], e1 = rs[w][64];
-        // four entries per lane per step so that their gathers overlap
-        for (int64_t eb = e0 + l; eb < e1; eb += 256) {
+        // four entries per lane per step so that their gathers overlap; the
+        // loop is uniform over the wave (lanes past the end hold no entry),
+        // as the wave reductions below need every lane
+        for (int64_t eb0 = e0; eb0 < e1; eb0 += 256) {
+            const int64_t eb = eb0 + l;
             int64_t len[4];
             int2 fl[4];
 #pragma unroll
@@ -113,16 +116,37 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t e = eb + 64 * u;
-                if (len[u] < 0) continue;
+                const bool ok = len[u] >= 0;
                 // largest r in [0, nrows) with rs[r] <= e (rows may be empty)
                 int lo = 0, hi = nrows - 1;
-                while (lo < hi) {
+                while (ok && lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (rs[w][mid] <= e) lo = mid; else hi = mid - 1;
                 }
+                const unsigned lc = ok ? (unsigned)(len[u] > 0xffffffffll ? 0xffffffffll : len[u]) : 0u;
+                const bool fr = range && ok && len[u] > 0;
+                // lanes hold consecutive entries, so lane 0 has the lowest
+                // row; when every lane with an entry is in that row (a long
+                // row), reduce over the wave and update the row once instead
+                // of 64 lanes contending for one LDS word
+                const int lo0 = __builtin_amdgcn_readfirstlane(lo);
+                if (__ballot(ok && lo != lo0) == 0ull) {
+                    const unsigned long long sa = wave_sum(ok ? (unsigned long long)len[u] : 0ull);
+                    const unsigned sm = wave_max(lc);
+                    const int smin = wave_min(fr ? fl[u].x : INT_MAX);
+                    const int smax = wave_max(fr ? fl[u].y : -1);
+                    if (l == 0 && __ballot(ok) != 0ull) {
+                        acc[w][lo0] += sa;
+                        bmx[w][lo0] = sm > bmx[w][lo0] ? sm : bmx[w][lo0];
+                        clo[w][lo0] = smin < clo[w][lo0] ? smin : clo[w][lo0];
+                        chi[w][lo0] = smax > chi[w][lo0] ? smax : chi[w][lo0];
+                    }
+                    continue;
+                }
+                if (!ok) continue;
                 atomicAdd(&acc[w][lo], (unsigned long long)len[u]);
-                atomicMax(&bmx[w][lo], (unsigned)(len[u] > 0xffffffffll ? 0xffffffffll : len[u]));
-                if (range && len[u] > 0) {
+                atomicMax(&bmx[w][lo], lc);
+                if (fr) {
                     atomicMin(&clo[w][lo], fl[u].x);
                     atomicMax(&chi[w][lo], fl[u].y);
                 }
