@@ -559,6 +559,24 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     }
     team_sync<WT>();
 
+    // A one-wave row of at most 64 entries: lane e holds packed entry e, and
+    // its rank is the number of the other lanes' keys below its own (keys are
+    // distinct), read lane by lane from registers.
+    if constexpr (WT) {
+        if (n <= 64) {   // uniform over the wave
+            const int key = t < n ? tk[t] : INT_MAX;
+            const int sl = t < n ? (int)ps[t] : 0;
+            const int nn = __builtin_amdgcn_readfirstlane(n);
+            int rank = 0;
+            for (int j = 0; j < nn; ++j) rank += __builtin_amdgcn_readlane(key, j) < key ? 1 : 0;
+            if (active && t < n && rank < cap) {
+                ccol[base + rank] = key;
+                cval[base + rank] = tv[sl];
+            }
+            return;
+        }
+    }
+
     // level-1 words (even count keeps level 0 4-byte aligned)
     const int span = kmax - kmin + 1;
     const int nblk1 = (int)(((int64_t)span + 31) >> 5);
