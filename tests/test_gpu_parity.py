@@ -284,3 +284,40 @@ def test_global_symbolic_bin_wide_ranges(n_cols, hash_all):
                          hash_all_rows=hash_all)
         check(A, B, cfg=cfg, stats=st)
         assert st.sym_bin_rows[8] == A.rows
+
+
+def _rows_with_output_counts(counts, n_cols=200003, seed=11):
+    """A, B with row i of A·B holding exactly counts[i] distinct columns
+    spread over n_cols (wider than any numeric LDS table, so rows are hashed
+    and then ordered): B rows k < K hold one column each, (48271 k) mod
+    n_cols (distinct, n_cols prime); B rows K + k repeat row k's column, and
+    A rows also reference up to five of those, so some outputs accumulate
+    two products."""
+    rng = np.random.default_rng(seed)
+    K = 4096
+    bcol = np.array([(48271 * k) % n_cols for k in range(K)] * 2, dtype=np.int32)
+    B = syn.CSR(2 * K, n_cols, np.arange(2 * K + 1, dtype=np.int64), bcol, rng.uniform(-1, 1, 2 * K))
+    rpt, col = [0], []
+    for i, n in enumerate(counts):
+        k0 = (131 * i) % (K - 200)
+        ent = list(range(k0, k0 + n)) + list(range(K + k0, K + k0 + min(n, 5)))
+        col.extend(sorted(ent))
+        rpt.append(len(col))
+    A = syn.CSR(len(counts), 2 * K, np.array(rpt, np.int64), np.array(col, np.int32),
+                rng.uniform(-1, 1, len(col)))
+    return A, B
+
+
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_one_wave_rows_around_64_outputs(hash_all):
+    """One-wave numeric rows of 0-128 outputs, on both sides of the 64-entry
+    limit below which entries are ranked from registers instead of the
+    two-level bitmap."""
+    ops = _ops()
+    counts = [0, 1, 2, 31, 63, 64, 65, 66, 100, 127, 128] * 3
+    A, B = _rows_with_output_counts(counts)
+    st = ops.Stats()
+    cfg = ops.Config(force_num_bin=1, validate=1, hash_all_rows=hash_all)
+    check(A, B, cfg=cfg, stats=st)
+    assert st.num_bin_rows[1] == A.rows
+    assert st.nnz == sum(counts)
