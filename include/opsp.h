@@ -261,8 +261,9 @@ typedef struct {
      * Rows with a_len >= 2, 1 <= n_prod < 2^21 and an output column range
      * of at most 2^23 columns are grouped by o = floor(log2 n_prod); of an octave's
      * c rows, about K = min(c, clamp(2^24 >> o, 4, calib_rows)) are picked
-     * (row i when h(i) mod ceil(c / K) == 0, h the high 32 bits of
-     * i * 0x9E3779B97F4A7C15) and counted exactly on the device.  In an
+     * (row i with probability K / c: when u(i) * c < K * 2^32, u(i) the
+     * high 32 bits of MurmurHash3's 64-bit finalizer fmix64(i); every row
+     * when c <= K) and counted exactly on the device.  In an
      * octave with at least 4 counted rows every row's estimate 2^y_i - 1 is
      * multiplied by the largest size / estimate (clamped as above) of the
      * counted rows before the margin; other rows are not scaled.

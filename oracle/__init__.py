@@ -14,6 +14,9 @@ Contents
                    Alg. 1-2): the first bin whose inclusive upper range bound
                    holds the row's value; the last bin is unbounded.
 * ``row_pointer``- exclusive prefix sum of row sizes (Section 5.3).
+* ``threads``    - ``symbolic`` and ``spgemm`` take ``threads=T``: the same
+                   per-row code on T threads over blocks of rows (rows are
+                   independent, Section 2.1), bit-identical to T = 1.
 * ``bin_ranges`` - binning ranges from table sizes and the ratio rule of
                    Section 5.7 (symbolic: t/ratio, numeric: (t+1)/ratio).
 
@@ -40,7 +43,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -59,8 +62,22 @@ def _load():
         lib.oracle_symbolic.argtypes = [I, P, I, P, P, P, P, P]
         lib.oracle_numeric.restype = ctypes.c_int
         lib.oracle_numeric.argtypes = [I, P, I, P, P, P, P, P, P, P, P, P, P]
+        lib.oracle_symbolic_mt.restype = ctypes.c_int
+        lib.oracle_symbolic_mt.argtypes = [ctypes.c_int, I, P, I, P, P, P, P, P]
+        lib.oracle_numeric_mt.restype = ctypes.c_int
+        lib.oracle_numeric_mt.argtypes = [ctypes.c_int, I, P, I, P, P, P, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
+
+
+def host_threads(cap: int = 16) -> int:
+    """Threads for the row-parallel oracle: the CPUs this process may use,
+    at most ``cap``."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
 
 
 def _p(a: Optional[np.ndarray]):
@@ -83,7 +100,7 @@ def row_stats(A, B) -> Tuple[np.ndarray, np.ndarray, np.ndarray, int]:
     return nprod, alen, bmax, int(tot)
 
 
-def symbolic(A, B, rows: Optional[np.ndarray] = None) -> np.ndarray:
+def symbolic(A, B, rows: Optional[np.ndarray] = None, threads: int = 1) -> np.ndarray:
     """Distinct output columns per row (all rows, or the listed ones)."""
     assert A.cols == B.rows
     lib = _load()
@@ -92,7 +109,8 @@ def symbolic(A, B, rows: Optional[np.ndarray] = None) -> np.ndarray:
     nnz = np.empty(nr, np.int64)
     arpt, acol = _c(A.rpt, np.int64), _c(A.col, np.int32)
     brpt, bcol = _c(B.rpt, np.int64), _c(B.col, np.int32)
-    rc = lib.oracle_symbolic(nr, _p(r), B.cols, _p(arpt), _p(acol), _p(brpt), _p(bcol), _p(nnz))
+    rc = lib.oracle_symbolic_mt(int(threads), nr, _p(r), B.cols, _p(arpt), _p(acol), _p(brpt),
+                                _p(bcol), _p(nnz))
     if rc != 0:
         raise MemoryError("oracle_symbolic failed")
     return nnz
@@ -105,14 +123,14 @@ def row_pointer(sizes: np.ndarray) -> np.ndarray:
     return out
 
 
-def spgemm(A, B, rows: Optional[np.ndarray] = None, with_scale: bool = True):
+def spgemm(A, B, rows: Optional[np.ndarray] = None, with_scale: bool = True, threads: int = 1):
     """C = A*B.  Returns (rpt, col, val, S) for all rows, or for the listed
     rows packed one after another (rpt then indexes that packing)."""
     assert A.cols == B.rows
     lib = _load()
     r = None if rows is None else _c(rows, np.int64)
     nr = A.rows if r is None else r.size
-    nnz = symbolic(A, B, r)
+    nnz = symbolic(A, B, r, threads=threads)
     off = row_pointer(nnz)
     total = int(off[-1])
     ccol = np.empty(total, np.int32)
@@ -120,8 +138,8 @@ def spgemm(A, B, rows: Optional[np.ndarray] = None, with_scale: bool = True):
     cabs = np.empty(total, np.float64) if with_scale else None
     arpt, acol, aval = _c(A.rpt, np.int64), _c(A.col, np.int32), _c(A.val, np.float64)
     brpt, bcol, bval = _c(B.rpt, np.int64), _c(B.col, np.int32), _c(B.val, np.float64)
-    rc = lib.oracle_numeric(nr, _p(r), B.cols, _p(arpt), _p(acol), _p(aval),
-                            _p(brpt), _p(bcol), _p(bval), _p(off), _p(ccol), _p(cval), _p(cabs))
+    rc = lib.oracle_numeric_mt(int(threads), nr, _p(r), B.cols, _p(arpt), _p(acol), _p(aval),
+                               _p(brpt), _p(bcol), _p(bval), _p(off), _p(ccol), _p(cval), _p(cabs))
     if rc != 0:
         raise RuntimeError("oracle_numeric failed (%d)" % rc)
     return off, ccol, cval, cabs

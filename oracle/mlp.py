@@ -201,29 +201,43 @@ def row_ranges(A, B):
     return lo, hi
 
 
+def fmix64(x: np.ndarray) -> np.ndarray:
+    """MurmurHash3's 64-bit finalizer (A. Appleby, MurmurHash3, public
+    domain): xor-shift 33, multiply by 0xff51afd7ed558ccd, xor-shift 33,
+    multiply by 0xc4ceb9fe1a85ec53, xor-shift 33, all modulo 2^64."""
+    k = np.asarray(x, np.uint64).copy()
+    with np.errstate(over="ignore"):
+        k ^= k >> np.uint64(33)
+        k *= np.uint64(0xFF51AFD7ED558CCD)
+        k ^= k >> np.uint64(33)
+        k *= np.uint64(0xC4CEB9FE1A85EC53)
+        k ^= k >> np.uint64(33)
+    return k
+
+
 def calibration_pick(alen, nprod, span, per_octave=64):
     """Rows counted exactly for the calibration, by a rule both sides apply
     in integer arithmetic.  Eligible rows have a_len >= 2,
     1 <= n_prod < 2^(CAL_MAX_OCT + 1) and a column range of at most
-    CAL_SPAN_MAX columns; they are grouped by octave o = floor(log2 n_prod).  An octave with c eligible rows takes
-    K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)) of
-    them on average: row i is picked when h(i) mod ceil(c / K) == 0, with
-    h(i) the high 32 bits of the 64-bit product i * 0x9E3779B97F4A7C15
-    (Fibonacci hashing, so the picks spread over the octave's rows).
+    CAL_SPAN_MAX columns; they are grouped by octave o = floor(log2 n_prod).
+    An octave with c eligible rows has the quota
+    K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)); each
+    of its rows is picked with probability K / c, by the draw
+    u(i) * c < K * 2^32 with u(i) the high 32 bits of fmix64(i), so an
+    octave yields K rows on average and every row when c <= K.
     Returns the picked rows (ascending) and every row's octave."""
     alen, nprod, span = (np.asarray(a, np.int64) for a in (alen, nprod, span))
     M = nprod.size
     octave = np.where(nprod >= 1, np.floor(np.log2(np.maximum(nprod, 1))).astype(np.int64), -1)
     elig = (alen >= 2) & (nprod >= 1) & (octave <= CAL_MAX_OCT) & (span <= CAL_SPAN_MAX)
     picked = np.zeros(M, bool)
-    idx = np.arange(M, dtype=np.uint64)
-    h = ((idx * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(32)).astype(np.int64)
+    u = fmix64(np.arange(M, dtype=np.uint64)) >> np.uint64(32)    # < 2^32
     for o in np.unique(octave[elig]):
         sel = elig & (octave == o)
         c = int(sel.sum())
         k = min(c, min(max(CAL_OCT_PRODUCTS >> int(o), CAL_MIN_ROWS), per_octave))
-        stride = -(-c // k)
-        picked |= sel & (h % stride == 0)
+        # u * c < 2^63 and K * 2^32 < 2^39: exact in uint64
+        picked |= sel & (u * np.uint64(c) < np.uint64(k << 32))
     return np.nonzero(picked)[0], octave
 
 

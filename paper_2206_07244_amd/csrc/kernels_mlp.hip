@@ -341,32 +341,47 @@ __global__ __launch_bounds__(256) void k_cal_hist(int64_t M, const int32_t *__re
 
 // Stride of every octave from its count c: ceil(c / K) with
 // K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)).
-__global__ void k_cal_strides(const unsigned long long *__restrict__ hist, int64_t per_octave,
-                              unsigned long long *__restrict__ stride) {
+__global__ void k_cal_quota(const unsigned long long *__restrict__ hist, int64_t per_octave,
+                              unsigned long long *__restrict__ quota) {
     const int o = threadIdx.x;
     if (o >= CAL_OCT) return;
     const int64_t c = (int64_t)hist[o];
     int64_t k = o < 62 ? (CAL_OCT_PRODUCTS >> o) : 0;
     k = k < CAL_MIN_ROWS ? CAL_MIN_ROWS : (k > per_octave ? per_octave : k);
     k = k < c ? k : c;
-    stride[o] = c > 0 ? (unsigned long long)((c + k - 1) / k) : 0ull;
+    quota[o] = c > 0 ? (unsigned long long)k : 0ull;
 }
 
-// Eligible row i of octave o is picked when h(i) mod stride[o] == 0, h(i)
-// the high half of i * 0x9E3779B97F4A7C15 (Fibonacci hashing); picked rows
-// are appended to `list` (which holds M entries, so it cannot overflow).
+// MurmurHash3's 64-bit finalizer (Appleby): every input bit affects every
+// output bit, so the high half of the result is uniform over [0, 2^32)
+// for any set of row indices, consecutive ones included.
+__device__ __forceinline__ unsigned long long fmix64(unsigned long long k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// Eligible row i of an octave with c eligible rows and quota K is picked
+// when u(i) * c < K * 2^32, u(i) the high half of fmix64(i): a Bernoulli
+// draw of probability K / c, so an octave yields K rows on average and all
+// of its rows when c <= K.  Picked rows are appended to `list` (which holds
+// M entries, so it cannot overflow).
 __global__ __launch_bounds__(256) void k_cal_pick(int64_t M, const int32_t *__restrict__ alen,
                                                   const int64_t *__restrict__ nprod,
                                                   const int2 *__restrict__ rng,
-                                                  const unsigned long long *__restrict__ stride,
+                                                  const unsigned long long *__restrict__ hist,
+                                                  const unsigned long long *__restrict__ quota,
                                                   int32_t *__restrict__ list,
                                                   unsigned int *__restrict__ count) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
         const int64_t np = nprod[i];
         if (!cal_eligible(alen[i], np, rng[i])) continue;
-        const unsigned long long sd = stride[63 - __clzll(np)];
-        const unsigned long long h = ((unsigned long long)i * 0x9E3779B97F4A7C15ull) >> 32;
-        if (sd && h % sd == 0) list[atomicAdd(count, 1u)] = (int32_t)i;
+        const int o = 63 - __clzll(np);
+        const unsigned long long u = fmix64((unsigned long long)i) >> 32;
+        if (u * hist[o] < (quota[o] << 32)) list[atomicAdd(count, 1u)] = (int32_t)i;
     }
 }
 
@@ -630,13 +645,13 @@ hipError_t launch_cal_hist(int64_t M, const int32_t *alen, const int64_t *nprod,
 
 hipError_t launch_cal_pick(int64_t M, const int32_t *alen, const int64_t *nprod, const int2 *rng,
                            const unsigned long long *hist, int64_t per_octave,
-                           unsigned long long *stride, int32_t *list, unsigned int *count,
+                           unsigned long long *quota, int32_t *list, unsigned int *count,
                            hipStream_t s) {
     if (M <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cal_strides, dim3(1), dim3(CAL_OCT), 0, s, hist, per_octave, stride);
+    hipLaunchKernelGGL(k_cal_quota, dim3(1), dim3(CAL_OCT), 0, s, hist, per_octave, quota);
     const int64_t g = (M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096;
-    hipLaunchKernelGGL(k_cal_pick, dim3((unsigned)g), dim3(256), 0, s, M, alen, nprod, rng, stride, list,
-                       count);
+    hipLaunchKernelGGL(k_cal_pick, dim3((unsigned)g), dim3(256), 0, s, M, alen, nprod, rng, hist, quota,
+                       list, count);
     return hipGetLastError();
 }
 

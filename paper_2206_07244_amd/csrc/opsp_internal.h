@@ -153,10 +153,11 @@ hipError_t launch_mlp_pred(int64_t M, const uint16_t *P, const int32_t *alen, co
 // CAL_SPAN_MAX columns (so that the bin-8 bitmap kernel counts them); they
 // are grouped by the octave o = floor(log2 n_prod).  launch_cal_hist adds
 // the number of eligible rows of each octave into hist[CAL_OCT];
-// launch_cal_pick turns an octave's count c into stride[o] = ceil(c / K),
-// K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave)), and
-// appends the eligible rows with h(i) mod stride[o] == 0 to `list` (h:
-// Fibonacci hash of the row index); after the picked rows are counted exactly into exact[row],
+// launch_cal_pick turns an octave's count c into its quota
+// quota[o] = K = min(c, clamp(CAL_OCT_PRODUCTS >> o, CAL_MIN_ROWS, per_octave))
+// and appends the eligible rows with u(i) * c < K * 2^32 to `list` (u: the
+// high half of MurmurHash3's fmix64 of the row index, so each row is picked
+// with probability K / c); after the picked rows are counted exactly into exact[row],
 // launch_cal_sum adds, per octave, their sizes into calib[o], their estimates
 // 2^pred - 1 clamped to [min(b_max, U), U] into calib[CAL_OCT + o] and 1 into
 // calib[2 CAL_OCT + o], and keeps the largest size / estimate in calmax[o]
@@ -172,7 +173,7 @@ hipError_t launch_cal_hist(int64_t M, const int32_t *alen, const int64_t *nprod,
                            unsigned long long *hist, hipStream_t s);
 hipError_t launch_cal_pick(int64_t M, const int32_t *alen, const int64_t *nprod, const int2 *rng,
                            const unsigned long long *hist, int64_t per_octave,
-                           unsigned long long *stride, int32_t *list, unsigned int *count,
+                           unsigned long long *quota, int32_t *list, unsigned int *count,
                            hipStream_t s);
 hipError_t launch_cal_sum(const int32_t *list, const unsigned int *count, const int64_t *nprod,
                           const int32_t *bmax, const float *pred, const int64_t *exact, int64_t ncols,

@@ -52,7 +52,7 @@ struct LearnedCounters {
     LearnCtr lc;
     double calib[3 * CAL_OCT];            // calibration sums per n_prod octave
     unsigned long long cal_hist[CAL_OCT];  // eligible rows per octave
-    unsigned long long cal_stride[CAL_OCT];
+    unsigned long long cal_quota[CAL_OCT];
     unsigned long long cal_max[CAL_OCT];   // largest exact / estimate per octave (bits)
     unsigned long long cal_sched[2];       // row counter of the exact count
     unsigned int cal_n;                    // picked rows
@@ -169,7 +169,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         int32_t *list = (int32_t *)p;
         CHK(ar.alloc(&p, sizeof(int64_t) * (size_t)M));
         int64_t *exact = (int64_t *)p;
-        CHK(launch_cal_pick(M, alen, np, rng, dc->cal_hist, cal_k, dc->cal_stride, list, &dc->cal_n, s));
+        CHK(launch_cal_pick(M, alen, np, rng, dc->cal_hist, cal_k, dc->cal_quota, list, &dc->cal_n, s));
         // exact sizes of the picked rows: the bin-8 bitmap windows (every
         // picked range fits them), one row per workgroup from a counter
         SymArgs g;

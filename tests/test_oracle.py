@@ -282,3 +282,26 @@ def test_paper_range_tables(oracle_lib):
                     assert d != p
                 else:
                     assert d == p, (step, ratio, j)
+
+
+# --------------------------------------------------------------------------
+# Row-parallel form: the same per-row code on several threads
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("threads", [2, 3, 8])
+def test_threads_bit_identical(oracle_lib, threads):
+    """Rows are independent (Section 2.1): the threaded oracle returns the
+    single-threaded result bit for bit, for all rows and for a row list."""
+    import synthetic as syn
+    A = syn.rmat(12, 8, seed=5)
+    one = oracle_lib.spgemm(A, A)
+    many = oracle_lib.spgemm(A, A, threads=threads)
+    for x, y in zip(one, many):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
+    rows = np.random.default_rng(threads).choice(A.rows, 700, replace=False)
+    one = oracle_lib.spgemm(A, A, rows=rows)
+    many = oracle_lib.spgemm(A, A, rows=rows, threads=threads)
+    for x, y in zip(one, many):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
+    np.testing.assert_array_equal(oracle_lib.symbolic(A, A, threads=threads),
+                                  oracle_lib.symbolic(A, A))

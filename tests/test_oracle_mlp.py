@@ -224,28 +224,109 @@ def test_row_ranges_brute_force():
             assert lo[i] > hi[i]
 
 
-def test_calibration_pick_rule():
-    """Hand-checked picks: octave sizes, the per-octave quota and the hash
-    stride; ineligible rows (a_len < 2, no products, wide range) never."""
-    M = 1000
-    alen = np.full(M, 3)
-    alen[5] = 1
-    nprod = np.full(M, 40)                 # octave 5: quota min(64, 2^24 >> 5) = 64
-    nprod[:10] = 0
-    nprod[900:] = 1 << 19                  # octave 19: quota 2^24 >> 19 = 32
-    nprod[990:] = 1 << 21                  # octave 21: never sampled
-    span = np.full(M, 100)
-    span[950] = (8 << 20) + 1
+def test_fmix64_is_a_bijection_with_avalanche():
+    """MurmurHash3's finalizer is invertible (each xor-shift by 33 >= 32 is
+    its own inverse, each multiplier is odd) and mixes: flipping one input
+    bit flips about half of the output bits."""
+    r = np.random.default_rng(11)
+    x = r.integers(0, 2 ** 63, 2000, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(1)
+    y = mlp.fmix64(x)
+    inv1, inv2 = pow(0xFF51AFD7ED558CCD, -1, 1 << 64), pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)
+    for a, b in zip(x[:200], y[:200]):
+        k = int(b)
+        k ^= k >> 33
+        k = (k * inv2) % (1 << 64)
+        k ^= k >> 33
+        k = (k * inv1) % (1 << 64)
+        k ^= k >> 33
+        assert k == int(a)
+    flips = []
+    for bit in range(64):
+        d = mlp.fmix64(x ^ np.uint64(1 << bit)) ^ y
+        flips.append(np.mean([bin(int(v)).count("1") for v in d[:300]]))
+    assert 30.0 < np.mean(flips) < 34.0 and min(flips) > 28.0
+
+
+def test_calibration_pick_eligibility_and_small_octaves():
+    """Picks are eligible rows only (a_len >= 2, 1 <= n_prod < 2^21, range
+    <= CAL_SPAN_MAX columns, each bound checked on both sides), octaves are
+    floor(log2 n_prod), and an octave with no more rows than its quota
+    gives every row."""
+    alen = np.array([2, 1, 2, 2, 2, 2, 2, 2, 3, 2])
+    nprod = np.array([1, 5, 0, (1 << 21) - 1, 1 << 21, 8, 7, 1 << 19, 100, 100])
+    span = np.array([1, 1, 1, 5, 5, mlp.CAL_SPAN_MAX, mlp.CAL_SPAN_MAX + 1, 3, 3, 3])
     rows, octave = mlp.calibration_pick(alen, nprod, span)
-    elig5 = [i for i in range(10, 900) if i != 5]
-    elig19 = [i for i in range(900, 990) if i != 950]
-    h = lambda i: ((i * 0x9E3779B97F4A7C15) % (1 << 64)) >> 32
-    s5 = -(-len(elig5) // 64)
-    s19 = -(-len(elig19) // 32)
-    want = sorted([i for i in elig5 if h(i) % s5 == 0] + [i for i in elig19 if h(i) % s19 == 0])
-    np.testing.assert_array_equal(rows, want)
-    assert 40 <= sum(1 for r in rows if r < 900) <= 90
-    assert octave[0] == -1 and octave[20] == 5 and octave[999] == 21
+    assert list(octave) == [0, 2, -1, 20, 21, 3, 2, 19, 6, 6]
+    assert list(rows) == [0, 3, 5, 7, 8, 9]
+    # a quota of 64 (octave 6) and of 32 (octave 19): c <= K takes every row
+    M = 96
+    nprod = np.where(np.arange(M) < 64, 100, 1 << 19)
+    rows, _ = mlp.calibration_pick(np.full(M, 2), nprod, np.zeros(M))
+    assert rows.size == 64 + 32
+
+
+def test_calibration_pick_counts_near_quota():
+    """An octave with c > K eligible rows yields about K picks: over seeded
+    layouts (octaves contiguous or scattered over the row indices) the
+    count lies in [K/2, 2K] for at least 99 % of the octaves, and the mean
+    of count / K is 1 within 5 %.  A stride or quota off by a factor of two
+    fails this."""
+    r = np.random.default_rng(1)
+    ratios, inside = [], []
+    for trial in range(200):
+        M = int(r.integers(2000, 40000))
+        base = int(r.integers(0, 1 << 17))   # different row indices per layout
+        npd = (2.0 ** r.uniform(0, 21.5, M)).astype(np.int64)
+        if trial % 2:
+            npd = np.sort(npd)
+        alen = r.integers(1, 6, M)
+        span = np.where(r.random(M) < 0.05, 1 << 24, 100)
+        big_alen = np.concatenate([np.zeros(base, np.int64), alen])
+        big_np = np.concatenate([np.zeros(base, np.int64), npd])
+        big_span = np.concatenate([np.zeros(base, np.int64), span])
+        rows, octave = mlp.calibration_pick(big_alen, big_np, big_span)
+        elig = (big_alen >= 2) & (big_np >= 1) & (octave <= mlp.CAL_MAX_OCT) & (big_span <= mlp.CAL_SPAN_MAX)
+        for o in np.unique(octave[elig]):
+            c = int(np.sum(elig & (octave == o)))
+            k = min(c, min(max(mlp.CAL_OCT_PRODUCTS >> int(o), mlp.CAL_MIN_ROWS), 64))
+            if c <= k:
+                continue
+            got = int(np.sum(octave[rows] == o))
+            ratios.append(got / k)
+            inside.append(k / 2 <= got <= 2 * k)
+    assert len(ratios) > 2000
+    assert np.mean(inside) >= 0.99
+    assert abs(np.mean(ratios) - 1.0) < 0.05
+
+
+def test_calibration_scale_covers_every_picked_row():
+    """With margin 0, every picked row of an octave that is scaled gets a
+    capacity of at least its exact size (the scale is the largest ratio of
+    the octave's picked rows); a mean ratio would leave rows short here."""
+    r = np.random.default_rng(5)
+    M = 20000
+    nprod = (2.0 ** r.uniform(2, 16, M)).astype(np.int64)
+    alen = np.full(M, 4)
+    bmax = np.minimum(nprod, 3)
+    true = np.maximum(bmax, (nprod * r.uniform(0.2, 0.9, M)).astype(np.int64))
+    # the estimates err by a random factor in [0.5, 2] per row
+    pred = np.log2(1.0 + true * 2.0 ** r.uniform(-1, 1, M))
+    sc, _, rows = mlp.calibration(pred, lambda q: true[q], alen, nprod, bmax, ncols=1 << 20,
+                                  span=np.full(M, 100))
+    cap = mlp.capacity(pred, 0.0, alen, nprod, bmax, 1 << 20, scale=sc)
+    octave = np.floor(np.log2(nprod)).astype(np.int64)
+    scaled = [o for o in np.unique(octave[rows]) if np.sum(octave[rows] == o) >= mlp.CAL_MIN_ROWS]
+    assert len(scaled) >= 10
+    pr = rows[np.isin(octave[rows], scaled)]
+    assert np.all(cap[pr] >= true[pr])
+    # the same rule with the mean ratio instead would not cover them
+    est = np.clip(np.exp2(pred) - 1.0, np.minimum(bmax, nprod), nprod)
+    mean_sc = np.ones(M)
+    for o in scaled:
+        sel = rows[octave[rows] == o]
+        mean_sc[octave == o] = np.mean(true[sel] / est[sel])
+    cap_mean = mlp.capacity(pred, 0.0, alen, nprod, bmax, 1 << 20, scale=mean_sc)
+    assert np.any(cap_mean[pr] < true[pr])
 
 
 def test_calibration_scales_per_octave():
