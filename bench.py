@@ -3,8 +3,11 @@
 
 One step = one full C = A*B through the C ABI (``opsp_spgemm``: setup,
 both binnings, symbolic, scan, allocation of C, numeric, release of C), on
-inputs already resident in HBM.  The default workload is the 3-D 27-point
-stencil on a 100^3 grid, values U[-1,1) from seed 27, C = A^2.
+inputs already resident in HBM.  The default workload is the square of an
+R-MAT graph of 2^20 vertices, degree 16, (a,b,c,d) = (.57,.19,.19,.05),
+values U(0,1] from seed 20 (C has 9.7e9 entries, 116 GB); the 3-D
+27-point stencil on a 100^3 grid (values U[-1,1) from seed 27) is reported
+beside it.
 
 Metric (OpSparse Section 6): GFLOPS = 2 * n_prod / time, FP64.
 
@@ -93,14 +96,198 @@ def symbolic_bytes(M, nnzA, nprod):
     return 4 * nprod + 20 * nnzA + 24 * M
 
 
+def bucket_bytes(ops, torch, dA, crpt, bounds_num):
+    """Algorithmic HBM bytes of one launch of the long-row numeric kernel
+    (bin 7): the numeric_bytes model over the rows of that bin only (rows
+    whose nnz exceeds every numeric LDS bin bound), and the rows, products
+    and outputs it covers."""
+    _, npd, _ = ops.row_features(dA, dA)
+    nnz = crpt[1:] - crpt[:-1]
+    alen = dA.rpt[1:] - dA.rpt[:-1]
+    in_lds = torch.zeros_like(nnz, dtype=torch.bool)
+    for ub in bounds_num:
+        in_lds |= nnz <= ub
+    big = ~in_lds
+    rows = int(big.sum().item())
+    nprod = int(npd[big].sum().item())
+    nnzc = int(nnz[big].sum().item())
+    annz = int(alen[big].sum().item())
+    return numeric_bytes(rows, annz, nprod, nnzc), {"rows": rows, "nprod": nprod, "nnzC": nnzc,
+                                                     "nnzA": annz}
+
+
+def numeric_bounds(ops, cfg):
+    """Inclusive nnz bounds of numeric bins 0..6 under `cfg` (explicit
+    bounds where given, else the ratio rule over the table sizes)."""
+    ts = ops.table_sizes(1)[:7]
+    ratio = cfg.num_ratio if cfg is not None and cfg.num_ratio > 0 else 2.0
+    derived = ops.bin_bounds(1, ts, ratio)
+    explicit = list(cfg.num_bounds) if cfg is not None else [0] * 7
+    return [e if e != 0 else d for e, d in zip(explicit, derived)]
+
+
+def measure_plain(ops, torch, np, syn, name, steps, warmup, dev, tuned_cls=True, builtin=True):
+    """Time `steps` whole products C = A^2 of a named workload (inputs
+    resident, C allocated and released inside the timed region) and the
+    dominant kernel's duration with HIP events on the call's stream."""
+    from paper_2206_07244_amd import autotune
+    desc, builder = syn.WORKLOADS[name]
+    t0 = time.time()
+    A = builder()
+    log(f"workload {name}: {A.rows} rows, {A.nnz} nnz, generated in {time.time() - t0:.1f}s")
+    dA = ops.DeviceCSR.from_host(A, dev)
+    torch.cuda.synchronize()
+    sh = torch.cuda.current_stream().cuda_stream
+    Ac = dA._c_fast(A.nnz)
+    L = ops.lib()
+    cls = workload_class(name)
+    tuned = autotune.load_config(cls) if tuned_cls else None
+    tref = ops.byref(tuned) if tuned is not None else None
+    log(f"bin configuration: {'tuned for ' + cls if tuned is not None else 'built-in'}")
+
+    st = ops.Stats()
+    for _ in range(max(warmup, 1)):
+        Cc = ops.opsp_csr()
+        code = L.opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), tref, ops.byref(st), sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_ex")
+        ops.free_raw(Cc, sh)
+    torch.cuda.synchronize()
+    nprod, nnzC = st.nprod, st.nnz
+    log(f"n_prod={nprod} nnz(C)={nnzC} CR={nprod / max(nnzC, 1):.3f} bins sym={list(st.sym_bin_rows)} "
+        f"num={list(st.num_bin_rows)}")
+
+    def timed(cref):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            Cc = ops.opsp_csr()
+            code = L.opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), cref, None, sh)
+            if code:
+                raise ops.OpspError(code, "opsp_spgemm_ex")
+            ops.free_raw(Cc, sh)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3 / steps
+    ms = timed(tref)
+    gflops = 2.0 * nprod / (ms * 1e-3) / 1e9
+    log(f"timed {steps} steps: {ms:.3f} ms/step, {gflops:.1f} GFLOPS")
+    ms_default = timed(None) if (tuned is not None and builtin) else None
+    if ms_default is not None:
+        log(f"built-in configuration: {ms_default:.3f} ms/step")
+
+    # per-stage and per-kernel durations: the same calls with HIP events
+    # recorded on the call's stream (stage 3 = all numeric kernels, slot 5 =
+    # the long-row numeric kernel alone)
+    cfg = autotune.load_config(cls) if tuned is not None else ops.Config()
+    cfg.stage_timing = 1
+    stage = np.zeros(8)
+    C_keep = None
+    for k in range(steps):
+        Cc = ops.opsp_csr()
+        s2 = ops.Stats()
+        code = L.opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), ops.byref(cfg),
+                                ops.byref(s2), sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_ex")
+        if k == steps - 1:
+            C_keep = Cc
+        else:
+            ops.free_raw(Cc, sh)
+        stage += np.array(list(s2.ms_stage))
+    torch.cuda.synchronize()
+    stage /= steps
+    log("stage ms (setup+bin, symbolic, numbin+scan, numeric, total, long-row numeric kernel):",
+        [round(x, 4) for x in stage[:6]])
+
+    M, nnzA = A.rows, A.nnz
+    if stage[5] > 0.5 * stage[3]:
+        # the long-row kernel dominates: its own bytes over its own time
+        crpt = ops._wrap(C_keep.rpt, M + 1, torch.int64, None, dev)
+        bytes_, cover = bucket_bytes(ops, torch, dA, crpt, numeric_bounds(ops, tuned))
+        del crpt
+        kernel = "k_num_global" if cfg.hash_all_rows else "k_num_bucket"
+        kms = stage[5]
+    else:
+        bytes_, cover = numeric_bytes(M, nnzA, nprod, nnzC), {"rows": M, "nprod": nprod,
+                                                               "nnzC": nnzC, "nnzA": nnzA}
+        kernel, kms = "numeric", stage[3]
+    ops.free_raw(C_keep, sh)
+    torch.cuda.synchronize()
+    achieved = bytes_ / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes": int(bytes_), "kernel_ms": round(float(kms), 4), "covers": cover}
+    rec = stored_traffic(kernel, name)
+    if rec is not None:
+        roof["traffic"] = int(rec["bytes_per_launch"])
+        roof["traffic_source"] = rec.get("file", "profiles")
+        roof["traffic_frac"] = round(rec["bytes_per_launch"] / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    res = {"A": A, "dA": dA, "desc": desc, "ms": ms, "gflops": gflops, "nprod": nprod, "nnzC": nnzC,
+           "ms_default": ms_default, "stage": stage, "roofline": roof, "cls": cls,
+           "tuned": tuned is not None}
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, np, seconds):
+    """The CPU oracle on a bounded, stratified sample of the workload's
+    rows: rows ordered by n_prod, every s-th taken, s chosen from a short
+    pilot so that the single-threaded run takes about `seconds`; then the
+    same rows on all available cores (the oracle's row-parallel form, same
+    per-row code).  GFLOPS = 2 * (products of the sampled rows) / time."""
+    import oracle
+    oracle.build(force=False)
+    nprod, _, _, tot = oracle.row_stats(A, A)
+    order = np.argsort(nprod, kind="stable")
+
+    def sample(stride):
+        return np.sort(order[stride // 2::stride]).astype(np.int64)
+
+    def run(rows, threads):
+        t = time.perf_counter()
+        oracle.spgemm(A, A, rows=rows, with_scale=False, threads=threads)
+        return time.perf_counter() - t
+    # pilot: a sparse sample, single-threaded
+    stride = max(1, A.rows // 512)
+    rows = sample(stride)
+    el = run(rows, 1)
+    rate = max(float(nprod[rows].sum()), 1.0) / max(el, 1e-3)      # products per second
+    want = rate * seconds
+    stride = int(max(1, min(A.rows, np.ceil(tot / max(want, 1.0)))))
+    rows = sample(stride)
+    prod = int(nprod[rows].sum())
+    t1 = run(rows, 1)
+    threads = oracle.host_threads()
+    tn = run(rows, threads)
+    g1 = 2.0 * prod / t1 / 1e9
+    gn = 2.0 * prod / tn / 1e9
+    log(f"cpu oracle: {rows.size} rows ({prod} products): 1 thread {t1:.1f}s {g1:.3f} GFLOPS; "
+        f"{threads} threads {tn:.1f}s {gn:.3f} GFLOPS")
+    return {"value": round(gn, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}-th row in n_prod order ({rows.size} rows, {prod} of {tot} "
+                      f"products), C oracle (symbolic + numeric), row-parallel on {threads} threads",
+            "single_thread": {"value": round(g1, 4), "seconds": round(t1, 2)},
+            "seconds": round(tn, 2), "cpu_model": cpu_model()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="st27_100")
+    ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "learned", "copy"],
                     help="plain: the headline product; batched: 512 uneven products as one "
                          "batch vs 512 plain calls; learned: one-phase product with the trained "
@@ -113,6 +300,8 @@ def main():
     ap.add_argument("--no-tuning", action="store_true",
                     help="plain mode: use the built-in bin configuration instead of the "
                          "autotuned one of the workload's class")
+    ap.add_argument("--secondary", default="st27_100",
+                    help="plain mode: a second workload reported beside the headline ('' = none)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -138,94 +327,14 @@ def main():
     if args.mode == "copy":
         return bench_copy(args, dev)
 
-    desc, builder = syn.WORKLOADS[args.workload]
-    t0 = time.time()
-    A = builder()
-    log(f"workload {args.workload}: {A.rows} rows, {A.nnz} nnz, generated in {time.time() - t0:.1f}s")
-    dA = ops.DeviceCSR.from_host(A, dev)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    sh = stream.cuda_stream
-    Ac = dA._c_fast(A.nnz)
-
-    # bin configuration: the autotuner's choice for the workload's class
-    from paper_2206_07244_amd import autotune
-    cls = workload_class(args.workload)
-    tuned = None if args.no_tuning else autotune.load_config(cls)
-    tref = ops.byref(tuned) if tuned is not None else None
-    log(f"bin configuration: {'tuned for ' + cls if tuned is not None else 'built-in'}")
-
-    # warm-up (also fills the memory pool)
-    st = ops.Stats()
-    for _ in range(max(args.warmup, 1)):
-        Cc = ops.opsp_csr()
-        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), tref,
-                                        ops.byref(st), sh)
-        if code:
-            raise ops.OpspError(code, "opsp_spgemm_ex")
-        ops.free_raw(Cc, sh)
-    torch.cuda.synchronize()
-    nprod, nnzC = st.nprod, st.nnz
-    log(f"n_prod={nprod} nnz(C)={nnzC} CR={nprod / max(nnzC, 1):.3f} bins sym={list(st.sym_bin_rows)} "
-        f"num={list(st.num_bin_rows)}")
-
-    # timed region: K whole products
-    L = ops.lib()
-
-    def timed(cref):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            Cc = ops.opsp_csr()
-            code = L.opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), cref, None, sh)
-            if code:
-                raise ops.OpspError(code, "opsp_spgemm_ex")
-            ops.free_raw(Cc, sh)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t1) * 1e3 / args.steps
-    ms = timed(tref)
-    gflops = 2.0 * nprod / (ms * 1e-3) / 1e9
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step, {gflops:.1f} GFLOPS")
-    ms_default = timed(None) if tuned is not None else ms
-    if tuned is not None:
-        log(f"built-in configuration: {ms_default:.3f} ms/step")
-
-    # per-stage kernel durations: same calls, HIP events recorded on the call's
-    # stream between stages (stage 1 = symbolic kernels, 3 = numeric kernels)
-    if tuned is not None:
-        cfg = autotune.load_config(cls)
-        cfg.stage_timing = 1
-    else:
-        cfg = ops.Config(stage_timing=1)
-    stage = np.zeros(8)
-    for _ in range(args.steps):
-        Cc = ops.opsp_csr()
-        s2 = ops.Stats()
-        code = ops.lib().opsp_spgemm_ex(ops.byref(Ac), ops.byref(Ac), ops.byref(Cc), ops.byref(cfg),
-                                        ops.byref(s2), sh)
-        if code:
-            raise ops.OpspError(code, "opsp_spgemm_ex")
-        ops.free_raw(Cc, sh)
-        stage += np.array(list(s2.ms_stage))
-    torch.cuda.synchronize()
-    stage /= args.steps
-    log("stage ms (setup+bin, symbolic, numbin+scan, numeric, total):",
-        [round(x, 4) for x in stage[:5]])
-
-    M, nnzA = A.rows, A.nnz
-    nb = numeric_bytes(M, nnzA, nprod, nnzC)
-    sb = symbolic_bytes(M, nnzA, nprod)
-    num_ms, sym_ms = stage[3], stage[1]
-    if num_ms >= sym_ms:
-        kernel, bytes_, kms = "numeric", nb, num_ms
-    else:
-        kernel, bytes_, kms = "symbolic", sb, sym_ms
-    achieved = bytes_ / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-
+    r = measure_plain(ops, torch, np, syn, args.workload, args.steps, args.warmup, dev,
+                      tuned_cls=not args.no_tuning)
+    A, dA = r["A"], r["dA"]
+    nprod, nnzC, ms = r["nprod"], r["nnzC"], r["ms"]
+    st = r["stage"]
     out = {
         "metric": METRIC,
-        "value": round(gflops, 3),
+        "value": round(r["gflops"], 3),
         "unit": "GFLOPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -236,28 +345,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "rows": M, "nnzA": nnzA,
+        "config": {"workload": args.workload, "description": r["desc"], "rows": A.rows, "nnzA": A.nnz,
                    "nprod": nprod, "nnzC": nnzC, "path": "plain two-pass",
-                   "bins": f"autotuned ({cls})" if tuned is not None else "built-in"},
-        "builtin_config": {"value": round(2.0 * nprod / (ms_default * 1e-3) / 1e9, 3),
-                           "ms_per_step": round(ms_default, 4)},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes": bytes_, "kernel_ms": round(kms, 4)},
-        "stage_ms": {"setup_bin": round(stage[0], 4), "symbolic": round(stage[1], 4),
-                     "numbin_scan_alloc": round(stage[2], 4), "numeric": round(stage[3], 4),
-                     "total": round(stage[4], 4)},
+                   "bins": f"autotuned ({r['cls']})" if r["tuned"] else "built-in"},
+        "roofline": r["roofline"],
+        "stage_ms": {"setup_bin": round(st[0], 4), "symbolic": round(st[1], 4),
+                     "numbin_scan_alloc": round(st[2], 4), "numeric": round(st[3], 4),
+                     "total": round(st[4], 4), "long_row_numeric_kernel": round(st[5], 4)},
     }
-
-    rec = stored_traffic(kernel, args.workload)
-    if rec is not None:
-        out["roofline"]["traffic"] = int(rec["bytes_per_launch"])
-        out["roofline"]["traffic_source"] = rec.get("file", "profiles")
+    if r["ms_default"] is not None:
+        out["builtin_config"] = {"value": round(2.0 * nprod / (r["ms_default"] * 1e-3) / 1e9, 3),
+                                 "ms_per_step": round(r["ms_default"], 4)}
 
     if not args.no_learned and os.path.exists(ops.DEFAULT_WEIGHTS):
         pred = ops.Predictor.load(device=dev)
         try:
-            r = time_learned(ops, torch, dA, dA, pred, args.steps, args.warmup)
+            rl = time_learned(ops, torch, dA, dA, pred, args.steps, args.warmup)
         except ops.OpspError as e:
             # the one-phase product holds its capacity arena, the staging
             # buffer and C at once; a product that does not fit that way is
@@ -268,26 +371,27 @@ def main():
             out["learned"] = {"skipped": f"one-phase product does not fit in device memory ({e})"}
             log(f"learned one-phase: skipped, {e}")
         else:
-            out["learned"] = {"value": round(2.0 * nprod / (r["ms"] * 1e-3) / 1e9, 3),
-                              "ms_per_step": round(r["ms"], 4),
-                              "speedup_vs_plain": round(ms / r["ms"], 4), **r["stats"]}
-            log(f"learned one-phase: {r['ms']:.3f} ms/step ({ms / r['ms']:.3f}x plain)")
+            out["learned"] = {"value": round(2.0 * nprod / (rl["ms"] * 1e-3) / 1e9, 3),
+                              "ms_per_step": round(rl["ms"], 4),
+                              "speedup_vs_plain": round(ms / rl["ms"], 4), **rl["stats"]}
+            log(f"learned one-phase: {rl['ms']:.3f} ms/step ({ms / rl['ms']:.3f}x plain)")
+
+    if args.secondary and args.secondary != args.workload:
+        del dA
+        torch.cuda.synchronize()
+        r2 = measure_plain(ops, torch, np, syn, args.secondary, args.steps, args.warmup, dev,
+                           tuned_cls=not args.no_tuning, builtin=False)
+        out["secondary"] = {"workload": args.secondary, "description": r2["desc"],
+                            "value": round(r2["gflops"], 3), "unit": "GFLOPS",
+                            "ms_per_step": round(r2["ms"], 4), "nprod": r2["nprod"], "nnzC": r2["nnzC"],
+                            "roofline": r2["roofline"],
+                            "stage_ms": {k: round(float(v), 4) for k, v in
+                                         zip(["setup_bin", "symbolic", "numbin_scan_alloc", "numeric",
+                                              "total"], r2["stage"][:5])}}
+        del r2
 
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        reps, el = 0, 0.0
-        tc = time.perf_counter()
-        while reps == 0 or (el < args.cpu_seconds and reps < 50):
-            oracle.spgemm(A, A, with_scale=False)
-            reps += 1
-            el = time.perf_counter() - tc
-        cpu_gflops = 2.0 * nprod * reps / el / 1e9
-        out["cpu_baseline"] = {"value": round(cpu_gflops, 4), "unit": "GFLOPS", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"whole {args.workload} product, {reps} run(s), {el:.1f}s, "
-                                         "single-threaded C oracle (symbolic + numeric)"}
-        log(f"cpu oracle: {cpu_gflops:.3f} GFLOPS over {reps} run(s)")
+        out["cpu_baseline"] = cpu_baseline(A, np, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
 

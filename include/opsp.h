@@ -120,7 +120,8 @@ typedef struct {
     int64_t num_bin_rows[OPSP_NUM_BINS];
     /* Stage times in ms when config.stage_timing != 0:
      * two-phase calls: 0 setup+binning, 1 symbolic, 2 numeric
-     *   binning+scan+allocation, 3 numeric, 4 total;
+     *   binning+scan+allocation, 3 numeric, 4 total, 5 the numeric
+     *   kernel of the longest rows (bin 7) alone (0 when it did not run);
      * opsp_spgemm_learned: 0 setup+capacities+binning+slot scan,
      *   1 one-phase numeric, 2 recompute+row-pointer scan+allocation of C,
      *   3 copy into C, 4 total */
@@ -325,6 +326,17 @@ opsp_status opsp_spgemm_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *
  * current device. */
 opsp_status opsp_cache_release(void);
 int64_t opsp_cache_bytes(void);
+
+/* Bytes of the blocks that the cache has handed out on the current device
+ * and not yet taken back (C arrays a caller still holds included).  A call
+ * that fails leaves this where it was before the call. */
+int64_t opsp_cache_live_bytes(void);
+
+/* Testing hook: after the next n successful allocations of the library,
+ * the following one fails as if the device were out of memory (once);
+ * n < 0 switches the hook off.  Lets a test drive every error exit of a
+ * call and check that nothing stays allocated. */
+void opsp_debug_fail_alloc(int64_t n);
 
 /* Host-side helpers (no device work; usable without a GPU).
  * Table sizes of the per-bin hash tables, in entries (-1 = global-memory

@@ -156,6 +156,10 @@ def lib():
         L.opsp_cache_release.argtypes = []
         L.opsp_cache_bytes.restype = c_int64
         L.opsp_cache_bytes.argtypes = []
+        L.opsp_cache_live_bytes.restype = c_int64
+        L.opsp_cache_live_bytes.argtypes = []
+        L.opsp_debug_fail_alloc.restype = None
+        L.opsp_debug_fail_alloc.argtypes = [c_int64]
         L.opsp_table_sizes.restype = ctypes.c_int
         L.opsp_table_sizes.argtypes = [c_int32, POINTER(c_int64), c_int32]
         L.opsp_bin_bounds.restype = ctypes.c_int
@@ -192,6 +196,17 @@ def cache_release():
 
 def cache_bytes() -> int:
     return int(lib().opsp_cache_bytes())
+
+
+def cache_live_bytes() -> int:
+    """Bytes the library has handed out and not taken back (see the header)."""
+    return int(lib().opsp_cache_live_bytes())
+
+
+def debug_fail_alloc(n: int):
+    """Testing: the allocation after the next `n` successful ones fails
+    (once); n < 0 switches this off."""
+    lib().opsp_debug_fail_alloc(int(n))
 
 
 def _check(code: int, where: str):

@@ -11,6 +11,7 @@
 // Blocks come from hipMallocAsync on the requesting stream; when that fails,
 // the cache of the device is returned to HIP (after a device synchronise)
 // and the allocation is retried.  opsp_cache_release() empties the cache.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -32,10 +33,22 @@ struct DeviceCache {
     std::map<std::pair<hipStream_t, size_t>, std::vector<void *>> free_lists;
     std::unordered_map<void *, Block> live;    // handed-out blocks
     size_t cached_bytes = 0;
+    size_t live_bytes = 0;
 };
 
 std::mutex g_cache_mu;
 std::unordered_map<int, DeviceCache> g_cache;
+
+// Testing: allocations still to succeed before one fails (-1 = never).
+std::atomic<int64_t> g_fail_after{-1};
+
+bool injected_failure() {
+    int64_t n = g_fail_after.load();
+    while (n >= 0) {
+        if (g_fail_after.compare_exchange_weak(n, n - 1)) return n == 0;
+    }
+    return false;
+}
 
 // Size classes: multiples of 256 B below 64 KB, then 8 classes per power of
 // two (at most 12.5 % rounding).
@@ -63,6 +76,7 @@ hipError_t cache_alloc(void **out, size_t bytes, hipStream_t s) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    if (injected_failure()) return hipErrorOutOfMemory;
     const size_t cls = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -72,6 +86,7 @@ hipError_t cache_alloc(void **out, size_t bytes, hipStream_t s) {
             void *p = it->second.back();
             it->second.pop_back();
             dc.cached_bytes -= cls;
+            dc.live_bytes += cls;
             dc.live[p] = Block{p, cls};
             *out = p;
             return hipSuccess;
@@ -93,6 +108,7 @@ hipError_t cache_alloc(void **out, size_t bytes, hipStream_t s) {
     }
     std::lock_guard<std::mutex> lk(g_cache_mu);
     g_cache[dev].live[*out] = Block{*out, cls};
+    g_cache[dev].live_bytes += cls;
     return hipSuccess;
 }
 
@@ -110,6 +126,7 @@ hipError_t cache_free(void *p, hipStream_t s) {
         if (it != dc.live.end()) {
             const size_t cls = it->second.bytes;
             dc.live.erase(it);
+            dc.live_bytes -= cls;
             dc.free_lists[{s, cls}].push_back(p);
             dc.cached_bytes += cls;
             return hipSuccess;
@@ -134,6 +151,13 @@ size_t cache_bytes() {
     return g_cache[dev].cached_bytes;
 }
 
+size_t live_bytes() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return g_cache[dev].live_bytes;
+}
+
 }  // namespace opsp
 
 extern "C" {
@@ -143,5 +167,9 @@ opsp_status opsp_cache_release(void) {
 }
 
 int64_t opsp_cache_bytes(void) { return (int64_t)opsp::cache_bytes(); }
+
+int64_t opsp_cache_live_bytes(void) { return (int64_t)opsp::live_bytes(); }
+
+void opsp_debug_fail_alloc(int64_t n) { opsp::g_fail_after.store(n < 0 ? -1 : n); }
 
 }  // extern "C"

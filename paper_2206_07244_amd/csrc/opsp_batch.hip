@@ -364,6 +364,18 @@ opsp_status opsp_batch_create(int32_t count, const opsp_csr *A, const opsp_csr *
         return fail(OPSP_ERR_NO_DEVICE);
     b->cus = cus > 0 ? cus : 256;
 
+    if (cfg && cfg->validate) {
+        // every operand canonical before the structure graph gathers through them
+        std::vector<const opsp_csr *> X;
+        X.reserve(2 * (size_t)count);
+        for (int p = 0; p < count; ++p) {
+            if (!opsp::host::csr_ok(&A[p]) || !opsp::host::csr_ok(&B[p])) return fail(OPSP_ERR_INVALID);
+            X.push_back(&A[p]);
+            X.push_back(&B[p]);
+        }
+        st = opsp::host::validate_csr(X.data(), (int)X.size(), s);
+        if (st != OPSP_OK) return fail(st);
+    }
     // problem layout
     b->desc.resize(count);
     b->N.resize(count);

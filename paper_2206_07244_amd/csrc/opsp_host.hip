@@ -201,6 +201,24 @@ hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipSt
 }
 
 
+opsp_status validate_csr(const opsp_csr *const *X, int n, hipStream_t s) {
+    Arena ar(s);
+    void *p = nullptr;
+    CHK(ar.alloc(&p, sizeof(unsigned int) * (size_t)(n > 0 ? n : 1)));
+    unsigned int *flags = (unsigned int *)p;
+    CHK(hipMemsetAsync(flags, 0, sizeof(unsigned int) * (size_t)n, s));
+    for (int k = 0; k < n; ++k)
+        CHK(launch_check_csr(X[k]->rows, X[k]->cols, X[k]->nnz, X[k]->rpt, X[k]->col, flags + k, s));
+    unsigned int h[64];
+    for (int k0 = 0; k0 < n; k0 += 64) {
+        const int m = n - k0 < 64 ? n - k0 : 64;
+        CHK(read_back(h, flags + k0, sizeof(unsigned int) * (size_t)m, s));
+        for (int k = 0; k < m; ++k)
+            if (h[k]) return OPSP_ERR_INVALID;
+    }
+    return OPSP_OK;
+}
+
 RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows) {
     RowSrc r;
     memset(&r, 0, sizeof(r));
@@ -231,6 +249,11 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     plan->N = N;
     plan->check = cfg && cfg->validate;
     plan->fixed_grid = cfg ? cfg->fixed_grid : 0;
+    if (plan->check) {
+        const opsp_csr *X[2] = {A, B};
+        opsp_status vs = validate_csr(X, 2, s);
+        if (vs != OPSP_OK) return vs;
+    }
 
     Arena ar(s);
     void *p = nullptr;
@@ -400,7 +423,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 
 // Step 6 into caller-visible C arrays.
 opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, int32_t *ccol,
-                        double *cval, hipStream_t s) {
+                        double *cval, hipStream_t s, Timer *kt = nullptr) {
     int dev = 0, cus = 256;
     opsp_status st = init_device(&dev, &cus);
     if (st != OPSP_OK) return st;
@@ -439,7 +462,9 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
             na.slab_vals = (double *)pv;
             na.slab_entries = cap;
             na.grid = grid;
+            if (kt) kt->mark();
             CHK(launch_numeric_bucket(na, s));
+            if (kt) kt->mark();
             first = false;
             continue;
         }
@@ -453,7 +478,9 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
             na.slab_entries = entries;
             na.grid = grid;
         }
+        if (kt && b == gb) kt->mark();
         CHK(launch_numeric_bin(b, na, s));
+        if (kt && b == gb) kt->mark();
         first = false;
     }
     (void)first;
@@ -526,7 +553,8 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
             return status_of(e);
         }
     }
-    st = run_numeric(&plan, A, B, (int32_t *)pc, (double *)pv, s);
+    Timer kt(tm.on, s);
+    st = run_numeric(&plan, A, B, (int32_t *)pc, (double *)pv, s, &kt);
     tm.mark();
     if (st == OPSP_OK && plan.check) st = check_errors(&plan, s);
     if (st != OPSP_OK) {
@@ -548,6 +576,7 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
             (void)hipStreamSynchronize(s);
             for (int k = 0; k < 4; ++k) stats->ms_stage[k] = tm.between(k, k + 1);
             stats->ms_stage[4] = tm.between(0, 4);
+            stats->ms_stage[5] = kt.between(0, 1);
         }
     }
     plan_release(&plan, s);

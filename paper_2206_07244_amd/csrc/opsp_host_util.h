@@ -32,6 +32,11 @@ opsp_status check_config(const opsp_config *c);
 hipError_t read_back(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t read_counters(Counters *dst, const Counters *src, size_t count, hipStream_t s);
 RowSrc host_rows(const int32_t *bins, int64_t off, int64_t nrows);
+// Validation mode: checks on the device that each of the `n` matrices is
+// canonical CSR (monotone row pointer covering exactly nnz entries, column
+// indices in range and strictly ascending per row) before anything gathers
+// through them; OPSP_ERR_INVALID if one is not.  Blocks the host once.
+opsp_status validate_csr(const opsp_csr *const *X, int n, hipStream_t s);
 // Bytes the bucketed long-row kernel may take for staging.  Fixed, so that
 // repeated products request the same block from the allocation cache (a
 // budget following the free memory made the request size drift between

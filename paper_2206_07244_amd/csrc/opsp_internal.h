@@ -64,6 +64,14 @@ hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counter
                           int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
                           int64_t *vout = nullptr);
 
+// ---- input check of the validation mode (kernels_check.hip) ----------------
+// Sets bits of *flags (zeroed before): 1 = rpt not monotone, rpt[0] < 0 or
+// rpt[rows] - rpt[0] != nnz; 2 = a column index outside [0, cols); 4 =
+// columns not strictly ascending in a row.  col is read only when bit 1
+// stays clear.
+hipError_t launch_check_csr(int64_t rows, int64_t cols, int64_t nnz, const int64_t *rpt,
+                            const int32_t *col, unsigned int *flags, hipStream_t s);
+
 // ---- symbolic step (kernels_sym.hip) ---------------------------------------
 struct SymArgs {
     DevCSR A, B;

@@ -90,6 +90,11 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     opsp_status st = init_device(&dev, &cus);
     if (st != OPSP_OK) return st;
     const int64_t M = A->rows, N = B->cols;
+    if (cfg && cfg->validate) {
+        const opsp_csr *X[2] = {A, B};
+        st = validate_csr(X, 2, s);
+        if (st != OPSP_OK) return st;
+    }
     Timer tm(cfg && cfg->stage_timing, s);
     opsp_stats S;
     memset(&S, 0, sizeof(S));
