@@ -321,9 +321,10 @@ opsp_status opsp_spgemm_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *
  * kept, per stream and size class, and handed out again to later calls on the
  * same stream without any HIP allocation call (on this stack a pool
  * allocation or release costs tens to hundreds of microseconds of host
- * time).  opsp_cache_release() synchronises the current device and returns
- * every cached block to HIP; opsp_cache_bytes() reports what is cached on the
- * current device. */
+ * time).  opsp_cache_release() synchronises the current device, returns
+ * every cached block to HIP and trims the device's default memory pool, so
+ * that the memory is free for other allocators of the process;
+ * opsp_cache_bytes() reports what is cached on the current device. */
 opsp_status opsp_cache_release(void);
 int64_t opsp_cache_bytes(void);
 

@@ -60,12 +60,20 @@ size_t size_class(size_t bytes) {
     return (bytes + step - 1) / step * step;
 }
 
-void release_device(int dev, DeviceCache &dc) {
-    (void)dev;
+// Frees every cached block of device `dev` (current) and, with `trim`,
+// shrinks the device's default pool to what is still allocated from it: the
+// library raises the pool's release threshold, so freed blocks would stay
+// reserved by the pool and out of reach of other allocators in the process.
+void release_device(int dev, DeviceCache &dc, bool trim) {
     for (auto &kv : dc.free_lists)
         for (void *p : kv.second) (void)hipFree(p);
     dc.free_lists.clear();
     dc.cached_bytes = 0;
+    hipMemPool_t pool;
+    if (trim && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        (void)hipDeviceSynchronize();
+        (void)hipMemPoolTrimTo(pool, 0);
+    }
 }
 
 }  // namespace
@@ -98,11 +106,14 @@ hipError_t cache_alloc(void **out, size_t bytes, hipStream_t s) {
         (void)hipDeviceSynchronize();
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
-            release_device(dev, g_cache[dev]);
+            release_device(dev, g_cache[dev], false);
         }
         e = hipMallocAsync(out, cls, s);
     }
     if (e != hipSuccess) {
+        // the status goes back to the caller; leave no error behind for the
+        // next HIP call of the process to report as its own
+        (void)hipGetLastError();
         *out = nullptr;
         return e;
     }
@@ -140,7 +151,7 @@ hipError_t cache_release_all() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    release_device(dev, g_cache[dev]);
+    release_device(dev, g_cache[dev], true);
     return e;
 }
 
