@@ -41,7 +41,9 @@ typedef enum {
     OPSP_ERR_OVERFLOW = 4,  /* a count exceeds its index type (e.g. a row of C above 2^31-1 entries) */
     OPSP_ERR_HIP = 5,       /* a HIP runtime call or kernel launch failed */
     OPSP_ERR_INTERNAL = 6,  /* internal consistency check failed */
-    OPSP_ERR_NO_DEVICE = 7  /* no usable gfx950 device */
+    OPSP_ERR_NO_DEVICE = 7, /* no usable gfx950 device */
+    OPSP_ERR_SCRATCH = 8    /* the product needs more scratch than the fixed buffer of
+                               opsp_spgemm_numeric_noalloc holds */
 } opsp_status;
 
 /* A CSR matrix in device memory (see the format note above). */
@@ -175,6 +177,30 @@ opsp_status opsp_spgemm_symbolic(const opsp_csr *A, const opsp_csr *B, const ops
  * buffer of rows+1 / nnzC / nnzC elements that is filled in. */
 opsp_status opsp_spgemm_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B,
                                 opsp_csr *C, void *stream);
+
+/* Numeric phase for a plan that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Same result as opsp_spgemm_numeric.
+ *   C      : caller buffers, all required: C->rpt int64[rows+1], C->col
+ *            int32[nnzC] and C->val double[nnzC] (col/val may be NULL when
+ *            nnzC == 0).  On success C->rows/cols/nnz are set; on error the
+ *            pointers are left as they were.
+ *   scratch: the long-row bin (numeric bin 7: staging of the bucketed kernel,
+ *            or the global hash tables) works in one fixed device buffer of
+ *            OPSP_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library is
+ *            loaded and held until the process ends.  Its grid is cut to what
+ *            fits; a product whose single workgroup needs more (bucketed:
+ *            12 (max row n_prod + 1) + 512 bytes; hashed: 12 next_pow2(2 max
+ *            row nnz) + 512 bytes) returns OPSP_ERR_SCRATCH.  Every call on
+ *            a GPU shares that GPU's buffer: calls that overlap in time on one
+ *            GPU (two streams, two threads) race and give wrong results.
+ *   No hipMalloc, hipFree, pool or cache allocation and no host
+ *   synchronisation happen inside the call; the internal consistency check
+ *   of a validating plan is not run.  C is complete when the stream reaches
+ *   the point of return. */
+#define OPSP_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+opsp_status opsp_spgemm_numeric_noalloc(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B,
+                                        opsp_csr *C, void *stream);
 
 /* Release a plan (stream-ordered on the plan's last stream). NULL is a no-op. */
 void opsp_plan_destroy(opsp_plan *plan);

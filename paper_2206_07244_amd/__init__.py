@@ -139,6 +139,8 @@ def lib():
                                            POINTER(c_int64), P]
         L.opsp_spgemm_numeric.restype = ctypes.c_int
         L.opsp_spgemm_numeric.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
+        L.opsp_spgemm_numeric_noalloc.restype = ctypes.c_int
+        L.opsp_spgemm_numeric_noalloc.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
         L.opsp_plan_destroy.restype = None
         L.opsp_plan_destroy.argtypes = [c_void_p]
         L.opsp_csr_free.restype = ctypes.c_int
@@ -396,6 +398,29 @@ def spgemm_numeric(plan: Plan, A: DeviceCSR, B: DeviceCSR, out: Optional[DeviceC
     if out is not None:
         return out
     return _adopt(Cc, s, A.rpt.device)
+
+
+# Bytes of the fixed device scratch behind spgemm_numeric_noalloc.
+NOALLOC_SCRATCH_BYTES = 64 << 20
+ERR_SCRATCH = 8
+
+
+def spgemm_numeric_noalloc(plan: Plan, A: DeviceCSR, B: DeviceCSR, out: DeviceCSR,
+                           stream=None) -> DeviceCSR:
+    """Numeric phase into caller buffers ``out`` (rpt int64[rows+1], col
+    int32[nnz], val float64[nnz]) through ``opsp_spgemm_numeric_noalloc``:
+    no device allocation inside the call; the long-row bin works in the
+    library's fixed per-GPU scratch (concurrent calls on one GPU race)."""
+    s = _stream_handle(stream)
+    Ac, Bc = A._c(), B._c()
+    assert out.rpt.numel() == plan.rows + 1 and out.col.numel() == plan.nnz == out.val.numel()
+    Cc = opsp_csr()
+    Cc.rpt = out.rpt.data_ptr()
+    Cc.col = out.col.data_ptr() if plan.nnz else None
+    Cc.val = out.val.data_ptr() if plan.nnz else None
+    _check(lib().opsp_spgemm_numeric_noalloc(plan.handle, byref(Ac), byref(Bc), byref(Cc), s),
+           "opsp_spgemm_numeric_noalloc")
+    return out
 
 
 # ---------------------------------------------------------------------------

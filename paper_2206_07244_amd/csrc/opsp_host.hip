@@ -51,6 +51,42 @@ namespace {
 const char *kVersion = "opsp 0.1.0 (gfx950)";
 }  // namespace
 
+// Fixed device scratch of opsp_spgemm_numeric_noalloc (the long-row bin's
+// staging or global tables).  Every device that loads the library holds its
+// own copy until the process ends.  On the host the array's name is not a
+// device address: host code uses only the per-device address that
+// hipGetSymbolAddress returns (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[OPSP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_addr[64];
+
+// Address of `scratch` on device `dev`, which must be current; looked up once
+// per device.
+opsp_status scratch_address(int dev, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? OPSP_ERR_ALLOC : OPSP_ERR_HIP;
+        if (!p) return OPSP_ERR_HIP;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return OPSP_OK;
+}
+
+// A caller-provided device region that replaces the allocations of the
+// long-row numeric bin.
+struct ScratchBuf {
+    char *p;
+    int64_t bytes;
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+}  // namespace
+
 namespace opsp {
 namespace host {
 
@@ -422,8 +458,12 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 }
 
 // Step 6 into caller-visible C arrays.
+// With `scr`, the long-row bin works in that region (its grid cut to fit)
+// instead of allocating; OPSP_ERR_SCRATCH when one workgroup's share does
+// not fit.
 opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, int32_t *ccol,
-                        double *cval, hipStream_t s, Timer *kt = nullptr) {
+                        double *cval, hipStream_t s, Timer *kt = nullptr,
+                        const ScratchBuf *scr = nullptr) {
     int dev = 0, cus = 256;
     opsp_status st = init_device(&dev, &cus);
     if (st != OPSP_OK) return st;
@@ -456,8 +496,16 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
             int64_t grid = rows < (int64_t)cus * BUCKET_WG_PER_CU ? rows : (int64_t)cus * BUCKET_WG_PER_CU;
             const int64_t fit = STAGING_BUDGET / (cap * 12);
             if (grid > fit) grid = fit > 1 ? fit : 1;
-            CHK(ar.alloc(&pk, sizeof(int) * (size_t)(cap * grid)));
-            CHK(ar.alloc(&pv, sizeof(double) * (size_t)(cap * grid)));
+            if (scr) {
+                const int64_t g = (scr->bytes - 256) / (cap * 12);
+                if (g < 1) return OPSP_ERR_SCRATCH;
+                if (grid > g) grid = g;
+                pk = scr->p;
+                pv = scr->p + align256(cap * grid * (int64_t)sizeof(int));
+            } else {
+                CHK(ar.alloc(&pk, sizeof(int) * (size_t)(cap * grid)));
+                CHK(ar.alloc(&pv, sizeof(double) * (size_t)(cap * grid)));
+            }
             na.slab_keys = (int *)pk;
             na.slab_vals = (double *)pv;
             na.slab_entries = cap;
@@ -470,9 +518,17 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
         }
         if (b == gb) {
             const int64_t entries = pow2_host(2 * plan->max_nnz > 64 ? 2 * plan->max_nnz : 64);
-            const int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
-            CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
-            CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));
+            int64_t grid = rows < (int64_t)cus * NUM_GLOBAL_WG_PER_CU ? rows : (int64_t)cus * NUM_GLOBAL_WG_PER_CU;
+            if (scr) {
+                const int64_t g = (scr->bytes - 256) / (entries * 12);
+                if (g < 1) return OPSP_ERR_SCRATCH;
+                if (grid > g) grid = g;
+                pk = scr->p;
+                pv = scr->p + align256(entries * grid * (int64_t)sizeof(int));
+            } else {
+                CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
+                CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));
+            }
             na.slab_keys = (int *)pk;
             na.slab_vals = (double *)pv;
             na.slab_entries = entries;
@@ -523,6 +579,9 @@ const char *opsp_status_string(opsp_status s) {
         case OPSP_ERR_HIP: return "OPSP_ERR_HIP: HIP runtime error";
         case OPSP_ERR_INTERNAL: return "OPSP_ERR_INTERNAL: internal consistency check failed";
         case OPSP_ERR_NO_DEVICE: return "OPSP_ERR_NO_DEVICE: no usable device";
+        case OPSP_ERR_SCRATCH:
+            return "OPSP_ERR_SCRATCH: the product needs more than the fixed scratch of the "
+                   "no-allocation entry point";
     }
     return "unknown opsp status";
 }
@@ -649,6 +708,33 @@ opsp_status opsp_spgemm_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_c
     C->rpt = (int64_t *)pr;
     C->col = (int32_t *)pc;
     C->val = (double *)pv;
+    return OPSP_OK;
+}
+
+opsp_status opsp_spgemm_numeric_noalloc(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B,
+                                        opsp_csr *C, void *stream) {
+    if (!plan || !C) return OPSP_ERR_INVALID;
+    opsp_status st = check_inputs(A, B);
+    if (st != OPSP_OK) return st;
+    if (A->rows != plan->M || A->cols != plan->K || B->cols != plan->N) return OPSP_ERR_SHAPE;
+    const int64_t nnz = plan->nnzC;
+    if (!C->rpt || (nnz > 0 && (!C->col || !C->val))) return OPSP_ERR_INVALID;
+    int dev = 0, cus = 256;
+    st = init_device(&dev, &cus);
+    if (st != OPSP_OK) return st;
+    if (dev != plan->device) return OPSP_ERR_INVALID;
+    void *base = nullptr;
+    st = scratch_address(dev, &base);
+    if (st != OPSP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    CHK(hipMemcpyAsync(C->rpt, plan->crpt, sizeof(int64_t) * (size_t)(plan->M + 1),
+                       hipMemcpyDeviceToDevice, s));
+    const ScratchBuf sb{(char *)base, (int64_t)OPSP_NOALLOC_SCRATCH_BYTES};
+    st = run_numeric(plan, A, B, C->col, C->val, s, nullptr, &sb);
+    if (st != OPSP_OK) return st;
+    C->rows = plan->M;
+    C->cols = plan->N;
+    C->nnz = nnz;
     return OPSP_OK;
 }
 

@@ -26,7 +26,7 @@ def test_library_loads_and_exports_header_symbols():
 def test_version_and_status_strings():
     L = ops.lib()
     assert b"gfx950" in L.opsp_version()
-    for code in range(8):
+    for code in range(9):
         assert L.opsp_status_string(code).startswith(b"OPSP_")
     assert b"unknown" in L.opsp_status_string(99)
 
