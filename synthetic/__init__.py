@@ -15,7 +15,8 @@ Section 2.1.1.  Random draws use numpy's PCG64 (``numpy.random.default_rng``),
 a published generator, so every matrix is a pure function of its seed.
 
 The workload families stand in for the paper's SuiteSparse A^2 benchmarks
-(Section 6.1, matrix table): regular stencils (FEM/structured class),
+(Section 6.1, matrix table): regular stencils (FEM/structured class; with
+dense node blocks, the high compression-ratio FEM matrices),
 R-MAT power-law graphs (webbase/wb-edu class, giant rows), random banded and
 Poisson-uniform rows (low compression-ratio class).
 """
@@ -30,6 +31,7 @@ __all__ = [
     "CSR", "lap5", "stencil27", "stencil", "rmat", "poisson_uniform",
     "banded", "random_csr", "identity", "batch_pairs", "training_set", "training_matrix",
     "WORKLOADS",
+    "block_stencil27",
 ]
 
 
@@ -142,6 +144,33 @@ def stencil27(g: int, seed: int = 27) -> CSR:
     in {-1,0,1}^3 that stays in the grid; values U[-1,1) from ``seed``."""
     offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
     return stencil([g, g, g], offs, values="uniform", seed=seed)
+
+
+def block_stencil27(g: int, dof: int = 3, seed: int = 40) -> CSR:
+    """27-point stencil on a g^3 grid with a dense dof x dof block per node
+    coupling (a finite-element-like matrix with `dof` unknowns per node):
+    scalar index dof * node + component, node index (z*g + y)*g + x; node i
+    couples to every in-grid node j with |x_i - x_j|, |y_i - y_j|,
+    |z_i - z_j| <= 1, and row dof*i + a holds columns dof*j + b for all such
+    j and every b.  Values U[-1,1) in CSR order from ``seed``."""
+    node = stencil27(g, seed=0)
+    n_nodes = node.rows
+    nlen = np.diff(node.rpt)
+    # the columns of one node row, each expanded into its dof components
+    exp = (dof * node.col.astype(np.int64))[:, None] + np.arange(dof, dtype=np.int64)[None, :]
+    exp = exp.reshape(-1)                                   # node rows back to back
+    seg_start = dof * node.rpt[:-1]                          # where node row i starts in exp
+    seg_len = dof * nlen
+    # every node row repeated dof times (once per component)
+    rep_start = np.repeat(seg_start, dof)
+    rep_len = np.repeat(seg_len, dof)
+    rpt = np.zeros(dof * n_nodes + 1, dtype=np.int64)
+    np.cumsum(rep_len, out=rpt[1:])
+    idx = np.repeat(rep_start - rpt[:-1], rep_len) + np.arange(rpt[-1], dtype=np.int64)
+    col = exp[idx].astype(np.int32)
+    rng = np.random.default_rng(seed)
+    val = rng.random(col.size) * 2.0 - 1.0
+    return CSR(dof * n_nodes, dof * n_nodes, rpt, col, val)
 
 
 # ---------------------------------------------------------------------------
@@ -343,4 +372,7 @@ WORKLOADS = {
                lambda: rmat(21, 16, 0.57, 0.19, 0.19, seed=21)),
     "band21": ("random banded n=2^21, half-bandwidth 64, 12 per row, seed 22, C = A^2",
                lambda: banded(1 << 21, 64, 12, seed=22)),
+    "bst27_40": ("3-D 27-point stencil 40^3 with dense 3x3 node blocks (3 unknowns per node, "
+                 "compression ratio 17.6), U[-1,1) seed 40, C = A^2",
+                 lambda: block_stencil27(40, 3, seed=40)),
 }

@@ -55,6 +55,18 @@ def test_stencil27_small(g):
     check(syn.stencil27(g, seed=g))
 
 
+@pytest.mark.parametrize("g", [1, 2, 6, 12])
+def test_block_stencil27_small(g):
+    """High compression-ratio rows (3x3 node blocks): closed-form totals and
+    every entry."""
+    st = _ops().Stats()
+    check(syn.block_stencil27(g, 3, seed=g), stats=st)
+    if g >= 2:
+        assert st.nprod == 27 * (9 * g - 10) ** 3
+    if g >= 4:
+        assert st.nnz == 9 * (5 * g - 6) ** 3
+
+
 @pytest.mark.parametrize("scale", [10, 14])
 def test_rmat_all_bins(scale):
     st = _ops().Stats()

@@ -181,6 +181,44 @@ def test_stencil27_square_closed_form(oracle_lib, g):
     assert np.array_equal(nprod, hn[x] * hn[y] * hn[z])
 
 
+@pytest.mark.parametrize("g", [2, 3, 4, 7])
+def test_block_stencil27_square_closed_form(oracle_lib, g):
+    """27-point stencil with dense 3x3 node blocks (the high compression-ratio
+    finite-element class): nnz(A) = 9 (3g-2)^3, n_prod = 27 (9g-10)^3 and
+    nnz(C) = 9 (5g-6)^3, and per scalar row 3x the node-level output count
+    and 9x the node-level product count of the 27-point stencil."""
+    d = 3
+    A = syn.block_stencil27(g, d, seed=g)
+    A.check()
+    assert A.rows == d * g ** 3 and A.nnz == 9 * (3 * g - 2) ** 3
+    nprod, _, _, tot = oracle_lib.row_stats(A, A)
+    nnz = oracle_lib.symbolic(A, A)
+    assert tot == 27 * (9 * g - 10) ** 3
+    if g >= 4:
+        assert nnz.sum() == 9 * (5 * g - 6) ** 3
+    f = np.array([min(x, 2) + min(g - 1 - x, 2) + 1 for x in range(g)])
+    h = np.array([min(x, 1) + min(g - 1 - x, 1) + 1 for x in range(g)])
+    hn = np.array([sum(h[xx] for xx in range(max(0, x - 1), min(g, x + 2))) for x in range(g)])
+    node = np.arange(g ** 3).repeat(d)
+    x, y, z = node % g, (node // g) % g, node // (g * g)
+    assert np.array_equal(nnz, d * f[x] * f[y] * f[z])
+    assert np.array_equal(nprod, d * d * hn[x] * hn[y] * hn[z])
+
+
+def test_block_stencil27_against_dense(oracle_lib):
+    A = syn.block_stencil27(2, 3, seed=11)
+    D = syn.to_dense(A)
+    rpt, col, val, S = oracle_lib.spgemm(A, A)
+    r = _rows_of(rpt)
+    P = D @ D
+    Sd = np.abs(D) @ np.abs(D)
+    cnt = (D != 0).astype(np.int64) @ (D != 0).astype(np.int64)
+    mask = np.zeros_like(cnt, dtype=bool)
+    mask[r, col] = True
+    assert np.array_equal(mask, cnt > 0)
+    assert np.all(np.abs(val - P[r, col]) <= 1e-13 * Sd[r, col])
+
+
 # --------------------------------------------------------------------------
 # Identities
 # --------------------------------------------------------------------------
