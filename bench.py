@@ -289,11 +289,15 @@ def main():
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "learned", "copy"],
+    ap.add_argument("--mode", default="plain",
+                    choices=["plain", "batched", "learned", "copy", "ablation"],
                     help="plain: the headline product; batched: 512 uneven products as one "
                          "batch vs 512 plain calls; learned: one-phase product with the trained "
                          "predictor vs the plain two-phase product and the upper-bound rule")
     ap.add_argument("--count", type=int, default=512, help="problems in the batched mode")
+    ap.add_argument("--workloads", default="st27_100,bst27_40,band21,rmat20",
+                    help="ablation mode: workloads of the tables")
+    ap.add_argument("--out", default="", help="ablation mode: also write the tables (markdown) here")
     ap.add_argument("--panel", default="", help="learned mode: 'k/P' = the k-th of P row panels "
                                                  "of equal n_prod (for products beyond HBM)")
     ap.add_argument("--no-learned", action="store_true",
@@ -328,6 +332,8 @@ def main():
         return bench_learned(args, dev)
     if args.mode == "copy":
         return bench_copy(args, dev)
+    if args.mode == "ablation":
+        return bench_ablation(args, dev)
 
     r = measure_plain(ops, torch, np, syn, args.workload, args.steps, args.warmup, dev,
                       tuned_cls=not args.no_tuning)
@@ -411,6 +417,124 @@ def main():
         out["cpu_baseline"] = cpu_baseline(A, np, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+def bench_ablation(args, dev):
+    """The paper's ablations (Section 6.3) on one MI355X, with every row taken
+    by the hash tables as in the paper (config.hash_all_rows):
+      hashing  the symbolic and numeric steps with the single-access probe
+               (one compare-and-swap per probe, the product library) and the
+               multiple-access probe (read, then swap: the library variant
+               built with OPSP_HASH_MULTI_ACCESS), Section 6.3.2;
+      ranges   the symbolic step at binning ratios 1, 1.2, 1.5 and the numeric
+               step at 1, 1.5, 2, 3 (Section 6.3.3; ratio r puts a row in the
+               first table at least r times its n_prod or nnz);
+      binning  the share of the binning kernels in the whole product, with the
+               setup kernel (into which the first binning pass is fused)
+               reported apart (Section 6.3.1), for the paper's hashing and for
+               this library's default (range bitmaps and dense rows).
+    Stage times are HIP events on the calling stream, mean of --steps calls
+    after --warmup."""
+    import ctypes
+    import numpy as np
+    import torch
+    import synthetic as syn
+    import paper_2206_07244_amd as ops
+
+    sh = torch.cuda.current_stream().cuda_stream
+    variants = {"single": ops.lib(), "multi": ops.lib_variant("multi_access")}
+
+    def stages(L, Ac, cfg):
+        acc = np.zeros(8)
+        for k in range(args.warmup + args.steps):
+            Cc = ops.opsp_csr()
+            st = ops.Stats()
+            cfg.stage_timing = 1
+            code = L.opsp_spgemm_ex(ctypes.byref(Ac), ctypes.byref(Ac), ctypes.byref(Cc),
+                                    ctypes.byref(cfg), ctypes.byref(st), sh)
+            if code:
+                raise ops.OpspError(code, "opsp_spgemm_ex")
+            code = L.opsp_csr_free(ctypes.byref(Cc), sh)
+            if k >= args.warmup:
+                acc += np.array(list(st.ms_stage))
+        torch.cuda.synchronize()
+        # each library keeps its own cache: hand it back before the next
+        # configuration (the R-MAT product needs most of the device)
+        L.opsp_cache_release()
+        return acc / args.steps
+
+    res = {}
+    for w in [x for x in args.workloads.split(",") if x]:
+        desc, builder = syn.WORKLOADS[w]
+        A = builder()
+        dA = ops.DeviceCSR.from_host(A, dev)
+        Ac = dA._c_fast(A.nnz)
+        r = {"description": desc}
+        for name, L in variants.items():
+            s_ = stages(L, Ac, ops.Config(hash_all_rows=1))
+            r[f"hash_{name}"] = {"symbolic_ms": round(s_[1], 4), "numeric_ms": round(s_[3], 4),
+                                 "total_ms": round(s_[4], 4)}
+            log(f"{w} hashing {name}: sym {s_[1]:.3f} num {s_[3]:.3f} total {s_[4]:.3f} ms")
+        r["sym_ratio"] = {}
+        for q in (1.0, 1.2, 1.5):
+            s_ = stages(variants["single"], Ac, ops.Config(hash_all_rows=1, sym_ratio=q))
+            r["sym_ratio"][str(q)] = round(s_[1], 4)
+        r["num_ratio"] = {}
+        for q in (1.0, 1.5, 2.0, 3.0):
+            s_ = stages(variants["single"], Ac, ops.Config(hash_all_rows=1, num_ratio=q))
+            r["num_ratio"][str(q)] = round(s_[3], 4)
+        log(f"{w} ranges: sym {r['sym_ratio']} num {r['num_ratio']}")
+        for tag, cfg in (("paper_hashing", ops.Config(hash_all_rows=1)), ("default", ops.Config())):
+            s_ = stages(variants["single"], Ac, cfg)
+            setup = s_[6]
+            binning = (s_[0] - s_[6]) + s_[2]
+            r[f"binning_{tag}"] = {"setup_ms": round(setup, 4), "binning_ms": round(binning, 4),
+                                   "total_ms": round(s_[4], 4),
+                                   "binning_share": round(binning / s_[4], 4),
+                                   "setup_and_binning_share": round((setup + binning) / s_[4], 4)}
+        res[w] = r
+        del dA, Ac, A
+        torch.cuda.synchronize()
+        ops.cache_release()
+        torch.cuda.empty_cache()
+
+    out = {"mode": "ablation", "steps": args.steps, "warmup": args.warmup, "workloads": res}
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(ablation_markdown(res))
+
+
+def ablation_markdown(res) -> str:
+    """The three ablation tables of bench_ablation as markdown."""
+    L = ["### Hashing: single- vs multiple-access probe (Section 6.3.2; every row hashed)", "",
+         "| workload | symbolic single ms | symbolic multi ms | speedup | numeric single ms | "
+         "numeric multi ms | speedup |", "|---|---|---|---|---|---|---|"]
+    for w, r in res.items():
+        a, b = r["hash_single"], r["hash_multi"]
+        L.append(f"| {w} | {a['symbolic_ms']:.3f} | {b['symbolic_ms']:.3f} | "
+                 f"{b['symbolic_ms'] / a['symbolic_ms']:.3f} | {a['numeric_ms']:.3f} | "
+                 f"{b['numeric_ms']:.3f} | {b['numeric_ms'] / a['numeric_ms']:.3f} |")
+    L += ["", "### Binning ranges (Section 6.3.3; every row hashed): step time and speedup over ratio 1",
+          "", "| workload | Sym_1x ms | Sym_1.2x | Sym_1.5x | Num_1x ms | Num_1.5x | Num_2x | Num_3x |",
+          "|---|---|---|---|---|---|---|---|"]
+    for w, r in res.items():
+        sr, nr = r["sym_ratio"], r["num_ratio"]
+        s1, n1 = sr["1.0"], nr["1.0"]
+        L.append(f"| {w} | {s1:.3f} | {sr['1.2']:.3f} ({s1 / sr['1.2']:.2f}x) | "
+                 f"{sr['1.5']:.3f} ({s1 / sr['1.5']:.2f}x) | {n1:.3f} | "
+                 f"{nr['1.5']:.3f} ({n1 / nr['1.5']:.2f}x) | {nr['2.0']:.3f} ({n1 / nr['2.0']:.2f}x) | "
+                 f"{nr['3.0']:.3f} ({n1 / nr['3.0']:.2f}x) |")
+    L += ["", "### Binning share of the whole product (Section 6.3.1)", "",
+          "| workload | configuration | setup kernel ms | binning kernels ms | total ms | "
+          "binning share | setup + binning share |", "|---|---|---|---|---|---|---|"]
+    for w, r in res.items():
+        for tag in ("paper_hashing", "default"):
+            b = r[f"binning_{tag}"]
+            L.append(f"| {w} | {tag.replace('_', ' ')} | {b['setup_ms']:.3f} | {b['binning_ms']:.3f} | "
+                     f"{b['total_ms']:.3f} | {100 * b['binning_share']:.2f} % | "
+                     f"{100 * b['setup_and_binning_share']:.2f} % |")
+    return "\n".join(L) + "\n"
 
 
 def bench_copy(args, dev):

@@ -64,9 +64,9 @@ typedef struct {
 
 /* Optional tuning / test controls.  Pass NULL for the defaults.
  * Set `version` to OPSP_CONFIG_VERSION; zero-initialised fields take their
- * defaults.  Version 1 structs (without the explicit bin bounds) are still
- * accepted. */
-#define OPSP_CONFIG_VERSION 2
+ * defaults.  Version 1 and 2 structs (without the explicit bin bounds, or
+ * without the stream count) are still accepted. */
+#define OPSP_CONFIG_VERSION 3
 typedef struct {
     int32_t version;
     /* Binning ratio (Section 5.7): a row goes to the first table whose size is
@@ -110,6 +110,14 @@ typedef struct {
      * bitmap of that range (symbolic) and accumulated in a dense array of it
      * (numeric), which gives the same result without probing. */
     int32_t hash_all_rows;
+    /* Version >= 3: streams that the bin kernels of each step are spread
+     * over (Section 5, computation flow: bins run concurrently, the longest
+     * rows' kernels launched first): the calling stream takes the longest-row
+     * bins, up to three library-owned side streams of default priority take
+     * the others, and the calling stream waits for them before the step's
+     * result is used.  0 = the library default (1: the calling stream
+     * only), at most 4. */
+    int32_t streams;
 } opsp_config;
 
 /* Counters of one call (filled when a stats pointer is given). */
@@ -123,7 +131,9 @@ typedef struct {
     /* Stage times in ms when config.stage_timing != 0:
      * two-phase calls: 0 setup+binning, 1 symbolic, 2 numeric
      *   binning+scan+allocation, 3 numeric, 4 total, 5 the numeric
-     *   kernel of the longest rows (bin 7) alone (0 when it did not run);
+     *   kernel of the longest rows (bin 7) alone (0 when it did not run),
+     *   6 the setup kernels alone (within 0; the first binning pass is
+     *   fused into the setup kernel);
      * opsp_spgemm_learned: 0 setup+capacities+binning+slot scan,
      *   1 one-phase numeric, 2 recompute+row-pointer scan+allocation of C,
      *   3 copy into C, 4 total */
@@ -154,9 +164,12 @@ const char *opsp_status_string(opsp_status s);
  *            device-memory cache and owned by the caller afterwards
  *            (release with opsp_csr_free).  nnz(C) == 0 gives col = val =
  *            NULL and a valid rpt of zeros.
- *   stream : hipStream_t or NULL.  The host blocks twice (to read the
- *            symbolic bin sizes and nnz(C)); C is complete once the stream
- *            reaches the point of return. */
+ *   stream : hipStream_t or NULL.  The host blocks once, to read nnz(C)
+ *            and the numeric bin sizes (the symbolic bin kernels take their
+ *            row counts from device memory); with config.hash_all_rows or
+ *            B.cols above 2^23 it blocks once more, to size the global hash
+ *            tables.  C is complete once the stream reaches the point of
+ *            return. */
 opsp_status opsp_spgemm(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, void *stream);
 
 /* As opsp_spgemm, with tuning/test controls and counters (either may be

@@ -33,7 +33,7 @@ _HEADER = os.path.join(os.path.dirname(_HERE), "include", "opsp.h")
 
 SYM_BINS = 9
 NUM_BINS = 8
-CONFIG_VERSION = 2
+CONFIG_VERSION = 3
 MLP_NPARAM = 4481
 PREDICTOR_VERSION = 1
 PRED_MLP, PRED_UPPER, PRED_RATIO = 0, 1, 2
@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
                 ("sym_abort_fraction", c_double), ("b_lanes", c_int32),
                 ("stage_timing", c_int32), ("validate", c_int32), ("fixed_grid", c_int32),
                 ("sym_bounds", c_int64 * 7), ("num_bounds", c_int64 * 7),
-                ("hash_all_rows", c_int32)]
+                ("hash_all_rows", c_int32), ("streams", c_int32)]
 
     def __init__(self, **kw):
         super().__init__()
@@ -71,7 +71,7 @@ class Config(ctypes.Structure):
         return {"sym_ratio": self.sym_ratio, "num_ratio": self.num_ratio,
                 "sym_abort_fraction": self.sym_abort_fraction,
                 "sym_bounds": list(self.sym_bounds), "num_bounds": list(self.num_bounds),
-                "hash_all_rows": self.hash_all_rows}
+                "hash_all_rows": self.hash_all_rows, "streams": self.streams}
 
 
 class Stats(ctypes.Structure):
@@ -115,6 +115,22 @@ def library_path() -> str:
     return _LIB_PATH
 
 
+_variants = {}
+
+
+def lib_variant(name: str):
+    """A build variant of the library (``_build.VARIANTS``), loaded beside the
+    product library with the same C ABI: ``"multi_access"`` is the
+    read-then-swap hash probe of the hashing ablation (Section 6.3.2)."""
+    if name not in _variants:
+        from . import _build
+        path = _build.VARIANTS[name][1]
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2206_07244_amd._build`")
+        _variants[name] = _bind(ctypes.CDLL(path))
+    return _variants[name]
+
+
 def lib():
     """The loaded ``libopsp.so`` (raises if it has not been built)."""
     global _lib
@@ -123,65 +139,69 @@ def lib():
             raise RuntimeError(
                 f"{_LIB_PATH} is missing: build it with `python -m paper_2206_07244_amd._build` "
                 "(there is no CPU fallback)")
-        L = ctypes.CDLL(_LIB_PATH)
-        P = c_void_p
-        csr_p = POINTER(opsp_csr)
-        L.opsp_version.restype = c_char_p
-        L.opsp_version.argtypes = []
-        L.opsp_status_string.restype = c_char_p
-        L.opsp_status_string.argtypes = [ctypes.c_int]
-        L.opsp_spgemm.restype = ctypes.c_int
-        L.opsp_spgemm.argtypes = [csr_p, csr_p, csr_p, P]
-        L.opsp_spgemm_ex.restype = ctypes.c_int
-        L.opsp_spgemm_ex.argtypes = [csr_p, csr_p, csr_p, POINTER(Config), POINTER(Stats), P]
-        L.opsp_spgemm_symbolic.restype = ctypes.c_int
-        L.opsp_spgemm_symbolic.argtypes = [csr_p, csr_p, POINTER(Config), POINTER(c_void_p),
-                                           POINTER(c_int64), P]
-        L.opsp_spgemm_numeric.restype = ctypes.c_int
-        L.opsp_spgemm_numeric.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
-        L.opsp_spgemm_numeric_noalloc.restype = ctypes.c_int
-        L.opsp_spgemm_numeric_noalloc.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
-        L.opsp_plan_destroy.restype = None
-        L.opsp_plan_destroy.argtypes = [c_void_p]
-        L.opsp_csr_free.restype = ctypes.c_int
-        L.opsp_csr_free.argtypes = [csr_p, P]
-        L.opsp_batch_create.restype = ctypes.c_int
-        L.opsp_batch_create.argtypes = [c_int32, csr_p, csr_p, POINTER(Config), POINTER(c_void_p), P]
-        L.opsp_batch_execute.restype = ctypes.c_int
-        L.opsp_batch_execute.argtypes = [c_void_p, csr_p, POINTER(Stats), P]
-        L.opsp_batch_destroy.restype = None
-        L.opsp_batch_destroy.argtypes = [c_void_p]
-        L.opsp_spgemm_batched.restype = ctypes.c_int
-        L.opsp_spgemm_batched.argtypes = [c_int32, csr_p, csr_p, csr_p, POINTER(Config),
-                                          POINTER(c_void_p), P]
-        L.opsp_cache_release.restype = ctypes.c_int
-        L.opsp_cache_release.argtypes = []
-        L.opsp_cache_bytes.restype = c_int64
-        L.opsp_cache_bytes.argtypes = []
-        L.opsp_cache_live_bytes.restype = c_int64
-        L.opsp_cache_live_bytes.argtypes = []
-        L.opsp_debug_fail_alloc.restype = None
-        L.opsp_debug_fail_alloc.argtypes = [c_int64]
-        L.opsp_table_sizes.restype = ctypes.c_int
-        L.opsp_table_sizes.argtypes = [c_int32, POINTER(c_int64), c_int32]
-        L.opsp_bin_bounds.restype = ctypes.c_int
-        L.opsp_bin_bounds.argtypes = [c_int32, POINTER(c_int64), c_int32, c_double, POINTER(c_int64)]
-        L.opsp_row_features.restype = ctypes.c_int
-        L.opsp_row_features.argtypes = [csr_p, csr_p, P, P, P, P]
-        L.opsp_mlp_features.restype = ctypes.c_int
-        L.opsp_mlp_features.argtypes = [csr_p, csr_p, P, P]
-        L.opsp_mlp_forward.restype = ctypes.c_int
-        L.opsp_mlp_forward.argtypes = [P, P, c_int64, P, P]
-        L.opsp_mlp_grad.restype = ctypes.c_int
-        L.opsp_mlp_grad.argtypes = [P, P, P, c_int64, ctypes.c_float, P, P, P]
-        L.opsp_mlp_adam.restype = ctypes.c_int
-        L.opsp_mlp_adam.argtypes = [P, P, P, P, c_int64, ctypes.c_float, ctypes.c_float,
-                                    ctypes.c_float, ctypes.c_float, P, P]
-        L.opsp_spgemm_learned.restype = ctypes.c_int
-        L.opsp_spgemm_learned.argtypes = [csr_p, csr_p, csr_p, POINTER(opsp_predictor),
-                                          POINTER(Config), POINTER(Stats), P]
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def _bind(L):
+    """Argument and result types of every exported function."""
+    P = c_void_p
+    csr_p = POINTER(opsp_csr)
+    L.opsp_version.restype = c_char_p
+    L.opsp_version.argtypes = []
+    L.opsp_status_string.restype = c_char_p
+    L.opsp_status_string.argtypes = [ctypes.c_int]
+    L.opsp_spgemm.restype = ctypes.c_int
+    L.opsp_spgemm.argtypes = [csr_p, csr_p, csr_p, P]
+    L.opsp_spgemm_ex.restype = ctypes.c_int
+    L.opsp_spgemm_ex.argtypes = [csr_p, csr_p, csr_p, POINTER(Config), POINTER(Stats), P]
+    L.opsp_spgemm_symbolic.restype = ctypes.c_int
+    L.opsp_spgemm_symbolic.argtypes = [csr_p, csr_p, POINTER(Config), POINTER(c_void_p),
+                                       POINTER(c_int64), P]
+    L.opsp_spgemm_numeric.restype = ctypes.c_int
+    L.opsp_spgemm_numeric.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
+    L.opsp_spgemm_numeric_noalloc.restype = ctypes.c_int
+    L.opsp_spgemm_numeric_noalloc.argtypes = [c_void_p, csr_p, csr_p, csr_p, P]
+    L.opsp_plan_destroy.restype = None
+    L.opsp_plan_destroy.argtypes = [c_void_p]
+    L.opsp_csr_free.restype = ctypes.c_int
+    L.opsp_csr_free.argtypes = [csr_p, P]
+    L.opsp_batch_create.restype = ctypes.c_int
+    L.opsp_batch_create.argtypes = [c_int32, csr_p, csr_p, POINTER(Config), POINTER(c_void_p), P]
+    L.opsp_batch_execute.restype = ctypes.c_int
+    L.opsp_batch_execute.argtypes = [c_void_p, csr_p, POINTER(Stats), P]
+    L.opsp_batch_destroy.restype = None
+    L.opsp_batch_destroy.argtypes = [c_void_p]
+    L.opsp_spgemm_batched.restype = ctypes.c_int
+    L.opsp_spgemm_batched.argtypes = [c_int32, csr_p, csr_p, csr_p, POINTER(Config),
+                                      POINTER(c_void_p), P]
+    L.opsp_cache_release.restype = ctypes.c_int
+    L.opsp_cache_release.argtypes = []
+    L.opsp_cache_bytes.restype = c_int64
+    L.opsp_cache_bytes.argtypes = []
+    L.opsp_cache_live_bytes.restype = c_int64
+    L.opsp_cache_live_bytes.argtypes = []
+    L.opsp_debug_fail_alloc.restype = None
+    L.opsp_debug_fail_alloc.argtypes = [c_int64]
+    L.opsp_table_sizes.restype = ctypes.c_int
+    L.opsp_table_sizes.argtypes = [c_int32, POINTER(c_int64), c_int32]
+    L.opsp_bin_bounds.restype = ctypes.c_int
+    L.opsp_bin_bounds.argtypes = [c_int32, POINTER(c_int64), c_int32, c_double, POINTER(c_int64)]
+    L.opsp_row_features.restype = ctypes.c_int
+    L.opsp_row_features.argtypes = [csr_p, csr_p, P, P, P, P]
+    L.opsp_mlp_features.restype = ctypes.c_int
+    L.opsp_mlp_features.argtypes = [csr_p, csr_p, P, P]
+    L.opsp_mlp_forward.restype = ctypes.c_int
+    L.opsp_mlp_forward.argtypes = [P, P, c_int64, P, P]
+    L.opsp_mlp_grad.restype = ctypes.c_int
+    L.opsp_mlp_grad.argtypes = [P, P, P, c_int64, ctypes.c_float, P, P, P]
+    L.opsp_mlp_adam.restype = ctypes.c_int
+    L.opsp_mlp_adam.argtypes = [P, P, P, P, c_int64, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, P, P]
+    L.opsp_spgemm_learned.restype = ctypes.c_int
+    L.opsp_spgemm_learned.argtypes = [csr_p, csr_p, csr_p, POINTER(opsp_predictor),
+                                      POINTER(Config), POINTER(Stats), P]
+    return L
 
 
 def exported_symbols() -> list:

@@ -35,9 +35,22 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+# Library variants: name -> (extra compile flags, library file).  The default
+# is the product; "multi_access" swaps the single compare-and-swap hash probe
+# for the read-then-swap probe of the paper's hashing ablation (Section 6.3.2).
+VARIANTS = {
+    "": ([], LIB),
+    "multi_access": (["-DOPSP_HASH_MULTI_ACCESS=1"],
+                     os.path.join(HERE, "libopsp_multi_access.so")),
+}
+
+
+def _compile(src: str, variant: str = "") -> str:
+    flags, _ = VARIANTS[variant]
+    odir = OBJ if not variant else os.path.join(OBJ, variant)
+    os.makedirs(odir, exist_ok=True)
+    obj = os.path.join(odir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -48,19 +61,22 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, variants=("", "multi_access")) -> str:
+    """Compile and link every library variant; returns the product library."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    if verbose:
-        print("built", LIB)
+    for variant in variants:
+        lib = VARIANTS[variant][1]
+        with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+            objs = list(ex.map(lambda f: _compile(f, variant), srcs))
+        tmp = lib + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
+        if verbose:
+            print("built", lib)
     return LIB
 
 

@@ -337,10 +337,15 @@ template <bool SCAN>
 __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds bd,
                                                  const Counters *__restrict__ ctr,
                                                  int32_t *__restrict__ bins, BlockParts parts,
-                                                 int64_t *vout) {
+                                                 int64_t *vout, int skip_full) {
     __shared__ unsigned int wcnt[4][BIN_SLOTS];
     __shared__ unsigned long long base[BIN_SLOTS];
     __shared__ unsigned long long wsum[4];
+    if (!SCAN && skip_full) {
+        // one bin holds every row: its rows are read in order, no list
+        for (int j = 0; j < bd.nslots; ++j)
+            if ((int64_t)ctr->size[j] == M) return;   // uniform over the grid
+    }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = i < M;
@@ -431,16 +436,16 @@ hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Count
 
 hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
                           int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
-                          int64_t *vout) {
+                          int64_t *vout, bool device_identity) {
     if (M == 0) return hipSuccess;
     const int64_t grid = (M + 255) / 256;
     if (!vout) vout = v;
     if (scan)
         hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, parts, vout);
+                           bins, parts, vout, 0);
     else
         hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, parts, vout);
+                           bins, parts, vout, device_identity ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ __device__ __forceinline__ bool num_insert_lds(int *keys, double *vals, uint32_t
                                                double v) {
     uint32_t s = hslot(key, T);
     for (uint32_t n = 0; n < T; ++n) {
-        const int old = atomicCAS(&keys[s], -1, key);
+        const int old = hash_claim(&keys[s], key);
         if (old == -1 || old == key) {
             atomicAdd(&vals[s], v);
             return true;
@@ -55,7 +55,7 @@ __device__ __forceinline__ int num_insert_wave(KeyT *keys, ValT *vals, uint32_t 
             break;
         }
         if (pend) {
-            const int old = atomicCAS(&keys[s], -1, key);
+            const int old = hash_claim(&keys[s], key);
             const bool hit = (old == -1) | (old == key);
             if (hit) add(&vals[s], v);
             isnew = old == -1;

@@ -27,7 +27,7 @@ namespace opsp {
 __device__ __forceinline__ int sym_insert_lds(int *tab, uint32_t T, int key) {
     uint32_t s = hslot(key, T);
     for (uint32_t n = 0; n < T; ++n) {
-        const int old = atomicCAS(&tab[s], -1, key);
+        const int old = hash_claim(&tab[s], key);
         if (old == -1) return 1;
         if (old == key) return 0;
         s = next_slot(s, T);

@@ -166,23 +166,6 @@ void bfree_all(opsp_batch *b, hipStream_t s) {
     b->owned.clear();
 }
 
-// Workgroups per CU of each symbolic kernel's grid: full residency, except
-// bin 0, whose short rows are better balanced by the hardware refilling CUs
-// with new workgroups than by each resident workgroup striding over a fixed
-// share (8x residency: the 512-pair batch 38.4 -> 36.5 ms); workgroups that
-// find no row left exit at once.
-int sym_wg_per_cu(int bin) {
-    switch (bin) {
-        case 0: return 64;           // 256-lane workgroups, 8 resident
-        case 1: return 8;
-        case 2: return 16;           // 128 lanes
-        case 3: return 8;
-        case 4: return 4;
-        case 5: case 6: return 2;
-        default: return 1;           // bin 7: 160 KB of LDS
-    }
-}
-
 opsp_status capture_g1(opsp_batch *b, hipStream_t s) {
     const DevCSR A{b->M, b->K, b->arpt, b->acol, b->aval};
     const DevCSR B{b->K, b->Nmax, b->brpt, b->bcol, b->bval};
@@ -210,7 +193,7 @@ opsp_status capture_g1(opsp_batch *b, hipStream_t s) {
             sa.src.dctr = &b->ctr[0];
             sa.src.bin = bin;
             int64_t g = (int64_t)b->cus * sym_wg_per_cu(bin);
-            const int64_t R = bin == 0 ? 32 : (bin == 1 ? 4 : 1);
+            const int64_t R = sym_rows_per_wg(bin);
             const int64_t need = (b->M + R - 1) / R;
             sa.grid = g < need ? g : need;
             if (sa.grid < 1) sa.grid = 1;

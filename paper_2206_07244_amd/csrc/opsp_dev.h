@@ -101,12 +101,20 @@ struct RowSrc {
     const Counters *dctr;
     const unsigned int *count;
     int bin;
+    // with dctr: the number of rows of the whole matrix (0 = unknown); a bin
+    // that holds all of them is read in row order without the list (the
+    // all-rows-in-one-bin case of Section 5.1, decided on the device)
+    int64_t all;
     __device__ __forceinline__ void resolve() {
         if (dctr) {
             nrows = (int64_t)dctr->size[bin];
             int64_t o = 0;
             for (int j = 0; j < bin; ++j) o += (int64_t)dctr->size[j];
             off = o;
+            if (all > 0 && nrows == all) {
+                bins = nullptr;
+                off = 0;
+            }
         }
         if (count) nrows = (int64_t)*count;
     }
@@ -246,6 +254,27 @@ __device__ __forceinline__ int64_t bpermute64(int64_t v, int src_lane) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// Claim of hash slot *p for `key`; returns the slot's previous content: -1
+// = the key was inserted here, `key` = it was already here, anything else =
+// the slot holds another key (probe on).  The single-access form of Alg. 4
+// and 5 is one compare-and-swap per probe, its returned value reused
+// (Section 5.2).  Built with OPSP_HASH_MULTI_ACCESS=1 the slot is read first
+// and swapped only when it reads empty: the multiple-access form that the
+// paper's ablation compares with (Section 6.3.2); same result.  A slot
+// changes once, from -1 to its key, so a stale read is harmless.
+#ifndef OPSP_HASH_MULTI_ACCESS
+#define OPSP_HASH_MULTI_ACCESS 0
+#endif
+template <class P>
+__device__ __forceinline__ int hash_claim(P *p, int key) {
+#if OPSP_HASH_MULTI_ACCESS
+    const int cur = (int)*(volatile P *)p;
+    if (cur == key) return key;
+    if (cur != -1) return cur;
+#endif
+    return (int)atomicCAS(p, (P)-1, (P)key);
+}
+
 // Symbolic hashing: insert one key per lane (lanes with ok == false take part without a key).
 // The probe loop is uniform over the wave and bounded by T iterations with a
 // scalar counter; every probe is a single compare-and-swap (Alg. 4).
@@ -262,7 +291,7 @@ __device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, in
             break;
         }
         if (pend) {
-            const int old = atomicCAS(&tab[s], -1, key);
+            const int old = hash_claim(&tab[s], key);
             const bool hit = (old == -1) | (old == key);
             isnew = old == -1;
             pend = !hit;

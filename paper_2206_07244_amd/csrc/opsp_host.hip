@@ -4,13 +4,14 @@
 //   1 setup      C.rpt allocated; n_prod per row written into it, fused with
 //                the first symbolic binning pass (Alg. 1); workspace
 //                allocation is stream-ordered and overlaps the kernel.
-//   2 sym. bins  one read-back of the 9 bin sizes (+ total, max) sizes the
-//                launches; second pass (Alg. 2) or the all-in-one-bin
-//                shortcut (Alg. 3: rows are their own ids, no list written).
-//   3 symbolic   per-bin kernels, biggest bins first (Section 5.5); bin 7
-//                aborts rows into the global-table kernel.
+//   2 sym. bins  second pass (Alg. 2), or the all-in-one-bin shortcut
+//                (Alg. 3: rows are their own ids, no list written), decided
+//                on the device from the bin sizes.
+//   3 symbolic   per-bin kernels, biggest bins first (Section 5.5), launched
+//                persistently with their row counts read on the device; bin
+//                7 aborts rows into the global-table kernel.
 //   4 num. bins  first pass over nnz with the nnz(C) total (Section 5.4);
-//                one read-back of nnz(C).
+//                the one read-back of the product (nnz(C), bin sizes).
 //   5 alloc+scan C.col/C.val come from the stream-ordered pool while the
 //                scan + second pass run (Section 5.4); C.rpt is scanned in
 //                place (Section 5.3).
@@ -42,6 +43,7 @@ struct opsp_plan {
     int identity_bin = -1;              // bin holding all rows when bins == NULL
     bool check = false;
     int64_t fixed_grid = 0;             // > 0: every bin kernel runs persistently with this grid
+    int streams = 1;                    // streams the numeric bin kernels are spread over
     Counters *ctr = nullptr;            // device counters (numeric step), owned
     int2 *range = nullptr;              // output column range (lo, hi) per row (owned)
     opsp_stats stats = {};
@@ -94,9 +96,39 @@ namespace {
 struct DeviceInfo {
     bool ready = false;
     int cus = 256;
+    hipStream_t side[MAX_STREAMS - 1] = {};   // library-owned, default priority
+    int nside = 0;
 };
 std::mutex g_mu;
 DeviceInfo g_dev[64];
+
+// Per-thread events that fork the bin kernels of a step onto the side
+// streams and join them back (created once per device and thread).
+struct ForkEvents {
+    int dev = -1;
+    hipEvent_t ev[MAX_STREAMS] = {};
+    bool ok = false;
+    bool get(int d) {
+        if (dev == d) return ok;
+        release();
+        dev = d;
+        ok = true;
+        for (int i = 0; i < MAX_STREAMS; ++i)
+            if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+                ev[i] = nullptr;
+                ok = false;
+            }
+        return ok;
+    }
+    void release() {
+        for (int i = 0; i < MAX_STREAMS; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        for (auto &e : ev) e = nullptr;
+        dev = -1;
+    }
+    ~ForkEvents() { release(); }
+};
+thread_local ForkEvents t_fork;
 
 // Per-thread pinned host buffer for the small counter read-backs.
 struct PinnedBuf {
@@ -136,11 +168,56 @@ opsp_status init_device(int *dev_out, int *cus_out) {
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return status_of(e);
         g_dev[dev].cus = cus > 0 ? cus : 256;
+        // side streams for concurrent bin kernels; without them every bin
+        // runs on the calling stream
+        g_dev[dev].nside = 0;
+        for (int i = 0; i < MAX_STREAMS - 1; ++i) {
+            if (hipStreamCreateWithFlags(&g_dev[dev].side[i], hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                break;
+            }
+            ++g_dev[dev].nside;
+        }
         g_dev[dev].ready = true;
     }
     *dev_out = dev;
     *cus_out = g_dev[dev].cus;
     return OPSP_OK;
+}
+
+int streams_of(const opsp_config *c) {
+    const int want = (c && c->version >= 3 && c->streams > 0) ? c->streams : DEFAULT_STREAMS;
+    return want < MAX_STREAMS ? want : MAX_STREAMS;
+}
+
+Fork::Fork(hipStream_t main, int want) : s{main}, n(1) {
+    int dev = 0;
+    if (want <= 1 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        const int avail = g_dev[dev].nside + 1;
+        n = want < avail ? want : avail;
+        for (int i = 1; i < n; ++i) s[i] = g_dev[dev].side[i - 1];
+    }
+    if (n > 1 && !t_fork.get(dev)) n = 1;
+    ev = t_fork.ev;
+}
+
+hipError_t Fork::begin() {
+    if (n <= 1) return hipSuccess;
+    hipError_t e = hipEventRecord(ev[0], s[0]);
+    for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(s[i], ev[0], 0);
+    return e;
+}
+
+hipError_t Fork::end() {
+    if (n <= 1) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int i = 1; i < n && e == hipSuccess; ++i) {
+        e = hipEventRecord(ev[i], s[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s[0], ev[i], 0);
+    }
+    return e;
 }
 
 bool csr_ok(const opsp_csr *X) {
@@ -204,7 +281,8 @@ Bounds config_bounds(int step, const opsp_config *c) {
 
 opsp_status check_config(const opsp_config *c) {
     if (!c) return OPSP_OK;
-    if (c->version != 1 && c->version != 2) return OPSP_ERR_INVALID;
+    if (c->version < 1 || c->version > 3) return OPSP_ERR_INVALID;
+    if (c->version >= 3 && (c->streams < 0 || c->streams > MAX_STREAMS)) return OPSP_ERR_INVALID;
     if (c->sym_ratio != 0 && !(c->sym_ratio >= 1.0)) return OPSP_ERR_INVALID;
     if (c->num_ratio != 0 && !(c->num_ratio >= 1.0)) return OPSP_ERR_INVALID;
     if (c->force_sym_bin < -1 || c->force_sym_bin > SYM_GLOBAL_BIN) return OPSP_ERR_INVALID;
@@ -285,6 +363,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     plan->N = N;
     plan->check = cfg && cfg->validate;
     plan->fixed_grid = cfg ? cfg->fixed_grid : 0;
+    plan->streams = streams_of(cfg);
     if (plan->check) {
         const opsp_csr *X[2] = {A, B};
         opsp_status vs = validate_csr(X, 2, s);
@@ -333,25 +412,20 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     tm.mark();
     if (bfl) CHK(launch_brange(dB, bfl, s));
     CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s, bfl, rng));
+    tm.mark();   // setup (with the first binning pass fused in) done
     CHK(launch_finalize(M, bs.nslots, parts, ctrS, nullptr, false, s));
-    Counters hS;
-    CHK(read_counters(&hS, ctrS, 1, s));
-    plan->stats.nprod = (int64_t)hS.total;
-    plan->stats.max_row_nprod = (int64_t)hS.maxv;
 
-    // 2 second pass (or identity rows when one bin holds everything)
-    int64_t ssz[16] = {}, soff[16] = {};
-    int sym_identity = -1;
-    for (int j = 0; j < bs.nslots; ++j) {
-        ssz[j] = (int64_t)hS.size[j];
-        if (ssz[j] == M) sym_identity = j;
-        plan->stats.sym_bin_rows[j < OPSP_SYM_BINS ? j : OPSP_SYM_BINS - 1] = ssz[j];
-    }
-    for (int j = 1; j < bs.nslots; ++j) soff[j] = soff[j - 1] + ssz[j - 1];
-    if (sym_identity < 0) CHK(launch_scatter(M, crpt, bs, ctrS, bins, parts, false, s));
+    // 2 second pass; the all-rows-in-one-bin case (Alg. 3) is decided on the
+    //   device: no list is written and the bin kernel reads rows in order
+    CHK(launch_scatter(M, crpt, bs, ctrS, bins, parts, false, s, nullptr, true));
     tm.mark();
 
-    // 3 symbolic, biggest bins first
+    // 3 symbolic, biggest bins first.  The bin sizes stay on the device:
+    //   every bin kernel is launched persistently and reads its row count
+    //   from the counters, so the host does not wait here (Section 5.5: no
+    //   synchronisation until every kernel is launched).  Only global hash
+    //   tables (matrices without a usable column range) are sized from the
+    //   largest n_prod, which takes one read-back.
     SymArgs sa;
     memset(&sa, 0, sizeof(sa));
     sa.A = dA;
@@ -359,28 +433,44 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.nnz = crpt;
     sa.ctr = ctrS;
     sa.rng = rng;
-    int32_t *fail_list = nullptr;
-    const int64_t big = ssz[7] + ssz[SYM_GLOBAL_BIN];
+    const bool need_slab = !rng || N > ((int64_t)SW_MAXPASS << SW_LG);
     int *slab = nullptr;
-    int64_t slab_entries = 0, sgrid = 0;
-    if (big > 0) {
-        if (ssz[7] > 0) {
-            CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)ssz[7]));
-            fail_list = (int32_t *)p;
-        }
-        // global hash tables only where a row's range can exceed the
-        // bitmap windows (every row's range lies within [0, N))
-        if (!rng || N > ((int64_t)SW_MAXPASS << SW_LG)) {
-            const int64_t bound = (int64_t)hS.maxv < N ? (int64_t)hS.maxv : N;
-            slab_entries = pow2_host(2 * bound > 64 ? 2 * bound : 64);
-        }
-        sgrid = big < (int64_t)cus * SYM_GLOBAL_WG_PER_CU ? big : (int64_t)cus * SYM_GLOBAL_WG_PER_CU;
+    int64_t slab_entries = 0;
+    const int64_t sgrid = M < (int64_t)cus * SYM_GLOBAL_WG_PER_CU ? M : (int64_t)cus * SYM_GLOBAL_WG_PER_CU;
+    if (need_slab) {
+        Counters hS;
+        CHK(read_counters(&hS, ctrS, 1, s));
+        const int64_t bound = (int64_t)hS.maxv < N ? (int64_t)hS.maxv : N;
+        slab_entries = pow2_host(2 * bound > 64 ? 2 * bound : 64);
     }
+    int32_t *fail_list = nullptr;
+    CHK(ar.alloc(&p, sizeof(int32_t) * (size_t)M));   // rows abandoned by bin 7 (at most all)
+    fail_list = (int32_t *)p;
+    auto grid_of = [&](int b) -> int64_t {
+        if (plan->fixed_grid > 0) return plan->fixed_grid;
+        const int64_t R = sym_rows_per_wg(b);
+        const int64_t need = (M + R - 1) / R;
+        const int64_t g = (int64_t)cus * sym_wg_per_cu(b);
+        return g < need ? g : need;
+    };
+    auto global_args = [&](const RowSrc &src) {
+        SymArgs g = sa;
+        g.src = src;
+        g.slab = slab;
+        g.slab_entries = slab_entries;
+        g.sched = ctrS->sched;
+        g.grid = sgrid;
+        return g;
+    };
+    Fork fk(s, plan->streams);
+    CHK(fk.begin());
     for (int b = 7; b >= 0; --b) {
-        if (ssz[b] == 0) continue;
-        sa.src = host_rows((sym_identity == b) ? nullptr : bins, (sym_identity == b) ? 0 : soff[b], ssz[b]);
-        sa.grid = 0;
-        if (plan->fixed_grid > 0) sa.grid = plan->fixed_grid < ssz[b] ? plan->fixed_grid : ssz[b];
+        memset(&sa.src, 0, sizeof(sa.src));
+        sa.src.bins = bins;
+        sa.src.dctr = ctrS;
+        sa.src.bin = b;
+        sa.src.all = M;
+        sa.grid = grid_of(b);
         if (b == 7) {
             const double frac = cfg && cfg->sym_abort_fraction != 0 ? cfg->sym_abort_fraction : 0.8;
             int64_t thr = frac < 0 ? -1 : (int64_t)(frac * SYM_T[7]);
@@ -389,45 +479,43 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
             sa.abort_thr = (int)thr;
             sa.fail_list = fail_list;
         }
-        CHK(launch_symbolic_bin(b, sa, s));
+        CHK(launch_symbolic_bin(b, sa, fk.on(b, 7)));
         if (b == 7) {
             // the global-table allocation overlaps the bin-7 kernel (Section 5.4)
             if (slab_entries > 0) {
                 CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
                 slab = (int *)p;
             }
-            SymArgs g = sa;
-            g.src = host_rows(fail_list, 0, ssz[7]);
-            g.src.count = &ctrS->fail;
-            g.slab = slab;
-            g.slab_entries = slab_entries;
-            g.sched = ctrS->sched;
-            g.grid = ssz[7] < sgrid ? ssz[7] : sgrid;
-            CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
+            RowSrc fr;
+            memset(&fr, 0, sizeof(fr));
+            fr.bins = fail_list;
+            fr.count = &ctrS->fail;
+            CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, global_args(fr), s));
         }
     }
-    if (ssz[SYM_GLOBAL_BIN] > 0) {
-        if (!slab && slab_entries > 0) {
-            CHK(ar.alloc(&p, sizeof(int) * (size_t)(slab_entries * sgrid)));
-            slab = (int *)p;
-        }
-        SymArgs g = sa;
-        g.src = host_rows((sym_identity == SYM_GLOBAL_BIN) ? nullptr : bins,
-                          (sym_identity == SYM_GLOBAL_BIN) ? 0 : soff[SYM_GLOBAL_BIN], ssz[SYM_GLOBAL_BIN]);
-        g.slab = slab;
-        g.slab_entries = slab_entries;
-        g.sched = ctrS->sched;
-        g.grid = g.src.nrows < sgrid ? g.src.nrows : sgrid;
-        CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, g, s));
+    if (bs.force == SYM_GLOBAL_BIN) {
+        // rows routed straight to the global tables
+        RowSrc gr;
+        memset(&gr, 0, sizeof(gr));
+        gr.bins = bins;
+        gr.dctr = ctrS;
+        gr.bin = SYM_GLOBAL_BIN;
+        gr.all = M;
+        CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, global_args(gr), s));
     }
+    CHK(fk.end());
     tm.mark();
 
     // 4 numeric binning, first pass with nnz(C)
     CHK(launch_hist(M, crpt, bn, parts, s));
     CHK(launch_finalize(M, bn.nslots, parts, ctrN, crpt + M, true, s));
     Counters hc[2];
-    CHK(read_counters(hc, ctrS, 2, s));
+    CHK(read_counters(hc, ctrS, 2, s));   // the one wait of the product
     const Counters &hN = hc[1];
+    plan->stats.nprod = (int64_t)hc[0].total;
+    plan->stats.max_row_nprod = (int64_t)hc[0].maxv;
+    for (int j = 0; j < bs.nslots; ++j)
+        plan->stats.sym_bin_rows[j < OPSP_SYM_BINS ? j : OPSP_SYM_BINS - 1] = (int64_t)hc[0].size[j];
     plan->nnzC = (int64_t)hN.total;
     plan->max_nnz = (int64_t)hN.maxv;
     plan->stats.nnz = plan->nnzC;
@@ -481,6 +569,8 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     const int gb = NUM_GLOBAL_BIN;
     bool first = true;
     void *pk = nullptr, *pv = nullptr;
+    Fork fk(s, scr ? 1 : plan->streams);
+    CHK(fk.begin());
     for (int b = gb; b >= 0; --b) {
         const int64_t rows = plan->num_size[b];
         if (rows == 0) continue;
@@ -535,11 +625,12 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
             na.grid = grid;
         }
         if (kt && b == gb) kt->mark();
-        CHK(launch_numeric_bin(b, na, s));
+        CHK(launch_numeric_bin(b, na, fk.on(b, gb)));
         if (kt && b == gb) kt->mark();
         first = false;
     }
     (void)first;
+    CHK(fk.end());
     return OPSP_OK;
 }
 
@@ -633,9 +724,13 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
         *stats = plan.stats;
         if (tm.on) {
             (void)hipStreamSynchronize(s);
-            for (int k = 0; k < 4; ++k) stats->ms_stage[k] = tm.between(k, k + 1);
-            stats->ms_stage[4] = tm.between(0, 4);
+            // marks: 0 start, 1 setup kernel, 2 symbolic binning, 3 symbolic,
+            // 4 numeric binning + scan + allocation, 5 numeric
+            stats->ms_stage[0] = tm.between(0, 2);
+            for (int k = 1; k < 4; ++k) stats->ms_stage[k] = tm.between(k + 1, k + 2);
+            stats->ms_stage[4] = tm.between(0, 5);
             stats->ms_stage[5] = kt.between(0, 1);
+            stats->ms_stage[6] = tm.between(0, 1);
         }
     }
     plan_release(&plan, s);

@@ -10,6 +10,32 @@ namespace opsp {
 namespace host {
 
 constexpr size_t PINNED_BYTES = 4096;   // per-thread pinned read-back buffer
+constexpr int MAX_STREAMS = 4;           // calling stream + library side streams
+// Bins on the calling stream only by default: spread over four streams the
+// bin kernels measured slower on one MI355X (R-MAT 2^20 squared 411 -> 416
+// ms, the 27-point stencil 3.98 -> 4.27 ms, the 64x64 Laplacian 0.11 -> 0.22
+// ms): the persistent long-row kernels fill every CU and the side-stream
+// kernels only delay their workgroups.
+constexpr int DEFAULT_STREAMS = 1;
+
+// The bin kernels of one step spread over the calling stream and up to
+// MAX_STREAMS - 1 side streams: begin() makes the side streams wait for the
+// work queued so far on the calling stream, end() makes the calling stream
+// wait for the side streams.  Bin b runs on on(b): the longest-row bin on the
+// calling stream, the others round-robin on the side streams.
+struct Fork {
+    hipStream_t s[MAX_STREAMS];
+    int n;
+    hipEvent_t *ev = nullptr;
+    Fork(hipStream_t main, int want);
+    hipError_t begin();
+    hipError_t end();
+    hipStream_t on(int bin, int longest) const {
+        return (n <= 1 || bin >= longest) ? s[0] : s[1 + (longest - 1 - bin) % (n - 1)];
+    }
+};
+// Streams a configuration asks for (1..MAX_STREAMS).
+int streams_of(const opsp_config *c);
 
 opsp_status status_of(hipError_t e);
 // Current device and its compute-unit count; first use per device raises the

@@ -59,10 +59,12 @@ hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Count
                            int64_t *total_out, bool scan, hipStream_t s);
 // Second binning pass: scatter row ids into `bins` (may be NULL when no
 // bins are needed); with `scan`, also write the exclusive offsets of v[] to
-// vout[] (NULL = in place).
+// vout[] (NULL = in place).  With `device_identity` (no scan), nothing is
+// written when one bin holds every row: readers given RowSrc::all take the
+// rows in order then.
 hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
                           int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
-                          int64_t *vout = nullptr);
+                          int64_t *vout = nullptr, bool device_identity = false);
 
 // ---- input check of the validation mode (kernels_check.hip) ----------------
 // Sets bits of *flags (zeroed before): 1 = rpt not monotone, rpt[0] < 0 or
@@ -89,6 +91,24 @@ struct SymArgs {
                                 // (null: rows assigned round-robin)
 };
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
+// Workgroups per CU of a symbolic bin kernel launched persistently (its rows
+// counted on the device): full residency, except bin 0, whose short rows are
+// better balanced by the hardware refilling CUs with new workgroups than by
+// each resident workgroup striding over a fixed share; workgroups that find
+// no row left exit at once.
+inline int sym_wg_per_cu(int bin) {
+    switch (bin) {
+        case 0: return 64;           // 256-lane workgroups, 8 resident
+        case 1: return 8;
+        case 2: return 16;           // 128 lanes
+        case 3: return 8;
+        case 4: return 4;
+        case 5: case 6: return 2;
+        default: return 1;           // bin 7: 160 KB of LDS
+    }
+}
+// Rows one workgroup of a symbolic bin kernel takes at a time.
+inline int sym_rows_per_wg(int bin) { return bin == 0 ? 256 / SYM_GL : (bin == 1 ? 4 : 1); }
 
 // ---- numeric step (kernels_num.hip) ----------------------------------------
 struct NumArgs {

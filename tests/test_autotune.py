@@ -73,7 +73,8 @@ def test_load_config_roundtrip(tmp_path):
     p = tmp_path / "t.json"
     p.write_text(json.dumps({"classes": {"rmat": {"config": dict(c), "ms": 1.0}}}))
     cfg = at.load_config("rmat", str(p))
-    assert cfg.version == 2 and cfg.sym_ratio == 1.5 and cfg.num_ratio == 3.0
+    from paper_2206_07244_amd import CONFIG_VERSION
+    assert cfg.version == CONFIG_VERSION and cfg.sym_ratio == 1.5 and cfg.num_ratio == 3.0
     assert list(cfg.num_bounds) == [10, 200, 0, 0, 0, 0, -1]
     assert at.load_config("stencil", str(p)) is None
     assert at.load_config("rmat", str(tmp_path / "missing.json")) is None

@@ -333,3 +333,41 @@ def test_one_wave_rows_around_64_outputs(hash_all):
     check(A, B, cfg=cfg, stats=st)
     assert st.num_bin_rows[1] == A.rows
     assert st.nnz == sum(counts)
+
+
+@pytest.mark.parametrize("hash_all", [1, 0])
+def test_multi_access_hash_variant(hash_all):
+    """The library built with the multiple-access hash probe (the hashing
+    ablation of Section 6.3.2) computes the same product."""
+    import ctypes
+    import torch
+    ops = _ops()
+    V = ops.lib_variant("multi_access")
+    for A in (syn.rmat(13, 16, seed=7), syn.stencil27(12, seed=3), syn.banded(5000, 64, 12, seed=4)):
+        dA = ops.DeviceCSR.from_host(A)
+        Ac = dA._c()
+        cfg = ops.Config(validate=1, hash_all_rows=hash_all)
+        Cc = ops.opsp_csr()
+        sh = torch.cuda.current_stream().cuda_stream
+        code = V.opsp_spgemm_ex(ctypes.byref(Ac), ctypes.byref(Ac), ctypes.byref(Cc), ctypes.byref(cfg),
+                                None, sh)
+        assert code == 0, code
+        rpt = ops._wrap(Cc.rpt, Cc.rows + 1, torch.int64, None, dA.rpt.device).cpu().numpy()
+        col = ops._wrap(Cc.col, Cc.nnz, torch.int32, None, dA.rpt.device).cpu().numpy()
+        val = ops._wrap(Cc.val, Cc.nnz, torch.float64, None, dA.rpt.device).cpu().numpy()
+        assert V.opsp_csr_free(ctypes.byref(Cc), sh) == 0
+        oracle.compare(rpt, col, val, oracle.spgemm(A, A), tol=TOL)
+
+
+
+@pytest.mark.parametrize("streams", [2, 4])
+def test_bins_on_several_streams(streams):
+    """Bin kernels spread over the calling stream and library side streams
+    give the same product (every symbolic and numeric bin populated)."""
+    st = _ops().Stats()
+    cfg = _ops().Config(validate=1, streams=streams)
+    check(syn.rmat(14, 16, seed=14), cfg=cfg, stats=st)
+    assert all(x > 0 for x in st.num_bin_rows), list(st.num_bin_rows)
+    for b in (0, 3, 7):
+        check(syn.rmat(12, 16, seed=b), cfg=_ops().Config(streams=streams, force_num_bin=b,
+                                                          force_sym_bin=b))
