@@ -835,14 +835,23 @@ __global__ __launch_bounds__(1024) void k_num_global(
 // workgroups share a CU, so that one's barriers and LDS round trips overlap
 // the other's work.
 // ---------------------------------------------------------------------------
-constexpr int BK_T = 512;           // threads per workgroup (two workgroups per CU)
+constexpr int BK_T = 512;           // threads per workgroup (two workgroups per CU: one's
+                                    // barriers and serial steps overlap the other's work)
 constexpr int BK_NW = BK_T / 64;    // waves per workgroup
 constexpr int BK_LG = 13;
-constexpr int BK_CW = 1 << BK_LG;   // columns per chunk
+constexpr int BK_CW = 1 << BK_LG;   // columns per chunk (a dense array of 64 KB)
 constexpr int BK_NB = 2048;         // chunks per row at most
 static_assert(BK_NB >= (int)(BUCKET_MAX_COLS >> BK_LG), "chunk counters");
 static_assert(BK_NB % BK_T == 0, "chunk scan");
+static_assert(BK_CW / 16 == BK_T, "one thread per 16 columns in the emission");
 constexpr int BK_U = 4;             // staged products in flight per thread
+constexpr int BK_ORD = 2048;        // ranks ordered per emission round
+
+// Position of chunk column o in the dense array: the low four bits are XORed
+// with the index of o's 16-column group, so that the threads of an emission
+// step, each reading the lowest remaining column of its own group, spread
+// over the LDS banks (randomly addressed accumulation does not care).
+__device__ __forceinline__ uint32_t bk_swz(uint32_t o) { return o ^ ((o >> 4) & 15u); }
 
 template <bool LRN>
 __global__ __launch_bounds__(BK_T) void k_num_bucket(
@@ -857,8 +866,8 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
     // hold the chunk counters
     __shared__ double dense[BK_CW];
     __shared__ unsigned int bits[BK_CW / 32];
-    __shared__ unsigned int wpre[BK_CW / 32];
     __shared__ unsigned int off[BK_NB + 1];
+    __shared__ unsigned short ord[BK_ORD];   // chunk column of each rank in the current round
     __shared__ unsigned int red[BK_NW];
     __shared__ long long s_base;
     __shared__ long long s_r;
@@ -1029,12 +1038,13 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
             base = (int64_t)s_base;
             if (base < 0) continue;   // uniform; no barrier pending
         }
-        // 4. per chunk: dense accumulation, popcount prefix, emission.  The
-        //    first staged products of the next nonempty chunk are loaded
-        //    while the current chunk is emitted (chunks of long sparse rows
-        //    hold a few hundred products: their load latency would dominate).
-        //    Outputs are emitted by rank (thread i takes ranks i, i + BK_T,
-        //    ...), so that stores to C are coalesced.
+        // 4. per chunk: dense accumulation, then emission.  Thread t owns
+        //    the 16 columns [16 t, 16 t + 16) of the chunk: a wave scan (DPP)
+        //    and one exchange over the waves give its first rank, and it
+        //    stores its columns in order.  The first staged products of the
+        //    next nonempty chunk are loaded while the current chunk is
+        //    emitted (chunks of long sparse rows hold a few hundred products:
+        //    their load latency would dominate).
         int64_t run = 0;
         int kk[BK_U];
         double vv[BK_U];
@@ -1047,6 +1057,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                 vv[u] = q < q1 ? sv[q] : 0.0;
             }
         };
+        const unsigned short *bits16 = reinterpret_cast<const unsigned short *>(bits);
         int b = 0;
         while (b < nb && off[b] == off[b + 1]) ++b;   // uniform
         if (b < nb) preload(b);
@@ -1058,7 +1069,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                 for (int u = 0; u < BK_U; ++u) {
                     if (kk[u] < 0) continue;
                     const uint32_t o = (uint32_t)(kk[u] - c0);
-                    atomicAdd(&dense[o], vv[u]);
+                    atomicAdd(&dense[bk_swz(o)], vv[u]);
                     atomicOr(&bits[o >> 5], 1u << (o & 31));
                 }
             };
@@ -1076,49 +1087,49 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
             int bn = b + 1;
             while (bn < nb && off[bn] == off[bn + 1]) ++bn;   // uniform
             if (bn < nb) preload(bn);
-            // exclusive popcount prefix over the chunk's words
-            const unsigned int wd = t < BK_CW / 32 ? bits[t] : 0u;
-            const unsigned int c = __popc(wd);
-            const unsigned int incl = wave_incl_scan(c);
-            if (l == 63) red[wv] = incl;
+            const unsigned int m0 = bits16[t];
+            const int c = __popc(m0);
+            const int incl = wave_incl_scan_dpp(c);
+            if (l == 63) red[wv] = (unsigned int)incl;
             __syncthreads();
             unsigned int pre = 0, tot = 0;
-            for (int i = 0; i < BK_NW; ++i) {
-                if (i < wv) pre += red[i];
-                tot += red[i];
-            }
-            if (t < BK_CW / 32) wpre[t] = pre + incl - c;
-            __syncthreads();
-            for (unsigned int k = t; k < tot; k += BK_T) {
-                // the word holding rank k: the last word whose prefix is <= k
-                int wlo = 0, whi = BK_CW / 32 - 1;
-                while (wlo < whi) {
-                    const int mid = (wlo + whi + 1) >> 1;
-                    if (wpre[mid] <= k) wlo = mid;
-                    else whi = mid - 1;
-                }
-                unsigned int m = bits[wlo];
-                int rr = (int)(k - wpre[wlo]);
-                int pos = 0;
 #pragma unroll
-                for (int h = 16; h >= 1; h >>= 1) {
-                    const int ch = __popc(m & ((1u << h) - 1u));
-                    if (rr >= ch) {
-                        rr -= ch;
-                        m >>= h;
-                        pos += h;
+            for (int i = 0; i < BK_NW; ++i) {
+                const unsigned int r = red[i];
+                pre += i < wv ? r : 0u;
+                tot += r;
+            }
+            pre += (unsigned int)(incl - c);   // rank of thread t's first column
+            // rounds of BK_ORD ranks: every thread writes the columns of its
+            // ranks in the round into ord[], then the ranks are stored in order
+            // (thread k takes ranks k, k + BK_T, ...: coalesced stores to C)
+            for (unsigned int r0 = 0; r0 < tot; r0 += BK_ORD) {
+                if (pre < r0 + BK_ORD && pre + (unsigned int)c > r0) {
+                    unsigned int m = m0;
+                    unsigned int k = pre;
+                    while (m) {
+                        const int bit = __ffs(m) - 1;
+                        m &= m - 1u;
+                        if (k >= r0 && k < r0 + BK_ORD) ord[k - r0] = (unsigned short)((t << 4) + bit);
+                        ++k;
                     }
                 }
-                const int o = (wlo << 5) + pos;
-                const int64_t kr = run + k;
-                if (kr < n) {
-                    ccol[base + kr] = c0 + o;
-                    cval[base + kr] = dense[o];
+                __syncthreads();
+                const unsigned int cnt = tot - r0 < (unsigned int)BK_ORD ? tot - r0 : (unsigned int)BK_ORD;
+                for (unsigned int k = t; k < cnt; k += BK_T) {
+                    const uint32_t o = ord[k];
+                    const uint32_t q = bk_swz(o);
+                    const double v = dense[q];
+                    dense[q] = 0.0;
+                    const int64_t kr = run + r0 + k;
+                    if (kr < n) {
+                        ccol[base + kr] = c0 + (int)o;
+                        cval[base + kr] = v;
+                    }
                 }
-                dense[o] = 0.0;
+                __syncthreads();
             }
-            __syncthreads();
-            if (wd) bits[t] = 0u;
+            if (t < BK_CW / 32) bits[t] = 0u;
             run += tot;
             __syncthreads();
             b = bn;

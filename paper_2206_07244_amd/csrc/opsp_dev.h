@@ -200,6 +200,19 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     return v;
 }
 
+// Inclusive prefix sum across the wave with DPP moves (no LDS round trips):
+// shifts by 1, 2, 4, 8 lanes within each row of 16 lanes, then lane 15 of a
+// row added into the next row and lane 31 into the upper half (row_bcast).
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return v;
+}
+
 // Synchronise the lanes of one wave through LDS: every LDS write issued
 // before is visible to every lane of the wave after.
 __device__ __forceinline__ void wave_lds_sync() {
