@@ -80,6 +80,8 @@ def workload_class(name: str) -> str:
         return "rmat"
     if name.startswith("band"):
         return "banded"
+    if name.startswith("bst"):
+        return "fem"
     return "stencil"
 
 
@@ -699,21 +701,35 @@ def bench_batched(args, dev):
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
-    with torch.cuda.stream(stream):
-        batch = ops.Batch(dA, dB, stream=stream)
+    from paper_2206_07244_amd import autotune
+    tuned = None if args.no_tuning else autotune.load_config("batch")
+
+    def time_batch(cfg):
+        """ms per execution of a batch created with `cfg` (graphs replayed)."""
+        batch = ops.Batch(dA, dB, config=cfg, stream=stream)
         st = ops.Stats()
         batch.execute(stats=st)
         for _ in range(max(args.warmup, 1)):
             batch.raw_execute(sh)
         torch.cuda.synchronize()
-        nprod, nnzC = st.nprod, st.nnz
         t1 = time.perf_counter()
         for _ in range(args.steps):
             batch.raw_execute(sh)
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        ms = (t2 - t1) * 1e3 / args.steps
-        log(f"batched: {ms:.3f} ms per batch, nprod={nprod}, nnz={nnzC}")
+        ms_ = (time.perf_counter() - t1) * 1e3 / args.steps
+        del batch
+        torch.cuda.synchronize()
+        return ms_, st
+
+    with torch.cuda.stream(stream):
+        ms, st = time_batch(tuned)
+        nprod, nnzC = st.nprod, st.nnz
+        log(f"batched ({'tuned batch class' if tuned is not None else 'built-in'}): {ms:.3f} ms per "
+            f"batch, nprod={nprod}, nnz={nnzC}")
+        ms_builtin = None
+        if tuned is not None:
+            ms_builtin, _ = time_batch(None)
+            log(f"batched (built-in configuration): {ms_builtin:.3f} ms per batch")
         # the same products as separate plain calls
         Ac = [a._c_fast(a.nnz) for a in dA]
         Bc = [b._c_fast(b.nnz) for b in dB]
@@ -746,10 +762,15 @@ def bench_batched(args, dev):
         "config": {"workload": f"batch{args.count}",
                    "description": "independent C_i = A_i B_i, n_i ~ U{1000..64000}, Poisson(8) "
                                   "rows, N(0,1) values, seed 4",
-                   "nprod": nprod, "nnzC": nnzC, "path": "batched (two replayed graphs)"},
+                   "nprod": nprod, "nnzC": nnzC, "path": "batched (two replayed graphs)",
+                   "bins": "autotuned (batch)" if tuned is not None else "built-in"},
         "plain_calls_ms": round(ms_plain, 3),
         "speedup_vs_plain_calls": round(ms_plain / ms, 3),
     }
+    if ms_builtin is not None:
+        out["builtin_config"] = {"ms_per_step": round(ms_builtin, 4),
+                                 "value": round(2.0 * nprod / (ms_builtin * 1e-3) / 1e9, 3),
+                                 "tuned_speedup": round(ms_builtin / ms, 4)}
     print(json.dumps(out), flush=True)
 
 

@@ -118,6 +118,13 @@ typedef struct {
      * result is used.  0 = the library default (1: the calling stream
      * only), at most 4. */
     int32_t streams;
+    /* Version >= 3: lanes per row of bin 0, the bin that packs several short
+     * rows into one 256-lane workgroup: 4, 8 or 16, with per-row tables of
+     * 64 / 128 / 256 keys (symbolic) and 19 / 39 / 79 entries (numeric), the
+     * same LDS per workgroup.  0 = 8.  The one-phase product always uses 8.
+     * Bin 0's ratio bound follows the table size; explicit bounds of bin 0
+     * may not exceed it. */
+    int32_t group_lanes;
 } opsp_config;
 
 /* Counters of one call (filled when a stats pointer is given). */

@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
                 ("sym_abort_fraction", c_double), ("b_lanes", c_int32),
                 ("stage_timing", c_int32), ("validate", c_int32), ("fixed_grid", c_int32),
                 ("sym_bounds", c_int64 * 7), ("num_bounds", c_int64 * 7),
-                ("hash_all_rows", c_int32), ("streams", c_int32)]
+                ("hash_all_rows", c_int32), ("streams", c_int32), ("group_lanes", c_int32)]
 
     def __init__(self, **kw):
         super().__init__()
@@ -71,7 +71,8 @@ class Config(ctypes.Structure):
         return {"sym_ratio": self.sym_ratio, "num_ratio": self.num_ratio,
                 "sym_abort_fraction": self.sym_abort_fraction,
                 "sym_bounds": list(self.sym_bounds), "num_bounds": list(self.num_bounds),
-                "hash_all_rows": self.hash_all_rows, "streams": self.streams}
+                "hash_all_rows": self.hash_all_rows, "streams": self.streams,
+                "group_lanes": self.group_lanes}
 
 
 class Stats(ctypes.Structure):

@@ -6,15 +6,17 @@ ratios (Sym 1x/1.2x/1.5x, Num 1x/1.5x/2x/3x) to pick Sym_1.2x and Num_2x.
 This tuner starts from that grid, refines the best pair of ratios, then
 moves each bin boundary of the best configuration on its own (coordinate
 search over the explicit per-bin bounds of opsp_config version 2, each kept
-within its table's capacity), and finally the abort fraction of the largest
-symbolic table.  Each candidate is timed on sample inputs of one workload
+within its table's capacity), then the abort fraction of the largest
+symbolic table and hashing every row, the lanes per row of bin 0 with its
+table sizes (4 / 8 / 16 lanes: tables of 64 / 128 / 256 keys), and the
+number of streams the bin kernels are spread over.  Each candidate is timed on sample inputs of one workload
 class; the fastest configuration per class is written to JSON.
 
 The search policy (``search``) is separate from the timing (``GpuTimer``) so
 that it can be exercised with any cost function.
 
 Usage:
-  python -m paper_2206_07244_amd.autotune --out tuning.json [--classes stencil,rmat,banded,batch]
+  python -m paper_2206_07244_amd.autotune --out tuning.json [--classes stencil,fem,rmat,banded,batch]
 """
 from __future__ import annotations
 
@@ -35,6 +37,8 @@ PAPER_SYM = [1.0, 1.2, 1.5]
 PAPER_NUM = [1.0, 1.5, 2.0, 3.0]
 BOUND_STEPS = [0.5, 0.75, 1.25, 1.5]
 ABORT_FRACTIONS = [0.6, 0.7, 0.8, 0.9]
+GROUP_LANES = [4, 16]       # bin 0: lanes per row (and with them its table sizes)
+STREAMS = [2, 4]            # bin kernels spread over several streams
 
 
 def log(*a):
@@ -48,12 +52,13 @@ class Candidate(dict):
     def key(self):
         return (round(self["sym_ratio"], 6), round(self["num_ratio"], 6), tuple(self["sym_bounds"]),
                 tuple(self["num_bounds"]), round(self["sym_abort_fraction"], 6),
-                int(self.get("hash_all_rows", 0)))
+                int(self.get("hash_all_rows", 0)), int(self.get("group_lanes", 0)),
+                int(self.get("streams", 0)))
 
 
 def base_candidate(sr=1.2, nr=2.0) -> Candidate:
     return Candidate(sym_ratio=sr, num_ratio=nr, sym_bounds=[0] * 7, num_bounds=[0] * 7,
-                     sym_abort_fraction=0.8, hash_all_rows=0)
+                     sym_abort_fraction=0.8, hash_all_rows=0, group_lanes=0, streams=0)
 
 
 def derived_bounds(step: int, tsizes: List[int], ratio: float) -> List[int]:
@@ -143,6 +148,24 @@ def search(cost: Callable[[Candidate], float], sym_t: List[int], num_t: List[int
         v = ev(c)
         if v < bc:
             best, bc = c, v
+    # 5. lanes per row of bin 0 (its tables grow or shrink with them; an
+    #    explicit bin-0 bound is re-derived from the ratio), then several
+    #    streams for the bin kernels
+    if abort:
+        for g in GROUP_LANES:
+            c = Candidate(best)
+            c["group_lanes"] = g
+            c["sym_bounds"] = [0] + list(best["sym_bounds"][1:])
+            c["num_bounds"] = [0] + list(best["num_bounds"][1:])
+            v = ev(c)
+            if v < bc:
+                best, bc = c, v
+        for n in STREAMS:
+            c = Candidate(best)
+            c["streams"] = n
+            v = ev(c)
+            if v < bc:
+                best, bc = c, v
     return best, bc
 
 
@@ -150,7 +173,8 @@ def to_config(c: dict):
     import paper_2206_07244_amd as ops
     return ops.Config(sym_ratio=c["sym_ratio"], num_ratio=c["num_ratio"],
                       sym_abort_fraction=c["sym_abort_fraction"], sym_bounds=c["sym_bounds"],
-                      num_bounds=c["num_bounds"], hash_all_rows=int(c.get("hash_all_rows", 0)))
+                      num_bounds=c["num_bounds"], hash_all_rows=int(c.get("hash_all_rows", 0)),
+                      group_lanes=int(c.get("group_lanes", 0)), streams=int(c.get("streams", 0)))
 
 
 def load_config(cls: str, path: Optional[str] = None):
@@ -196,6 +220,9 @@ def class_inputs(cls: str):
     if cls == "stencil":
         A = syn.stencil27(60, seed=60)
         return [(A, A)]
+    if cls == "fem":
+        A = syn.block_stencil27(24, 3, seed=24)
+        return [(A, A)]
     if cls == "rmat":
         A = syn.rmat(18, 16, seed=18)
         return [(A, A)]
@@ -238,7 +265,7 @@ def make_runner(cls: str, dev):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TUNING)
-    ap.add_argument("--classes", default="stencil,rmat,banded,batch")
+    ap.add_argument("--classes", default="stencil,fem,rmat,banded,batch")
     ap.add_argument("--calls", type=int, default=3)
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args(argv)

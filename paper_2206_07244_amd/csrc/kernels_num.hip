@@ -1268,17 +1268,25 @@ hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
     if (!a.src.dctr && !a.src.count && a.src.nrows == 0) return hipSuccess;
     switch (bin) {
         case 0: {
-            constexpr int RPW = 256 / NUM_GL;
-            const int64_t grid = grid_for(a, RPW);
+            const int gv = a.lrn.mode == 1 ? 0 : a.gv;
+            const int64_t grid = grid_for(a, 256 / GROUP_GL[gv]);
             if (grid <= 0) return hipSuccess;
             if (a.lrn.mode == 1)
-                hipLaunchKernelGGL((k_num_group<NUM_GL, NUM_T[0], true>), dim3((unsigned)grid), dim3(256),
-                                   0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val,
-                                   a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
+                hipLaunchKernelGGL((k_num_group<GROUP_GL[0], NUM_T0[0], true>), dim3((unsigned)grid),
+                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
+                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
+            else if (gv == 1)
+                hipLaunchKernelGGL((k_num_group<GROUP_GL[1], NUM_T0[1], false>), dim3((unsigned)grid),
+                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
+                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
+            else if (gv == 2)
+                hipLaunchKernelGGL((k_num_group<GROUP_GL[2], NUM_T0[2], false>), dim3((unsigned)grid),
+                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
+                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
             else
-                hipLaunchKernelGGL((k_num_group<NUM_GL, NUM_T[0], false>), dim3((unsigned)grid), dim3(256),
-                                   0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val,
-                                   a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
+                hipLaunchKernelGGL((k_num_group<GROUP_GL[0], NUM_T0[0], false>), dim3((unsigned)grid),
+                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
+                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
             return hipGetLastError();
         }
         case 1: return go_row<NUM_W[1], NUM_T[1]>(a, s);

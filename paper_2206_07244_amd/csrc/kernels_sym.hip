@@ -352,11 +352,21 @@ hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
     if (!a.src.dctr && !a.src.count && a.src.nrows == 0) return hipSuccess;
     switch (bin) {
         case 0: {
-            constexpr int RPW = 256 / SYM_GL;
-            const int64_t grid = grid_for(a, RPW);
+            const int64_t grid = grid_for(a, 256 / GROUP_GL[a.gv]);
             if (grid <= 0) return hipSuccess;
-            hipLaunchKernelGGL((k_sym_group<SYM_GL, SYM_T[0]>), dim3((unsigned)grid), dim3(256), 0, s,
-                               a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.ctr);
+            switch (a.gv) {
+                case 1:
+                    hipLaunchKernelGGL((k_sym_group<GROUP_GL[1], SYM_T0[1]>), dim3((unsigned)grid), dim3(256), 0,
+                                       s, a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.ctr);
+                    break;
+                case 2:
+                    hipLaunchKernelGGL((k_sym_group<GROUP_GL[2], SYM_T0[2]>), dim3((unsigned)grid), dim3(256), 0,
+                                       s, a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.ctr);
+                    break;
+                default:
+                    hipLaunchKernelGGL((k_sym_group<GROUP_GL[0], SYM_T0[0]>), dim3((unsigned)grid), dim3(256), 0,
+                                       s, a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.ctr);
+            }
             return hipGetLastError();
         }
         case 1: return go_row<SYM_W[1], SYM_T[1], false>(a, s);

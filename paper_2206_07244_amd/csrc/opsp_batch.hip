@@ -115,6 +115,7 @@ struct opsp_batch {
     int64_t M = 0, K = 0, nnzA = 0, nnzB = 0, Nmax = 0;
     int64_t sym_ub[8] = {};
     Bounds bs, bn;
+    int gv = 0;                      // bin 0 variant (lanes per row, table size)
     // device memory (cache blocks)
     std::vector<std::pair<void *, size_t>> owned;
     ProbDesc *d_desc = nullptr;
@@ -181,6 +182,7 @@ opsp_status capture_g1(opsp_batch *b, hipStream_t s) {
         if ((e = launch_scatter(b->M, b->crpt, b->bs, &b->ctr[0], b->bins, b->parts, false, s)) != hipSuccess) return e;
         SymArgs sa;
         memset(&sa, 0, sizeof(sa));
+        sa.gv = b->gv;
         sa.A = A;
         sa.B = B;
         sa.nnz = b->crpt;
@@ -193,7 +195,7 @@ opsp_status capture_g1(opsp_batch *b, hipStream_t s) {
             sa.src.dctr = &b->ctr[0];
             sa.src.bin = bin;
             int64_t g = (int64_t)b->cus * sym_wg_per_cu(bin);
-            const int64_t R = sym_rows_per_wg(bin);
+            const int64_t R = sym_rows_per_wg(bin, b->gv);
             const int64_t need = (b->M + R - 1) / R;
             sa.grid = g < need ? g : need;
             if (sa.grid < 1) sa.grid = 1;
@@ -249,6 +251,7 @@ opsp_status capture_g2(opsp_batch *b, const int64_t *sizes, hipStream_t s) {
         if ((e = hipGetLastError()) != hipSuccess) return e;
         NumArgs na;
         memset(&na, 0, sizeof(na));
+        na.gv = b->gv;
         na.A = A;
         na.B = B;
         na.crpt = b->crpt;
@@ -398,11 +401,13 @@ opsp_status opsp_batch_create(int32_t count, const opsp_csr *A, const opsp_csr *
     // the batch's kernels route every row by its natural bin
     opsp_config c2;
     memset(&c2, 0, sizeof(c2));
-    if (cfg) memcpy(&c2, cfg, cfg->version >= 2 ? sizeof(opsp_config)
-                                                : offsetof(opsp_config, sym_bounds));
+    if (cfg) memcpy(&c2, cfg, cfg->version >= 3   ? sizeof(opsp_config)
+                              : cfg->version == 2 ? offsetof(opsp_config, streams)
+                                                  : offsetof(opsp_config, sym_bounds));
     c2.force_sym_bin = c2.force_num_bin = -1;
-    b->bs = opsp::host::config_bounds(0, &c2);
-    b->bn = opsp::host::config_bounds(1, &c2);
+    b->gv = opsp::host::gv_of(&c2);
+    b->bs = opsp::host::config_bounds(0, &c2, b->gv);
+    b->bn = opsp::host::config_bounds(1, &c2, b->gv);
 
     // device memory
     void *p = nullptr;

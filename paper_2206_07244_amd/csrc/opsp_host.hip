@@ -44,6 +44,7 @@ struct opsp_plan {
     bool check = false;
     int64_t fixed_grid = 0;             // > 0: every bin kernel runs persistently with this grid
     int streams = 1;                    // streams the numeric bin kernels are spread over
+    int gv = 0;                         // bin 0 variant (lanes per row, table size)
     Counters *ctr = nullptr;            // device counters (numeric step), owned
     int2 *range = nullptr;              // output column range (lo, hi) per row (owned)
     opsp_stats stats = {};
@@ -252,25 +253,29 @@ int64_t bound_for(int step, int64_t t, double ratio) {
     return b;
 }
 
-Bounds make_bounds(int step, double ratio, int force) {
+int gv_of(const opsp_config *c) {
+    return (c && c->version >= 3) ? group_variant(c->group_lanes) : 0;
+}
+
+Bounds make_bounds(int step, double ratio, int force, int gv) {
     Bounds b;
     memset(&b, 0, sizeof(b));
     if (step == 0) {
         b.nb = SYM_NLDS;                    // bins 0..7 natural; 8 only by force
-        for (int j = 0; j < SYM_NLDS - 1; ++j) b.ub[j] = bound_for(0, SYM_T[j], ratio);
+        for (int j = 0; j < SYM_NLDS - 1; ++j) b.ub[j] = bound_for(0, j ? SYM_T[j] : SYM_T0[gv], ratio);
         b.nslots = SYM_NLDS + 1;
     } else {
         b.nb = NUM_NLDS + 1;                // bins 0..6 LDS, 7 global
-        for (int j = 0; j < NUM_NLDS; ++j) b.ub[j] = bound_for(1, NUM_T[j], ratio);
+        for (int j = 0; j < NUM_NLDS; ++j) b.ub[j] = bound_for(1, j ? NUM_T[j] : NUM_T0[gv], ratio);
         b.nslots = NUM_NLDS + 1;
     }
     b.force = force;
     return b;
 }
 
-Bounds config_bounds(int step, const opsp_config *c) {
+Bounds config_bounds(int step, const opsp_config *c, int gv) {
     const int force = c ? (step == 0 ? c->force_sym_bin : c->force_num_bin) : -1;
-    Bounds b = make_bounds(step, step == 0 ? sym_ratio(c) : num_ratio(c), force);
+    Bounds b = make_bounds(step, step == 0 ? sym_ratio(c) : num_ratio(c), force, gv);
     if (c && c->version >= 2) {
         const int64_t *eb = step == 0 ? c->sym_bounds : c->num_bounds;
         for (int j = 0; j < 7; ++j)
@@ -283,6 +288,8 @@ opsp_status check_config(const opsp_config *c) {
     if (!c) return OPSP_OK;
     if (c->version < 1 || c->version > 3) return OPSP_ERR_INVALID;
     if (c->version >= 3 && (c->streams < 0 || c->streams > MAX_STREAMS)) return OPSP_ERR_INVALID;
+    if (c->version >= 3 && group_variant(c->group_lanes) < 0) return OPSP_ERR_INVALID;
+    const int gv = gv_of(c);
     if (c->sym_ratio != 0 && !(c->sym_ratio >= 1.0)) return OPSP_ERR_INVALID;
     if (c->num_ratio != 0 && !(c->num_ratio >= 1.0)) return OPSP_ERR_INVALID;
     if (c->force_sym_bin < -1 || c->force_sym_bin > SYM_GLOBAL_BIN) return OPSP_ERR_INVALID;
@@ -290,8 +297,8 @@ opsp_status check_config(const opsp_config *c) {
     if (c->b_lanes != 0) return OPSP_ERR_INVALID;
     if (c->version >= 2) {
         for (int j = 0; j < 7; ++j) {
-            if (c->sym_bounds[j] < -1 || c->sym_bounds[j] > SYM_T[j]) return OPSP_ERR_INVALID;
-            if (c->num_bounds[j] < -1 || c->num_bounds[j] > NUM_T[j]) return OPSP_ERR_INVALID;
+            if (c->sym_bounds[j] < -1 || c->sym_bounds[j] > (j ? SYM_T[j] : SYM_T0[gv])) return OPSP_ERR_INVALID;
+            if (c->num_bounds[j] < -1 || c->num_bounds[j] > (j ? NUM_T[j] : NUM_T0[gv])) return OPSP_ERR_INVALID;
         }
     }
     return OPSP_OK;
@@ -404,8 +411,10 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     parts.mx = parts.tot + nblk;
     parts.hist = (unsigned int *)(parts.mx + nblk);
 
-    const Bounds bs = config_bounds(0, cfg);
-    const Bounds bn = config_bounds(1, cfg);
+    const int gv = gv_of(cfg);
+    plan->gv = gv;
+    const Bounds bs = config_bounds(0, cfg, gv);
+    const Bounds bn = config_bounds(1, cfg, gv);
     const DevCSR dA = dev_of(A), dB = dev_of(B);
 
     // 1 setup + first symbolic binning pass
@@ -433,6 +442,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.nnz = crpt;
     sa.ctr = ctrS;
     sa.rng = rng;
+    sa.gv = gv;
     const bool need_slab = !rng || N > ((int64_t)SW_MAXPASS << SW_LG);
     int *slab = nullptr;
     int64_t slab_entries = 0;
@@ -448,7 +458,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     fail_list = (int32_t *)p;
     auto grid_of = [&](int b) -> int64_t {
         if (plan->fixed_grid > 0) return plan->fixed_grid;
-        const int64_t R = sym_rows_per_wg(b);
+        const int64_t R = sym_rows_per_wg(b, gv);
         const int64_t need = (M + R - 1) / R;
         const int64_t g = (int64_t)cus * sym_wg_per_cu(b);
         return g < need ? g : need;
@@ -559,6 +569,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     Arena ar(s);
     NumArgs na;
     memset(&na, 0, sizeof(na));
+    na.gv = plan->gv;
     na.A = dev_of(A);
     na.B = dev_of(B);
     na.crpt = plan->crpt;

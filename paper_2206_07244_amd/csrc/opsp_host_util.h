@@ -48,10 +48,12 @@ double sym_ratio(const opsp_config *c);
 double num_ratio(const opsp_config *c);
 int64_t bound_for(int step, int64_t t, double ratio);
 // Bin bounds of step 0 (symbolic) or 1 (numeric) for a ratio (Section 5.7).
-Bounds make_bounds(int step, double ratio, int force);
+Bounds make_bounds(int step, double ratio, int force, int gv = 0);
+// Bin 0 variant of a configuration (GROUP_GL / SYM_T0 / NUM_T0).
+int gv_of(const opsp_config *c);
 // Bin bounds of a step from a (checked) configuration: ratio rule, explicit
 // per-bin bounds of version-2 configurations, forced bin.
-Bounds config_bounds(int step, const opsp_config *c);
+Bounds config_bounds(int step, const opsp_config *c, int gv);
 // Version, ratios, forced bins and explicit bounds of a configuration.
 opsp_status check_config(const opsp_config *c);
 // Device-to-host copy of a few bytes followed by a stream synchronisation.

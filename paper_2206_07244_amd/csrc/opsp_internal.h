@@ -89,6 +89,7 @@ struct SymArgs {
                              // with a narrow range are counted with a bitmap
     unsigned long long *sched;  // bin 8: Counters::sched of the launch, zero on entry
                                 // (null: rows assigned round-robin)
+    int gv;                  // bin 0 variant (GROUP_GL / SYM_T0)
 };
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
 // Workgroups per CU of a symbolic bin kernel launched persistently (its rows
@@ -111,7 +112,9 @@ inline int sym_wg_per_cu(int bin) {
     }
 }
 // Rows one workgroup of a symbolic bin kernel takes at a time.
-inline int sym_rows_per_wg(int bin) { return bin == 0 ? 256 / SYM_GL : (bin == 1 ? 4 : 1); }
+inline int sym_rows_per_wg(int bin, int gv = 0) {
+    return bin == 0 ? 256 / GROUP_GL[gv] : (bin == 1 ? 4 : 1);
+}
 
 // ---- numeric step (kernels_num.hip) ----------------------------------------
 struct NumArgs {
@@ -128,6 +131,8 @@ struct NumArgs {
     Learn lrn;               // one-phase step (lrn.mode > 0); crpt unused then
     const int2 *rng;         // optional column range of each row (setup step): rows
                              // with a narrow range accumulate densely (bins 1-6)
+    int gv;                  // bin 0 variant (GROUP_GL / NUM_T0); the one-phase
+                             // step uses variant 0
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 // Bin 7 by bucketed dense accumulation (rows with a column range in `rng`;

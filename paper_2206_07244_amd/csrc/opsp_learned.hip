@@ -143,7 +143,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     LearnedCounters hc;
 
     const Bounds bs = make_bounds(0, sym_ratio(cfg), -1);
-    const Bounds bn = config_bounds(1, cfg);
+    const Bounds bn = config_bounds(1, cfg, 0);   // the one-phase bin 0 kernel is variant 0
     const DevCSR dA = dev_of(A), dB = dev_of(B);
 
     // 1-2 setup, capacities, numeric bins by capacity, slot offsets

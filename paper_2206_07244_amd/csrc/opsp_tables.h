@@ -31,6 +31,20 @@ constexpr int NUM_T[NUM_NLDS] = {39, 425, 848, 1700, 3408, 6816, 13632};
 constexpr int NUM_W[NUM_NLDS] = {NUM_GL, 64, 128, 256, 512, 1024, 1024};
 constexpr int NUM_GLOBAL_BIN = 7;
 
+// Bin 0 packs several rows into one 256-lane workgroup with GROUP_GL[v]
+// lanes and a table of SYM_T0[v] / NUM_T0[v] entries per row; the variants
+// keep the workgroup's LDS the same (fewer lanes, more and smaller rows).
+// Variant 0 is the default; config.group_lanes selects another.
+constexpr int GROUP_VARIANTS = 3;
+constexpr int GROUP_GL[GROUP_VARIANTS] = {SYM_GL, 4, 16};
+constexpr int SYM_T0[GROUP_VARIANTS] = {SYM_T[0], 64, 256};
+constexpr int NUM_T0[GROUP_VARIANTS] = {NUM_T[0], 19, 79};
+static_assert(SYM_GL == NUM_GL, "one lane count for both steps");
+// Variant of a lane count (0 = default), -1 when there is none.
+constexpr int group_variant(int lanes) {
+    return lanes == 0 || lanes == GROUP_GL[0] ? 0 : lanes == GROUP_GL[1] ? 1 : lanes == GROUP_GL[2] ? 2 : -1;
+}
+
 // Workgroups per CU that the global-table kernels are sized for.
 constexpr int SYM_GLOBAL_WG_PER_CU = 1;
 

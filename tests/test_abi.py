@@ -113,3 +113,31 @@ def test_stats_struct_matches_header():
     """ctypes mirrors have the sizes the header implies."""
     assert ctypes.sizeof(ops.Stats) == 8 * (4 + ops.SYM_BINS + ops.NUM_BINS) + 4 * 8 + 8 * 5 + 8
     assert ctypes.sizeof(ops.opsp_predictor) == 4 + 4 + 8 + 8 * 3 + 8 + 8 + 4 + 4
+
+
+def test_config_fields_checked_on_host():
+    """Configuration errors are caught before any device work (the fake
+    device pointers are never dereferenced): stream count, lanes per row of
+    bin 0, explicit bounds beyond the table of the chosen variant, and the
+    ctypes mirror's layout (version-3 fields at the end)."""
+    L = ops.lib()
+    A = ops.opsp_csr(rows=3, cols=4, nnz=0, rpt=1, col=None, val=None)
+    B = ops.opsp_csr(rows=4, cols=2, nnz=0, rpt=1, col=None, val=None)
+    C = ops.opsp_csr()
+
+    def call(**kw):
+        c = ops.Config(**kw)
+        return L.opsp_spgemm_ex(ctypes.byref(A), ctypes.byref(B), ctypes.byref(C), ctypes.byref(c),
+                                None, None)
+
+    assert call(streams=5) == 1
+    assert call(streams=-1) == 1
+    assert call(group_lanes=5) == 1
+    assert call(group_lanes=32) == 1
+    # bin 0's table: 128 keys / 39 entries by default, 64 / 19 with 4 lanes
+    assert call(group_lanes=4, sym_bounds=[65, 0, 0, 0, 0, 0, 0]) == 1
+    assert call(group_lanes=4, num_bounds=[20, 0, 0, 0, 0, 0, 0]) == 1
+    assert call(version=4) == 1
+    fields = [f for f, _ in ops.Config._fields_]
+    assert fields[-2:] == ["streams", "group_lanes"]
+    assert ops.Config.group_lanes.offset == ops.Config.streams.offset + 4

@@ -78,3 +78,21 @@ def test_load_config_roundtrip(tmp_path):
     assert list(cfg.num_bounds) == [10, 200, 0, 0, 0, 0, -1]
     assert at.load_config("stencil", str(p)) is None
     assert at.load_config("rmat", str(tmp_path / "missing.json")) is None
+
+
+def test_group_lanes_and_streams_search():
+    """After the bounds, the search tries bin 0 with 4 and 16 lanes per row
+    (its explicit bound re-derived: the table size changes with the lanes)
+    and several streams, and keeps what is cheaper."""
+    def cost(c):
+        v = 10.0
+        if c.get("group_lanes", 0) == 16:
+            v -= 2.0
+            assert c["sym_bounds"][0] == 0 and c["num_bounds"][0] == 0
+        if c.get("streams", 0) == 2:
+            v -= 1.0
+        return v
+    best, v = at.search(cost, [128, 1024, 2048, 4096, 8192, 16384, 20448, 40896],
+                        [39, 425, 848, 1700, 3408, 6816, 13632], refine=False, coordinate=False)
+    assert best["group_lanes"] == 16 and best["streams"] == 2 and v == 7.0
+

@@ -32,11 +32,11 @@ def _problems(seed):
     return [(A, A if B is None else B) for A, B in probs]
 
 
-def _run(probs, stats=None):
+def _run(probs, stats=None, config=None):
     import torch
     ops = _ops()
     dev = [(ops.DeviceCSR.from_host(A), ops.DeviceCSR.from_host(B)) for A, B in probs]
-    batch = ops.Batch([a for a, _ in dev], [b for _, b in dev])
+    batch = ops.Batch([a for a, _ in dev], [b for _, b in dev], config=config)
     views = batch.execute(stats=stats)
     torch.cuda.synchronize()
     return batch, dev, views
@@ -101,3 +101,14 @@ def test_batched_structure_equals_plain_path():
         r1, c1, _ = C.to_host()
         r2, c2, _ = v.to_host()
         assert np.array_equal(r1, r2) and np.array_equal(c1, c2)
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_batched_group_lanes(lanes):
+    """The bin-0 variants (lanes per row and table sizes chosen by the
+    autotuner) inside the captured graphs."""
+    probs = _problems(9)
+    batch, dev, views = _run(probs, config=_ops().Config(group_lanes=lanes))
+    for (A, B), v in zip(probs, views):
+        oracle.compare(*v.to_host(), oracle.spgemm(A, B))
+

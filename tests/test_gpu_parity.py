@@ -371,3 +371,22 @@ def test_bins_on_several_streams(streams):
     for b in (0, 3, 7):
         check(syn.rmat(12, 16, seed=b), cfg=_ops().Config(streams=streams, force_num_bin=b,
                                                           force_sym_bin=b))
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_group_lanes_variants(lanes):
+    """Bin 0 with 4, 8 or 16 lanes per row (tables of 64 / 128 / 256 keys and
+    19 / 39 / 79 entries), every row that fits routed there."""
+    ops = _ops()
+    cases = [(syn.poisson_uniform(5000, 4000, 3.0, seed=1), syn.poisson_uniform(4000, 3000, 4.0, seed=2)),
+             (syn.lap5(30), None), (syn.rmat(12, 4, seed=12), None),
+             (syn.random_csr(300, 200, 0.08, seed=3, values="int"),
+              syn.random_csr(200, 300, 0.08, seed=4, values="int"))]
+    for i, (A, B) in enumerate(cases):
+        for forced in (-1, 0):
+            st = ops.Stats()
+            check(A, B, cfg=ops.Config(validate=1, group_lanes=lanes, force_sym_bin=forced,
+                                       force_num_bin=forced), stats=st)
+            if forced == 0 and i == 0:   # rows of about 12 products: all fit bin 0
+                assert st.sym_bin_rows[0] > 0 and st.num_bin_rows[0] > 0
+
