@@ -229,6 +229,26 @@ void opsp_plan_destroy(opsp_plan *plan);
  * zero *C.  NULL arrays are skipped. */
 opsp_status opsp_csr_free(opsp_csr *C, void *stream);
 
+/* ---- FP32 values --------------------------------------------------------
+ * The same product with single-precision values (the paper evaluates FP64
+ * only, Section 6.1; the method is the same for any value type): a CSR
+ * matrix whose val is float[nnz], otherwise laid out as opsp_csr.  Products
+ * a_ik * b_kj are rounded to float and summed in float in an unspecified
+ * order, so each value of C lies within about (number of its terms + 1)
+ * units of float rounding of sum_k |a_ik b_kj| from the exact sum of the
+ * float inputs; rows and columns are exact.  Structure, allocation,
+ * ownership, errors and the single host wait are those of opsp_spgemm_ex
+ * (release C with opsp_csr_f32_free). */
+typedef struct {
+    int64_t rows, cols, nnz;
+    int64_t *rpt;
+    int32_t *col;
+    float *val;
+} opsp_csr_f32;
+opsp_status opsp_spgemm_f32(const opsp_csr_f32 *A, const opsp_csr_f32 *B, opsp_csr_f32 *C,
+                            const opsp_config *config, opsp_stats *stats, void *stream);
+opsp_status opsp_csr_f32_free(opsp_csr_f32 *C, void *stream);
+
 /* ---- Batched products --------------------------------------------------
  * `count` independent products C_p = A_p * B_p computed as ONE block-diagonal
  * product over the concatenation of their rows (rows of C are independent,

@@ -154,6 +154,11 @@ def _bind(L):
     L.opsp_status_string.argtypes = [ctypes.c_int]
     L.opsp_spgemm.restype = ctypes.c_int
     L.opsp_spgemm.argtypes = [csr_p, csr_p, csr_p, P]
+    # the FP32 structs have opsp_csr's layout (val: float* instead of double*)
+    L.opsp_spgemm_f32.restype = ctypes.c_int
+    L.opsp_spgemm_f32.argtypes = [csr_p, csr_p, csr_p, POINTER(Config), POINTER(Stats), P]
+    L.opsp_csr_f32_free.restype = ctypes.c_int
+    L.opsp_csr_f32_free.argtypes = [csr_p, P]
     L.opsp_spgemm_ex.restype = ctypes.c_int
     L.opsp_spgemm_ex.argtypes = [csr_p, csr_p, csr_p, POINTER(Config), POINTER(Stats), P]
     L.opsp_spgemm_symbolic.restype = ctypes.c_int
@@ -298,7 +303,7 @@ def _wrap(ptr, n, dtype, owner, device):
     torch = _torch()
     if n == 0 or not ptr:
         return torch.empty(0, dtype=dtype, device=device)
-    typestr = {torch.int64: "<i8", torch.int32: "<i4", torch.float64: "<f8"}[dtype]
+    typestr = {torch.int64: "<i8", torch.int32: "<i4", torch.float64: "<f8", torch.float32: "<f4"}[dtype]
     t = torch.as_tensor(_CudaArray(int(ptr), int(n), typestr, owner), device=device)
     assert t.data_ptr() == int(ptr)
     return t
@@ -316,11 +321,13 @@ class DeviceCSR:
         return int(self.col.numel())
 
     @classmethod
-    def from_host(cls, A, device="cuda") -> "DeviceCSR":
+    def from_host(cls, A, device="cuda", dtype=np.float64) -> "DeviceCSR":
+        """Upload a host CSR; ``dtype`` np.float32 rounds the values for the
+        FP32 product."""
         torch = _torch()
         rpt = torch.from_numpy(np.ascontiguousarray(A.rpt, np.int64)).to(device)
         col = torch.from_numpy(np.ascontiguousarray(A.col, np.int32)).to(device)
-        val = torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).to(device)
+        val = torch.from_numpy(np.ascontiguousarray(A.val, dtype)).to(device)
         return cls(A.rows, A.cols, rpt, col, val)
 
     def to_host(self):
@@ -344,12 +351,12 @@ class DeviceCSR:
         return c
 
 
-def _adopt(c: opsp_csr, stream, device) -> DeviceCSR:
+def _adopt(c: opsp_csr, stream, device, vdtype=None) -> DeviceCSR:
     torch = _torch()
     owner = _Owner(c, stream)
     rpt = _wrap(c.rpt, c.rows + 1, torch.int64, owner, device)
     col = _wrap(c.col, c.nnz, torch.int32, owner, device)
-    val = _wrap(c.val, c.nnz, torch.float64, owner, device)
+    val = _wrap(c.val, c.nnz, vdtype or torch.float64, owner, device)
     return DeviceCSR(c.rows, c.cols, rpt, col, val)
 
 
@@ -363,6 +370,21 @@ def spgemm(A: DeviceCSR, B: DeviceCSR, config: Optional[Config] = None,
                                 byref(stats) if stats is not None else None, s)
     _check(code, "opsp_spgemm")
     return _adopt(Cc, s, A.rpt.device)
+
+
+def spgemm_f32(A: DeviceCSR, B: DeviceCSR, config: Optional[Config] = None,
+               stats: Optional[Stats] = None, stream=None) -> DeviceCSR:
+    """C = A*B with FP32 values (``opsp_spgemm_f32``); A and B hold float32
+    values (``DeviceCSR.from_host(..., dtype=np.float32)``)."""
+    torch = _torch()
+    assert A.val.dtype == torch.float32 and B.val.dtype == torch.float32
+    s = _stream_handle(stream)
+    Ac, Bc, Cc = A._c(), B._c(), opsp_csr()
+    code = lib().opsp_spgemm_f32(byref(Ac), byref(Bc), byref(Cc),
+                                 byref(config) if config is not None else None,
+                                 byref(stats) if stats is not None else None, s)
+    _check(code, "opsp_spgemm_f32")
+    return _adopt(Cc, s, A.rpt.device, torch.float32)
 
 
 def spgemm_raw(Ac: opsp_csr, Bc: opsp_csr, stream_handle) -> opsp_csr:

@@ -23,10 +23,21 @@
 
 namespace opsp {
 
+// Value pointers of the launch arguments in the product's value type.
+template <class V>
+struct VPtrs {
+    const V *aval, *bval;
+    V *cval, *slab_vals;
+    explicit VPtrs(const NumArgs &a)
+        : aval((const V *)a.A.val), bval((const V *)a.B.val), cval((V *)a.cval),
+          slab_vals((V *)a.slab_vals) {}
+};
+
+
 // Returns false when no slot was found after T probes (cannot happen when the
 // bin bounds hold; reported instead of spinning).
-__device__ __forceinline__ bool num_insert_lds(int *keys, double *vals, uint32_t T, int key,
-                                               double v) {
+template <class V>
+__device__ __forceinline__ bool num_insert_lds(int *keys, V *vals, uint32_t T, int key, V v) {
     uint32_t s = hslot(key, T);
     for (uint32_t n = 0; n < T; ++n) {
         const int old = hash_claim(&keys[s], key);
@@ -45,7 +56,7 @@ __device__ __forceinline__ bool num_insert_lds(int *keys, double *vals, uint32_t
 // iterations with a scalar counter.  Returns 1 when this lane's key was new.
 template <class KeyT, class ValT, class AddF>
 __device__ __forceinline__ int num_insert_wave(KeyT *keys, ValT *vals, uint32_t T, bool ok, int key,
-                                               double v, unsigned int *err, AddF &&add) {
+                                               ValT v, unsigned int *err, AddF &&add) {
     bool pend = ok;
     int isnew = 0;
     uint32_t s = ok ? hslot(key, T) : 0u;
@@ -103,23 +114,23 @@ __device__ __forceinline__ void lrn_done(const Learn &L, int64_t row, int64_t n,
 // bin 0: GL lanes per row (eight waves per SIMD requested: the
 // occupancy is otherwise capped at seven by scalar registers); rank counting over the packed keys
 // ---------------------------------------------------------------------------
-template <int GL, int T, bool LRN>
+template <int GL, int T, bool LRN, class V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_num_group(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
-    const double *__restrict__ aval, const int64_t *__restrict__ brpt,
-    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
+    const V *__restrict__ aval, const int64_t *__restrict__ brpt,
+    const int32_t *__restrict__ bcol, const V *__restrict__ bval,
+    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
     Counters *__restrict__ ctr, Learn L) {
     constexpr int RPW = 256 / GL;
     constexpr int ITEMS = (T + GL - 1) / GL;
-    __shared__ double vals[RPW * T];
+    __shared__ V vals[RPW * T];
     __shared__ int keys[RPW * T];
     __shared__ int ck[RPW * T];
     __shared__ int s_full[RPW];   // one-phase: the row's table filled up
     src.resolve();
     const int slot = threadIdx.x / GL, g = threadIdx.x % GL;
     int *tk = keys + slot * T;
-    double *tv = vals + slot * T;
+    V *tv = vals + slot * T;
     int *pk = ck + slot * T;
     for (int64_t b0 = (int64_t)blockIdx.x * RPW; b0 < src.nrows; b0 += (int64_t)gridDim.x * RPW) {
         const int64_t idx = b0 + slot;
@@ -137,7 +148,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             }
             for (int64_t p = arpt[row] + g; p < a1; p += GL) {
                 const int k = acol[p];
-                const double a = aval[p];
+                const V a = aval[p];
                 const int64_t b1 = brpt[k + 1];
                 bool full = false;
                 // GRP_U entries of the B row are loaded before any is
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 // unused)
                 for (int64_t q = brpt[k]; q < b1 && !full; q += GRP_U) {
                     int kk[GRP_U];
-                    double vv[GRP_U];
+                    V vv[GRP_U];
 #pragma unroll
                     for (int u = 0; u < GRP_U; ++u) {
                         const int64_t qq = q + u < b1 ? q + u : q;
@@ -338,14 +349,14 @@ __device__ __forceinline__ int team_excl_scan(int x, int &total, int *red) {
 // network instead; with binning ratios below 1.5 pairs may not fit at all and
 // entries are ranked by counting over the table.
 // ---------------------------------------------------------------------------
-template <int W, int T, bool LRN>
+template <int W, int T, bool LRN, class V>
 // wave teams: eight waves per SIMD requested (scalar registers would
 // otherwise cap the occupancy at seven)
 __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu(W == 64 ? 8 : 1))) void k_num_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
-    const double *__restrict__ aval, const int64_t *__restrict__ brpt,
-    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
+    const V *__restrict__ aval, const int64_t *__restrict__ brpt,
+    const int32_t *__restrict__ bcol, const V *__restrict__ bval,
+    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
     Counters *__restrict__ ctr, Learn L, const int2 *__restrict__ rng) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
@@ -358,7 +369,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     // keys, so the table never holds more than THR + W <= T keys.
     constexpr int THR = (4 * T) / 5 < T - W ? (4 * T) / 5 : T - W;
     static_assert(THR > 0, "table too small for the one-phase bound");
-    __shared__ double vals[R * T];
+    __shared__ V vals[R * T];
     __shared__ int keys[R * T];
     __shared__ int red[3 * NW];
     __shared__ int s_cnt[R];
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / W), t = threadIdx.x % W;
     const int wv = t >> 6;
     int *tk = keys + team * T;
-    double *tv = vals + team * T;
+    V *tv = vals + team * T;
     // one team per row (grids are sized from the numeric bin counts, which
     // are always read back before this step); every lane of the team makes
     // the same early returns
@@ -433,7 +444,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     if (dn) {   // uniform over the team
         if (active) {
             unsigned int *bits = reinterpret_cast<unsigned int *>(tk);
-            auto acc = [&](bool ok, int key, double v) {
+            auto acc = [&](bool ok, int key, V v) {
                 const uint32_t o = (uint32_t)(key - lo);
                 if (ok && o < (uint32_t)dspan) {
                     atomicOr(&bits[o >> 5], 1u << (o & 31));
@@ -479,9 +490,9 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     // count in a scalar register; larger teams add into LDS.
     int wcnt = 0;
     if (active) {
-        auto ins = [&](bool ok, int key, double v) {
+        auto ins = [&](bool ok, int key, V v) {
             const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
-                                           [](double *p, double x) { atomicAdd(p, x); });
+                                           [](V *p, V x) { atomicAdd(p, x); });
             if constexpr (LRN) {
                 const int nm = (int)__popcll(__ballot(nw));
                 if constexpr (WT) wcnt += nm;
@@ -676,13 +687,13 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
 // bin 7: global-memory tables (one slab per persistent workgroup), ordered
 // through LDS bitmaps of 2^19 columns at a time.
 // ---------------------------------------------------------------------------
-template <bool LRN>
+template <bool LRN, class V>
 __global__ __launch_bounds__(1024) void k_num_global(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
-    const double *__restrict__ aval, const int64_t *__restrict__ brpt,
-    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    int *slab_keys, double *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr, Learn L) {
+    const V *__restrict__ aval, const int64_t *__restrict__ brpt,
+    const int32_t *__restrict__ bcol, const V *__restrict__ bval,
+    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
+    int *slab_keys, V *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr, Learn L) {
     constexpr int CW = NUM_GLOBAL_CHUNK_WORDS;
     constexpr int CBITS = CW * 32;
     constexpr int WPT = CW / 1024;  // bitmap words per thread
@@ -695,7 +706,7 @@ __global__ __launch_bounds__(1024) void k_num_global(
 
     src.resolve();
     int *tk = slab_keys + (int64_t)blockIdx.x * slab_entries;
-    double *tv = slab_vals + (int64_t)blockIdx.x * slab_entries;
+    V *tv = slab_vals + (int64_t)blockIdx.x * slab_entries;
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
 
     for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
@@ -729,13 +740,13 @@ __global__ __launch_bounds__(1024) void k_num_global(
         __syncthreads();
 
         int kmin = INT_MAX, kmax = -1;
-        auto ins = [&](bool ok, int key, double v) {
+        auto ins = [&](bool ok, int key, V v) {
             if (ok) {
                 kmin = key < kmin ? key : kmin;
                 kmax = key > kmax ? key : kmax;
             }
             const int nw = num_insert_wave(tk, tv, T, ok, key, v, &ctr->error,
-                                           [](double *p, double x) { unsafeAtomicAdd(p, x); });
+                                           [](V *p, V x) { unsafeAtomicAdd(p, x); });
             if constexpr (LRN) {
                 const unsigned nm = (unsigned)__popcll(__ballot(nw));
                 if (nm && l == 0) atomicAdd(&s_cnt, nm);
@@ -853,18 +864,18 @@ constexpr int BK_ORD = 2048;        // ranks ordered per emission round
 // over the LDS banks (randomly addressed accumulation does not care).
 __device__ __forceinline__ uint32_t bk_swz(uint32_t o) { return o ^ ((o >> 4) & 15u); }
 
-template <bool LRN>
+template <bool LRN, class V>
 __global__ __launch_bounds__(BK_T) void k_num_bucket(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
-    const double *__restrict__ aval, const int64_t *__restrict__ brpt,
-    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, double *__restrict__ cval,
-    const int2 *__restrict__ rng, int *stage_keys, double *stage_vals, int64_t stage_cap,
+    const V *__restrict__ aval, const int64_t *__restrict__ brpt,
+    const int32_t *__restrict__ bcol, const V *__restrict__ bval,
+    const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
+    const int2 *__restrict__ rng, int *stage_keys, V *stage_vals, int64_t stage_cap,
     Counters *__restrict__ ctr, Learn L) {
     // dense accumulator of one chunk; while the products are counted and
     // scattered (before any chunk is accumulated) its first BK_NB / 2 words
     // hold the chunk counters
-    __shared__ double dense[BK_CW];
+    __shared__ V dense[BK_CW];
     __shared__ unsigned int bits[BK_CW / 32];
     __shared__ unsigned int off[BK_NB + 1];
     __shared__ unsigned short ord[BK_ORD];   // chunk column of each rank in the current round
@@ -876,7 +887,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
     unsigned int *cc = reinterpret_cast<unsigned int *>(dense);
     int *sk = stage_keys + (int64_t)blockIdx.x * stage_cap;
-    double *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
+    V *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
     for (int i = t; i < BK_CW; i += BK_T) dense[i] = 0.0;
     for (int i = t; i < BK_CW / 32; i += BK_T) bits[i] = 0u;
 
@@ -923,7 +934,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
             run_len = in ? next - head_lane : 0;
         };
         // 1. products per chunk
-        row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, BK_NW,
+        row_products<false, WIDE_D>(a0, a1, acol, (const V *)nullptr, brpt, bcol, (const V *)nullptr, wv, BK_NW,
                                   [&](bool ok, int key) {
                                       const uint32_t o = (uint32_t)(key - lo);
                                       const bool in = ok && o < (uint64_t)span;
@@ -972,7 +983,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         //    workgroup's spare last entry, so that no branch sits around the
         //    stores, which count with the loads in flight)
         row_products<true, WIDE_D>(a0, a1, acol, aval, brpt, bcol, bval, wv, BK_NW,
-                                   [&](bool ok, int key, double v) {
+                                   [&](bool ok, int key, V v) {
                                        const uint32_t o = (uint32_t)(key - lo);
                                        const bool in = ok && o < (uint64_t)span;
                                        const int c = in ? (int)(o >> BK_LG) : -1;
@@ -993,7 +1004,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         // reads below (plain loads, so that several are in flight per thread)
         __threadfence();
         __syncthreads();
-        for (int i = t; i < BK_NB / 2; i += BK_T) dense[i] = 0.0;
+        for (int i = t; i < BK_NB * 4 / (int)sizeof(V); i += BK_T) dense[i] = V(0);
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if constexpr (LRN) {
@@ -1047,7 +1058,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         //    their load latency would dominate).
         int64_t run = 0;
         int kk[BK_U];
-        double vv[BK_U];
+        V vv[BK_U];
         auto preload = [&](int bb) {
             const unsigned int q0 = off[bb], q1 = off[bb + 1];
 #pragma unroll
@@ -1119,7 +1130,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                 for (unsigned int k = t; k < cnt; k += BK_T) {
                     const uint32_t o = ord[k];
                     const uint32_t q = bk_swz(o);
-                    const double v = dense[q];
+                    const V v = dense[q];
                     dense[q] = 0.0;
                     const int64_t kr = run + r0 + k;
                     if (kr < n) {
@@ -1139,17 +1150,24 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
     }
 }
 
+template <class V>
+static hipError_t go_bucket(const NumArgs &a, hipStream_t s) {
+    const VPtrs<V> v(a);
+    if (a.lrn.mode > 0)
+        hipLaunchKernelGGL((k_num_bucket<true, V>), dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
+                           a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval, a.rng,
+                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+    else
+        hipLaunchKernelGGL((k_num_bucket<false, V>), dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
+                           a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval, a.rng,
+                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+    return hipGetLastError();
+}
+
 hipError_t launch_numeric_bucket(const NumArgs &a, hipStream_t s) {
     if (a.grid <= 0 || !a.rng) return hipSuccess;
-    if (a.lrn.mode > 0)
-        hipLaunchKernelGGL(k_num_bucket<true>, dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
-                           a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng,
-                           a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
-    else
-        hipLaunchKernelGGL(k_num_bucket<false>, dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
-                           a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol, a.cval, a.rng,
-                           a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
-    return hipGetLastError();
+    if (a.fp32 && a.lrn.mode > 0) return hipErrorInvalidValue;   // one-phase step: FP64 only
+    return a.fp32 ? go_bucket<float>(a, s) : go_bucket<double>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1248,65 +1266,80 @@ static int64_t grid_for(const NumArgs &a, int64_t per_wg) {
     return (a.src.nrows + per_wg - 1) / per_wg;
 }
 
-template <int W, int T>
-static hipError_t go_row(const NumArgs &a, hipStream_t s) {
+template <int W, int T, class V>
+static hipError_t go_row_v(const NumArgs &a, hipStream_t s) {
     constexpr int R = (W == 64) ? 4 : 1;
     const int64_t grid = (a.src.nrows + R - 1) / R;   // one team per row
     if (grid <= 0) return hipSuccess;
+    const VPtrs<V> v(a);
     if (a.lrn.mode == 1)
-        hipLaunchKernelGGL((k_num_row<W, T, true>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
-                           a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                           a.cval, a.ctr, a.lrn, a.rng);
+        hipLaunchKernelGGL((k_num_row<W, T, true, V>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
+                           a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol,
+                           v.cval, a.ctr, a.lrn, a.rng);
     else
-        hipLaunchKernelGGL((k_num_row<W, T, false>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
-                           a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                           a.cval, a.ctr, a.lrn, a.rng);
+        hipLaunchKernelGGL((k_num_row<W, T, false, V>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
+                           a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol,
+                           v.cval, a.ctr, a.lrn, a.rng);
+    return hipGetLastError();
+}
+
+template <int W, int T>
+static hipError_t go_row(const NumArgs &a, hipStream_t s) {
+    return a.fp32 ? go_row_v<W, T, float>(a, s) : go_row_v<W, T, double>(a, s);
+}
+
+template <class V>
+static hipError_t go_group(const NumArgs &a, hipStream_t s) {
+    const int gv = a.lrn.mode == 1 ? 0 : a.gv;
+    const int64_t grid = grid_for(a, 256 / GROUP_GL[gv]);
+    if (grid <= 0) return hipSuccess;
+    const VPtrs<V> v(a);
+    if (a.lrn.mode == 1)
+        hipLaunchKernelGGL((k_num_group<GROUP_GL[0], NUM_T0[0], true, V>), dim3((unsigned)grid),
+                           dim3(256), 0, s, a.src, a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval,
+                           a.crpt, a.ccol, v.cval, a.ctr, a.lrn);
+    else if (gv == 1)
+        hipLaunchKernelGGL((k_num_group<GROUP_GL[1], NUM_T0[1], false, V>), dim3((unsigned)grid),
+                           dim3(256), 0, s, a.src, a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval,
+                           a.crpt, a.ccol, v.cval, a.ctr, a.lrn);
+    else if (gv == 2)
+        hipLaunchKernelGGL((k_num_group<GROUP_GL[2], NUM_T0[2], false, V>), dim3((unsigned)grid),
+                           dim3(256), 0, s, a.src, a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval,
+                           a.crpt, a.ccol, v.cval, a.ctr, a.lrn);
+    else
+        hipLaunchKernelGGL((k_num_group<GROUP_GL[0], NUM_T0[0], false, V>), dim3((unsigned)grid),
+                           dim3(256), 0, s, a.src, a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval,
+                           a.crpt, a.ccol, v.cval, a.ctr, a.lrn);
+    return hipGetLastError();
+}
+
+template <class V>
+static hipError_t go_global(const NumArgs &a, hipStream_t s) {
+    if (a.grid <= 0) return hipSuccess;
+    const VPtrs<V> v(a);
+    if (a.lrn.mode > 0)
+        hipLaunchKernelGGL((k_num_global<true, V>), dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
+                           a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval,
+                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+    else
+        hipLaunchKernelGGL((k_num_global<false, V>), dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
+                           a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval,
+                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
     return hipGetLastError();
 }
 
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s) {
     if (!a.src.dctr && !a.src.count && a.src.nrows == 0) return hipSuccess;
+    if (a.fp32 && a.lrn.mode > 0) return hipErrorInvalidValue;   // one-phase step: FP64 only
     switch (bin) {
-        case 0: {
-            const int gv = a.lrn.mode == 1 ? 0 : a.gv;
-            const int64_t grid = grid_for(a, 256 / GROUP_GL[gv]);
-            if (grid <= 0) return hipSuccess;
-            if (a.lrn.mode == 1)
-                hipLaunchKernelGGL((k_num_group<GROUP_GL[0], NUM_T0[0], true>), dim3((unsigned)grid),
-                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
-                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
-            else if (gv == 1)
-                hipLaunchKernelGGL((k_num_group<GROUP_GL[1], NUM_T0[1], false>), dim3((unsigned)grid),
-                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
-                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
-            else if (gv == 2)
-                hipLaunchKernelGGL((k_num_group<GROUP_GL[2], NUM_T0[2], false>), dim3((unsigned)grid),
-                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
-                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
-            else
-                hipLaunchKernelGGL((k_num_group<GROUP_GL[0], NUM_T0[0], false>), dim3((unsigned)grid),
-                                   dim3(256), 0, s, a.src, a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col,
-                                   a.B.val, a.crpt, a.ccol, a.cval, a.ctr, a.lrn);
-            return hipGetLastError();
-        }
+        case 0: return a.fp32 ? go_group<float>(a, s) : go_group<double>(a, s);
         case 1: return go_row<NUM_W[1], NUM_T[1]>(a, s);
         case 2: return go_row<NUM_W[2], NUM_T[2]>(a, s);
         case 3: return go_row<NUM_W[3], NUM_T[3]>(a, s);
         case 4: return go_row<NUM_W[4], NUM_T[4]>(a, s);
         case 5: return go_row<NUM_W[5], NUM_T[5]>(a, s);
         case 6: return go_row<NUM_W[6], NUM_T[6]>(a, s);
-        case NUM_GLOBAL_BIN: {
-            if (a.grid <= 0) return hipSuccess;
-            if (a.lrn.mode > 0)
-                hipLaunchKernelGGL(k_num_global<true>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
-                                   a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                                   a.cval, a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
-            else
-                hipLaunchKernelGGL(k_num_global<false>, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
-                                   a.A.rpt, a.A.col, a.A.val, a.B.rpt, a.B.col, a.B.val, a.crpt, a.ccol,
-                                   a.cval, a.slab_keys, a.slab_vals, a.slab_entries, a.ctr, a.lrn);
-            return hipGetLastError();
-        }
+        case NUM_GLOBAL_BIN: return a.fp32 ? go_global<float>(a, s) : go_global<double>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

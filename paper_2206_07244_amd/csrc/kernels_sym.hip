@@ -176,7 +176,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 const uint32_t o = (uint32_t)(key - lo);
                 if (ok && o < span) atomicOr((unsigned int *)&tb[o & wmask], 1u << (o >> lgw));
             };
-            row_products<false, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, nullptr, brpt, bcol, nullptr, t >> 6, NW, set,
+            row_products<false, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, set,
                                 [] { return false; });
         } else if (active) {
             auto ins = [&](bool ok, int key) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
                 else return false;
             };
-            row_products<false, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, nullptr, brpt, bcol, nullptr, t >> 6, NW, ins, stop);
+            row_products<false, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, ins, stop);
         }
         if (bm) {   // uniform over the team
             team_sync<WT>();
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(1024) void k_sym_global(
                 for (uint32_t i = t; i < words; i += 1024) bm[i] = 0u;
                 __syncthreads();
                 const uint32_t base = (uint32_t)(lo + w0);
-                row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16,
+                row_products<false, WIDE_D>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, wv, 16,
                                     [&](bool ok, int key) {
                                         const uint32_t o = (uint32_t)key - base;
                                         if (ok && o < wlen) atomicOr(&bm[o >> 5], 1u << (o & 31));
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(1024) void k_sym_global(
             __syncthreads();
             int cnt = 0;
             auto ins = [&](bool ok, int key) { cnt += sym_insert_wave(tb, T, ok, key, &ctr->error); };
-            row_products<false, WIDE_D>(a0, a1, acol, nullptr, brpt, bcol, nullptr, wv, 16, ins,
+            row_products<false, WIDE_D>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, wv, 16, ins,
                                 [] { return false; });
             cnt = wave_sum(cnt);
             if (l == 0) red[wv] = cnt;

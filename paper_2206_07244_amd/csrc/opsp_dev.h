@@ -242,6 +242,9 @@ __device__ __forceinline__ int ld_coherent(const int *p) {
 __device__ __forceinline__ double ld_coherent(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ float ld_coherent(const float *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 }  // namespace opsp
 
@@ -314,6 +317,19 @@ __device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, in
     return isnew;
 }
 
+// Value of lane s (readlane) / of lane src_lane (bpermute) for the value
+// types of the numeric step (FP64 as two 32-bit halves, FP32 as one).
+__device__ __forceinline__ double readlane_v(double v, int s) { return readlane_f64(v, s); }
+__device__ __forceinline__ float readlane_v(float v, int s) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), s));
+}
+__device__ __forceinline__ double bpermute_v(double v, int src_lane) {
+    return __longlong_as_double(bpermute64(__double_as_longlong(v), src_lane));
+}
+__device__ __forceinline__ float bpermute_v(float v, int src_lane) {
+    return __int_as_float(bpermute(__float_as_int(v), src_lane));
+}
+
 // Enumeration of the intermediate products of one row of C = A*B
 // (Eq. 2: C_i* = sum over k in A_i* of A_ik * B_k*), spread over `nwaves`
 // waves of which the caller is wave `wv`.
@@ -335,12 +351,12 @@ __device__ __forceinline__ int sym_insert_wave(Tab *tab, uint32_t T, bool ok, in
 // (`f(ok, key)` for the symbolic step); every lane calls f once per window,
 // `ok` says whether it holds a product.  `stop()` is polled once per window
 // and ends the enumeration for the whole wave.
-template <bool NUMERIC, int D = 1, class F, class Stop>
+template <bool NUMERIC, int D = 1, class V = double, class F, class Stop>
 __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32_t *__restrict__ acol,
-                                             const double *__restrict__ aval,
+                                             const V *__restrict__ aval,
                                              const int64_t *__restrict__ brpt,
                                              const int32_t *__restrict__ bcol,
-                                             const double *__restrict__ bval, int wv_in, int nwaves,
+                                             const V *__restrict__ bval, int wv_in, int nwaves,
                                              F &&f, Stop &&stop) {
     const int l = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(wv_in);   // wave-uniform: window indices in SGPRs
@@ -348,7 +364,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         const int64_t j = c0 + l;
         const bool v = j < a1;
         int k = 0;
-        double av = 0.0;
+        V av = 0;
         if (v) {
             k = acol[j];
             if constexpr (NUMERIC) av = aval[j];
@@ -375,7 +391,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         auto pipelined = [&](int64_t nwin, auto &&fetchw) -> bool {
             constexpr int S = D + 1;
             int key[S];
-            double bv[S], a[S];
+            V bv[S], a[S];
             bool ok[S];
 #pragma unroll
             for (int d = 0; d < S; ++d) fetchw(wv + (int64_t)nwaves * d, key[d], bv[d], a[d], ok[d]);
@@ -393,12 +409,12 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
 
         if (grouped) {
             const int g = l >> lg, r = l & ((1 << lg) - 1);
-            auto fetch = [&](int64_t w, int &key, double &bv, double &a, bool &ok) {
+            auto fetch = [&](int64_t w, int &key, V &bv, V &a, bool &ok) {
                 const int e = (int)w * per + g;
                 const int src = e < 64 ? e : 63;
                 const int64_t eb0 = bpermute64(b0, src);
                 const int elen = bpermute(len, src);
-                if constexpr (NUMERIC) a = __longlong_as_double(bpermute64(__double_as_longlong(av), src));
+                if constexpr (NUMERIC) a = bpermute_v(av, src);
                 ok = e < nent && r < elen;
                 // every lane loads (index 0 when it holds no product): no
                 // divergent branch around the loads, so that the wait before
@@ -407,8 +423,8 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                 const int kv = bcol[ix];
                 key = ok ? kv : -1;
                 if constexpr (NUMERIC) {
-                    const double bw = bval[ix];
-                    bv = ok ? bw : 0.0;
+                    const V bw = bval[ix];
+                    bv = ok ? bw : V(0);
                 }
             };
             int64_t w = wv;
@@ -418,7 +434,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                 continue;
             }
             int key, key1;
-            double bv = 0.0, bv1 = 0.0, a = 0.0, a1v = 0.0;
+            V bv = 0, bv1 = 0, a = 0, a1v = 0;
             bool ok, ok1;
             fetch(w, key, bv, a, ok);
             while (true) {
@@ -439,12 +455,12 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             const int64_t off = incl - len;
             const int64_t base = b0 - off;
             const bool starts = len > 0;
-            auto fetch = [&](int64_t w0, int &key, double &bv, double &a, bool &ok) {
+            auto fetch = [&](int64_t w0, int &key, V &bv, V &a, bool &ok) {
                 const unsigned long long cov = __ballot(starts && off <= w0);
                 int s = 63 - __clzll((long long)cov);
                 int64_t cb = readlane64(base, s);
-                double ca = 0.0;
-                if constexpr (NUMERIC) ca = readlane_f64(av, s);
+                V ca = 0;
+                if constexpr (NUMERIC) ca = readlane_v(av, s);
                 unsigned long long in = __ballot(starts && off > w0 && off < w0 + 64);
                 const int64_t p = w0 + l;
                 while (in) {
@@ -453,7 +469,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                     const int64_t os = readlane64(off, s);
                     if (p >= os) {
                         cb = readlane64(base, s);
-                        if constexpr (NUMERIC) ca = readlane_f64(av, s);
+                        if constexpr (NUMERIC) ca = readlane_v(av, s);
                     }
                 }
                 ok = p < total;
@@ -461,8 +477,8 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                 const int kv = bcol[ix];
                 key = ok ? kv : -1;
                 if constexpr (NUMERIC) {
-                    const double bw = bval[ix];
-                    bv = ok ? bw : 0.0;
+                    const V bw = bval[ix];
+                    bv = ok ? bw : V(0);
                 }
                 a = ca;
             };
@@ -470,14 +486,14 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             int64_t w0 = (int64_t)wv * 64;
             if (w0 >= total) continue;
             if constexpr (D > 1) {
-                auto fetch_w = [&](int64_t w, int &key, double &bv, double &a, bool &ok) {
+                auto fetch_w = [&](int64_t w, int &key, V &bv, V &a, bool &ok) {
                     fetch(w * 64, key, bv, a, ok);
                 };
                 if (pipelined(win_flat, fetch_w)) break;
                 continue;
             }
             int key, key1;
-            double bv = 0.0, bv1 = 0.0, a = 0.0, a1v = 0.0;
+            V bv = 0, bv1 = 0, a = 0, a1v = 0;
             bool ok, ok1;
             fetch(w0, key, bv, a, ok);
             while (true) {

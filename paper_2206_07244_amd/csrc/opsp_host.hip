@@ -45,6 +45,7 @@ struct opsp_plan {
     int64_t fixed_grid = 0;             // > 0: every bin kernel runs persistently with this grid
     int streams = 1;                    // streams the numeric bin kernels are spread over
     int gv = 0;                         // bin 0 variant (lanes per row, table size)
+    bool fp32 = false;                  // FP32 values (opsp_spgemm_f32)
     Counters *ctr = nullptr;            // device counters (numeric step), owned
     int2 *range = nullptr;              // output column range (lo, hi) per row (owned)
     opsp_stats stats = {};
@@ -570,6 +571,8 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     NumArgs na;
     memset(&na, 0, sizeof(na));
     na.gv = plan->gv;
+    na.fp32 = plan->fp32 ? 1 : 0;
+    const size_t vsize = plan->fp32 ? sizeof(float) : sizeof(double);
     na.A = dev_of(A);
     na.B = dev_of(B);
     na.crpt = plan->crpt;
@@ -605,7 +608,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
                 pv = scr->p + align256(cap * grid * (int64_t)sizeof(int));
             } else {
                 CHK(ar.alloc(&pk, sizeof(int) * (size_t)(cap * grid)));
-                CHK(ar.alloc(&pv, sizeof(double) * (size_t)(cap * grid)));
+                CHK(ar.alloc(&pv, vsize * (size_t)(cap * grid)));
             }
             na.slab_keys = (int *)pk;
             na.slab_vals = (double *)pv;
@@ -628,7 +631,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
                 pv = scr->p + align256(entries * grid * (int64_t)sizeof(int));
             } else {
                 CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
-                CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));
+                CHK(ar.alloc(&pv, vsize * (size_t)(entries * grid)));
             }
             na.slab_keys = (int *)pk;
             na.slab_vals = (double *)pv;
@@ -688,8 +691,13 @@ const char *opsp_status_string(opsp_status s) {
     return "unknown opsp status";
 }
 
-opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
-                           const opsp_config *config, opsp_stats *stats, void *stream) {
+}  // extern "C"
+
+namespace {
+// The whole two-phase product; values are FP64, or FP32 when `fp32` (the
+// val pointers of A, B and C then point to float).
+opsp_status two_phase(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const opsp_config *config,
+                      opsp_stats *stats, void *stream, bool fp32) {
     if (!C) return OPSP_ERR_INVALID;
     memset(C, 0, sizeof(*C));
     opsp_status st = check_inputs(A, B);
@@ -698,6 +706,7 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
     if (st != OPSP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     opsp_plan plan;
+    plan.fp32 = fp32;
     Timer tm(config && config->stage_timing, s);
     st = run_symbolic(A, B, config, s, &plan, tm);
     if (st != OPSP_OK) {
@@ -707,7 +716,7 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
     void *pc = nullptr, *pv = nullptr;
     if (plan.nnzC > 0) {
         hipError_t e = cache_alloc(&pc, sizeof(int32_t) * (size_t)plan.nnzC, s);
-        if (e == hipSuccess) e = cache_alloc(&pv, sizeof(double) * (size_t)plan.nnzC, s);
+        if (e == hipSuccess) e = cache_alloc(&pv, (fp32 ? sizeof(float) : sizeof(double)) * (size_t)plan.nnzC, s);
         if (e != hipSuccess) {
             if (pc) (void)cache_free(pc, s);
             plan_release(&plan, s);
@@ -746,6 +755,49 @@ opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
     }
     plan_release(&plan, s);
     return OPSP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+opsp_status opsp_spgemm_ex(const opsp_csr *A, const opsp_csr *B, opsp_csr *C,
+                           const opsp_config *config, opsp_stats *stats, void *stream) {
+    return two_phase(A, B, C, config, stats, stream, false);
+}
+
+// The FP32 structs differ from opsp_csr only in the element type of val.
+static_assert(sizeof(opsp_csr_f32) == sizeof(opsp_csr), "layouts");
+
+opsp_status opsp_spgemm_f32(const opsp_csr_f32 *A, const opsp_csr_f32 *B, opsp_csr_f32 *C,
+                            const opsp_config *config, opsp_stats *stats, void *stream) {
+    if (!C) return OPSP_ERR_INVALID;
+    opsp_csr a, b, c;
+    memset(&c, 0, sizeof(c));
+    const opsp_csr *pa = nullptr, *pb = nullptr;
+    if (A) {
+        a = opsp_csr{A->rows, A->cols, A->nnz, A->rpt, A->col, (double *)(void *)A->val};
+        pa = &a;
+    }
+    if (B) {
+        b = opsp_csr{B->rows, B->cols, B->nnz, B->rpt, B->col, (double *)(void *)B->val};
+        pb = &b;
+    }
+    const opsp_status st = two_phase(pa, pb, &c, config, stats, stream, true);
+    C->rows = c.rows;
+    C->cols = c.cols;
+    C->nnz = c.nnz;
+    C->rpt = c.rpt;
+    C->col = c.col;
+    C->val = (float *)(void *)c.val;
+    return st;
+}
+
+opsp_status opsp_csr_f32_free(opsp_csr_f32 *C, void *stream) {
+    if (!C) return OPSP_ERR_INVALID;
+    opsp_csr c{C->rows, C->cols, C->nnz, C->rpt, C->col, (double *)(void *)C->val};
+    const opsp_status st = opsp_csr_free(&c, stream);
+    memset(C, 0, sizeof(*C));
+    return st;
 }
 
 opsp_status opsp_spgemm(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, void *stream) {

@@ -24,7 +24,7 @@ struct DevCSR {
     int64_t rows, cols;
     const int64_t *rpt;
     const int32_t *col;
-    const double *val;
+    const void *val;         // double, or float for the FP32 product
 };
 
 // ---- binning / setup / scan (kernels_bin.hip) -----------------------------
@@ -121,11 +121,11 @@ struct NumArgs {
     DevCSR A, B;
     const int64_t *crpt;     // C row pointer (exclusive offsets, crpt[M] = nnz)
     int32_t *ccol;
-    double *cval;
+    void *cval;              // double, or float when fp32
     RowSrc src;              // rows of the bin
     Counters *ctr;           // error counter
     int *slab_keys;          // global tables (bin 7)
-    double *slab_vals;
+    void *slab_vals;         // value type of the product
     int64_t slab_entries;
     int64_t grid;
     Learn lrn;               // one-phase step (lrn.mode > 0); crpt unused then
@@ -133,6 +133,7 @@ struct NumArgs {
                              // with a narrow range accumulate densely (bins 1-6)
     int gv;                  // bin 0 variant (GROUP_GL / NUM_T0); the one-phase
                              // step uses variant 0
+    int fp32;                // values are float (A, B, C and the tables); two-phase only
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 // Bin 7 by bucketed dense accumulation (rows with a column range in `rng`;
