@@ -231,6 +231,44 @@ def measure_plain(ops, torch, np, syn, name, steps, warmup, dev, tuned_cls=True,
     return res
 
 
+def time_fp32(ops, torch, np, syn, name, steps, warmup, dev, tuned_cls=True):
+    """The same product with FP32 values (opsp_spgemm_f32, inputs rounded to
+    float32), timed like the FP64 legs."""
+    import ctypes
+    from paper_2206_07244_amd import autotune
+    desc, builder = syn.WORKLOADS[name]
+    A = builder()
+    dA = ops.DeviceCSR.from_host(A, dev, dtype=np.float32)
+    torch.cuda.synchronize()
+    sh = torch.cuda.current_stream().cuda_stream
+    Ac = dA._c_fast(A.nnz)
+    L = ops.lib()
+    tuned = autotune.load_config(workload_class(name)) if tuned_cls else None
+    tref = ctypes.byref(tuned) if tuned is not None else None
+    st = ops.Stats()
+
+    def once(stats=None):
+        Cc = ops.opsp_csr()
+        code = L.opsp_spgemm_f32(ctypes.byref(Ac), ctypes.byref(Ac), ctypes.byref(Cc), tref,
+                                 ctypes.byref(stats) if stats is not None else None, sh)
+        if code:
+            raise ops.OpspError(code, "opsp_spgemm_f32")
+        L.opsp_csr_f32_free(ctypes.byref(Cc), sh)
+    once(st)
+    for _ in range(warmup):
+        once()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / steps
+    g = 2.0 * st.nprod / (ms * 1e-3) / 1e9
+    log(f"fp32 {name}: {ms:.3f} ms/step, {g:.1f} GFLOPS")
+    return {"workload": name, "dtype": "f32", "value": round(g, 3), "unit": "GFLOPS",
+            "ms_per_step": round(ms, 4), "nprod": st.nprod, "nnzC": st.nnz}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -292,7 +330,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--mode", default="plain",
-                    choices=["plain", "batched", "learned", "copy", "ablation"],
+                    choices=["plain", "batched", "learned", "copy", "ablation", "lds"],
                     help="plain: the headline product; batched: 512 uneven products as one "
                          "batch vs 512 plain calls; learned: one-phase product with the trained "
                          "predictor vs the plain two-phase product and the upper-bound rule")
@@ -300,6 +338,8 @@ def main():
     ap.add_argument("--workloads", default="st27_100,bst27_40,band21,rmat20",
                     help="ablation mode: workloads of the tables")
     ap.add_argument("--out", default="", help="ablation mode: also write the tables (markdown) here")
+    ap.add_argument("--fp32", default="st27_100",
+                    help="plain mode: workload also timed with FP32 values ('' = none)")
     ap.add_argument("--panel", default="", help="learned mode: 'k/P' = the k-th of P row panels "
                                                  "of equal n_prod (for products beyond HBM)")
     ap.add_argument("--no-learned", action="store_true",
@@ -336,6 +376,8 @@ def main():
         return bench_copy(args, dev)
     if args.mode == "ablation":
         return bench_ablation(args, dev)
+    if args.mode == "lds":
+        return bench_lds(args, dev)
 
     r = measure_plain(ops, torch, np, syn, args.workload, args.steps, args.warmup, dev,
                       tuned_cls=not args.no_tuning)
@@ -414,6 +456,11 @@ def main():
                                               zip(["setup_bin", "symbolic", "numbin_scan_alloc",
                                                    "numeric", "total"], r2["stage"][:5])}})
         del r2
+
+    if args.fp32:
+        release()
+        out["fp32"] = time_fp32(ops, torch, np, syn, args.fp32, args.steps, args.warmup, dev,
+                                tuned_cls=not args.no_tuning)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, np, args.cpu_seconds)
@@ -537,6 +584,36 @@ def ablation_markdown(res) -> str:
                      f"{b['total_ms']:.3f} | {100 * b['binning_share']:.2f} % | "
                      f"{100 * b['setup_and_binning_share']:.2f} % |")
     return "\n".join(L) + "\n"
+
+
+def bench_lds(args, dev):
+    """Rate of the LDS atomics the hash and dense kernels issue (the second
+    ceiling beside HBM): lane operations per CU per clock at the 2.4 GHz
+    peak engine clock, for ds_add_f64, ds_cmpst_rtn_b32, ds_or_b32 and ds_add_f32 with
+    lane-consecutive and pseudo-random addresses in a 64 KB table, 512-thread
+    workgroups, two per CU (microbench/lds_atomics.hip)."""
+    import ctypes
+    import torch
+    from paper_2206_07244_amd import _build
+    L = ctypes.CDLL(_build.MICROBENCH_LIB)
+    L.opsp_mb_lds_atomics.restype = ctypes.c_int
+    L.opsp_mb_lds_atomics.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_float)]
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    grid, iters, reps = cus * 8, 4096, 5
+    res = {}
+    for kind, kname in enumerate(["ds_add_f64", "ds_cmpst_rtn_b32", "ds_or_b32", "ds_add_f32"]):
+        for pattern, pname in enumerate(["consecutive", "random"]):
+            ms = ctypes.c_float()
+            code = L.opsp_mb_lds_atomics(kind, pattern, grid, iters, reps, ctypes.byref(ms))
+            if code:
+                raise RuntimeError(f"microbenchmark failed: hipError {code}")
+            ops_ = grid * 512 * iters
+            rate = ops_ / (ms.value * 1e-3) / (2.4e9 * cus)
+            res[f"{kname}/{pname}"] = {"ms": round(ms.value, 4), "lane_ops_per_cu_per_clock": round(rate, 3),
+                                       "G_lane_ops_per_s": round(ops_ / (ms.value * 1e-3) / 1e9, 1)}
+            log(f"{kname} {pname}: {ms.value:.3f} ms, {rate:.2f} lane ops per CU per clock")
+    print(json.dumps({"mode": "lds", "cus": cus, "grid": grid, "threads": 512, "iters": iters,
+                      "results": res}), flush=True)
 
 
 def bench_copy(args, dev):

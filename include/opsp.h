@@ -233,10 +233,10 @@ opsp_status opsp_csr_free(opsp_csr *C, void *stream);
  * The same product with single-precision values (the paper evaluates FP64
  * only, Section 6.1; the method is the same for any value type): a CSR
  * matrix whose val is float[nnz], otherwise laid out as opsp_csr.  Products
- * a_ik * b_kj are rounded to float and summed in float in an unspecified
- * order, so each value of C lies within about (number of its terms + 1)
- * units of float rounding of sum_k |a_ik b_kj| from the exact sum of the
- * float inputs; rows and columns are exact.  Structure, allocation,
+ * a_ik * b_kj are rounded to float, summed in double in an unspecified order
+ * and rounded to float once, so each value of C lies within (number of its
+ * terms + 1) units of float rounding of sum_k |a_ik b_kj| from the exact sum
+ * of the float inputs; rows and columns are exact.  Structure, allocation,
  * ownership, errors and the single host wait are those of opsp_spgemm_ex
  * (release C with opsp_csr_f32_free). */
 typedef struct {

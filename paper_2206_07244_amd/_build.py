@@ -61,6 +61,23 @@ def _compile(src: str, variant: str = "") -> str:
     return obj
 
 
+MICROBENCH_SRC = os.path.join(HERE, "microbench", "lds_atomics.hip")
+MICROBENCH_LIB = os.path.join(HERE, "libopsp_microbench.so")
+
+
+def build_microbench(verbose: bool = False) -> str:
+    """The LDS-atomics microbenchmark (not part of the library)."""
+    tmp = MICROBENCH_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *CFLAGS, "-shared", "-o", tmp, MICROBENCH_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {MICROBENCH_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, MICROBENCH_LIB)
+    if verbose:
+        print("built", MICROBENCH_LIB)
+    return MICROBENCH_LIB
+
+
 def build(verbose: bool = False, variants=("", "multi_access")) -> str:
     """Compile and link every library variant; returns the product library."""
     os.makedirs(OBJ, exist_ok=True)
@@ -77,6 +94,7 @@ def build(verbose: bool = False, variants=("", "multi_access")) -> str:
         os.replace(tmp, lib)
         if verbose:
             print("built", lib)
+    build_microbench(verbose)
     return LIB
 
 

@@ -23,6 +23,13 @@
 
 namespace opsp {
 
+// Value types.  The kernels read A and B and write C in the product's value
+// type V (double, or float for the FP32 product) and form each product
+// a_ik * b_kj in V, but their LDS tables and global tables always sum in
+// FP64: on gfx950 the LDS FP32 atomic add (ds_add_f32) runs at about 1/20 of
+// the rate of ds_add_f64 (0.33 against 7.5 lane operations per CU per clock,
+// measured), and an FP64 sum rounded once is the more accurate anyway.
+
 // Value pointers of the launch arguments in the product's value type.
 template <class V>
 struct VPtrs {
@@ -123,14 +130,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     Counters *__restrict__ ctr, Learn L) {
     constexpr int RPW = 256 / GL;
     constexpr int ITEMS = (T + GL - 1) / GL;
-    __shared__ V vals[RPW * T];
+    __shared__ double vals[RPW * T];   // sums in FP64 for either value type
     __shared__ int keys[RPW * T];
     __shared__ int ck[RPW * T];
     __shared__ int s_full[RPW];   // one-phase: the row's table filled up
     src.resolve();
     const int slot = threadIdx.x / GL, g = threadIdx.x % GL;
     int *tk = keys + slot * T;
-    V *tv = vals + slot * T;
+    double *tv = vals + slot * T;
     int *pk = ck + slot * T;
     for (int64_t b0 = (int64_t)blockIdx.x * RPW; b0 < src.nrows; b0 += (int64_t)gridDim.x * RPW) {
         const int64_t idx = b0 + slot;
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                     }
 #pragma unroll
                     for (int u = 0; u < GRP_U; ++u) {
-                        if (q + u < b1 && !full && !num_insert_lds(tk, tv, T, kk[u], a * vv[u])) {
+                        if (q + u < b1 && !full && !num_insert_lds(tk, tv, T, kk[u], (double)(a * vv[u]))) {
                             if constexpr (LRN) {
                                 s_full[slot] = 1;
                                 full = true;
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     // keys, so the table never holds more than THR + W <= T keys.
     constexpr int THR = (4 * T) / 5 < T - W ? (4 * T) / 5 : T - W;
     static_assert(THR > 0, "table too small for the one-phase bound");
-    __shared__ V vals[R * T];
+    __shared__ double vals[R * T];   // sums in FP64 for either value type
     __shared__ int keys[R * T];
     __shared__ int red[3 * NW];
     __shared__ int s_cnt[R];
@@ -381,7 +388,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / W), t = threadIdx.x % W;
     const int wv = t >> 6;
     int *tk = keys + team * T;
-    V *tv = vals + team * T;
+    double *tv = vals + team * T;
     // one team per row (grids are sized from the numeric bin counts, which
     // are always read back before this step); every lane of the team makes
     // the same early returns
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 const uint32_t o = (uint32_t)(key - lo);
                 if (ok && o < (uint32_t)dspan) {
                     atomicOr(&bits[o >> 5], 1u << (o & 31));
-                    atomicAdd(&tv[o], v);
+                    atomicAdd(&tv[o], (double)v);
                 }
             };
             row_products<true, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, acc,
@@ -491,8 +498,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     int wcnt = 0;
     if (active) {
         auto ins = [&](bool ok, int key, V v) {
-            const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, v, &ctr->error,
-                                           [](V *p, V x) { atomicAdd(p, x); });
+            const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, (double)v, &ctr->error,
+                                           [](double *p, double x) { atomicAdd(p, x); });
             if constexpr (LRN) {
                 const int nm = (int)__popcll(__ballot(nw));
                 if constexpr (WT) wcnt += nm;
@@ -693,7 +700,7 @@ __global__ __launch_bounds__(1024) void k_num_global(
     const V *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const V *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
-    int *slab_keys, V *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr, Learn L) {
+    int *slab_keys, double *slab_vals, int64_t slab_entries, Counters *__restrict__ ctr, Learn L) {
     constexpr int CW = NUM_GLOBAL_CHUNK_WORDS;
     constexpr int CBITS = CW * 32;
     constexpr int WPT = CW / 1024;  // bitmap words per thread
@@ -706,7 +713,7 @@ __global__ __launch_bounds__(1024) void k_num_global(
 
     src.resolve();
     int *tk = slab_keys + (int64_t)blockIdx.x * slab_entries;
-    V *tv = slab_vals + (int64_t)blockIdx.x * slab_entries;
+    double *tv = slab_vals + (int64_t)blockIdx.x * slab_entries;
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
 
     for (int64_t r = blockIdx.x; r < src.nrows; r += gridDim.x) {
@@ -745,8 +752,8 @@ __global__ __launch_bounds__(1024) void k_num_global(
                 kmin = key < kmin ? key : kmin;
                 kmax = key > kmax ? key : kmax;
             }
-            const int nw = num_insert_wave(tk, tv, T, ok, key, v, &ctr->error,
-                                           [](V *p, V x) { unsafeAtomicAdd(p, x); });
+            const int nw = num_insert_wave(tk, tv, T, ok, key, (double)v, &ctr->error,
+                                           [](double *p, double x) { unsafeAtomicAdd(p, x); });
             if constexpr (LRN) {
                 const unsigned nm = (unsigned)__popcll(__ballot(nw));
                 if (nm && l == 0) atomicAdd(&s_cnt, nm);
@@ -875,7 +882,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
     // dense accumulator of one chunk; while the products are counted and
     // scattered (before any chunk is accumulated) its first BK_NB / 2 words
     // hold the chunk counters
-    __shared__ V dense[BK_CW];
+    __shared__ double dense[BK_CW];   // sums in FP64 for either value type
     __shared__ unsigned int bits[BK_CW / 32];
     __shared__ unsigned int off[BK_NB + 1];
     __shared__ unsigned short ord[BK_ORD];   // chunk column of each rank in the current round
@@ -1004,7 +1011,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         // reads below (plain loads, so that several are in flight per thread)
         __threadfence();
         __syncthreads();
-        for (int i = t; i < BK_NB * 4 / (int)sizeof(V); i += BK_T) dense[i] = V(0);
+        for (int i = t; i < BK_NB / 2; i += BK_T) dense[i] = 0.0;
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if constexpr (LRN) {
@@ -1080,7 +1087,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                 for (int u = 0; u < BK_U; ++u) {
                     if (kk[u] < 0) continue;
                     const uint32_t o = (uint32_t)(kk[u] - c0);
-                    atomicAdd(&dense[bk_swz(o)], vv[u]);
+                    atomicAdd(&dense[bk_swz(o)], (double)vv[u]);
                     atomicOr(&bits[o >> 5], 1u << (o & 31));
                 }
             };
@@ -1130,12 +1137,12 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                 for (unsigned int k = t; k < cnt; k += BK_T) {
                     const uint32_t o = ord[k];
                     const uint32_t q = bk_swz(o);
-                    const V v = dense[q];
+                    const V v = (V)dense[q];
                     dense[q] = 0.0;
                     const int64_t kr = run + r0 + k;
-                    if (kr < n) {
-                        ccol[base + kr] = c0 + (int)o;
-                        cval[base + kr] = v;
+                    if (kr < n) {   // C is not read again here: keep it out of the caches
+                        __builtin_nontemporal_store(c0 + (int)o, &ccol[base + kr]);
+                        __builtin_nontemporal_store(v, &cval[base + kr]);
                     }
                 }
                 __syncthreads();
@@ -1320,11 +1327,11 @@ static hipError_t go_global(const NumArgs &a, hipStream_t s) {
     if (a.lrn.mode > 0)
         hipLaunchKernelGGL((k_num_global<true, V>), dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
                            a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval,
-                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+                           a.slab_keys, (double *)a.slab_vals, a.slab_entries, a.ctr, a.lrn);
     else
         hipLaunchKernelGGL((k_num_global<false, V>), dim3((unsigned)a.grid), dim3(1024), 0, s, a.src,
                            a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval,
-                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+                           a.slab_keys, (double *)a.slab_vals, a.slab_entries, a.ctr, a.lrn);
     return hipGetLastError();
 }
 

@@ -631,7 +631,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
                 pv = scr->p + align256(entries * grid * (int64_t)sizeof(int));
             } else {
                 CHK(ar.alloc(&pk, sizeof(int) * (size_t)(entries * grid)));
-                CHK(ar.alloc(&pv, vsize * (size_t)(entries * grid)));
+                CHK(ar.alloc(&pv, sizeof(double) * (size_t)(entries * grid)));   // FP64 sums
             }
             na.slab_keys = (int *)pk;
             na.slab_vals = (double *)pv;

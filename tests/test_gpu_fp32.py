@@ -2,10 +2,11 @@
 
 The inputs are rounded to float32 first; the oracle multiplies those values
 exactly representable in FP64.  The GPU rounds every product a_ik b_kj to
-float32 and sums the terms of an entry in float32 in any order, so with
-u = 2^-24 each entry obeys |c - c_ref| <= (k_ij + 1) u S_ij, where k_ij is
-its number of terms and S_ij = sum |a_ik b_kj| (standard bound for a sum of
-k rounded terms; c_ref is exact to 1e-16 S).  k_ij <= a_len_i, the length of
+float32, sums the terms of an entry in FP64 in any order and rounds the sum
+to float32, so with u = 2^-24 each entry obeys |c - c_ref| <= (k_ij + 1) u
+S_ij, where k_ij is its number of terms and S_ij = sum |a_ik b_kj| (the
+bound for a float32 sum of k rounded terms, which the FP64 sum only
+tightens; c_ref is exact to 1e-16 S).  k_ij <= a_len_i, the length of
 row i of A, which the tests use.  Rows and columns must be identical to the
 oracle's; integer inputs below 2^24 in magnitude are exact in float32 and
 must match bit for bit.

@@ -103,6 +103,30 @@ def test_block_stencil27_40_full():
     assert info["max_err_over_S"] < 1e-14
 
 
+def test_stencil27_100_fp32_full():
+    """The 27-point stencil 100^3 squared with FP32 values: structure exact,
+    every value within (k + 1) 2^-24 S of the FP64 oracle on the rounded
+    inputs (see test_gpu_fp32)."""
+    import torch
+    import paper_2206_07244_amd as ops
+    g = 100
+    A = syn.stencil27(g, seed=27)
+    A = syn.CSR(A.rows, A.cols, A.rpt, A.col, A.val.astype(np.float32).astype(np.float64))
+    dA = ops.DeviceCSR.from_host(A, dtype=np.float32)
+    st = ops.Stats()
+    C = ops.spgemm_f32(dA, dA, config=_tuned("stencil"), stats=st)
+    torch.cuda.synchronize()
+    assert st.nnz == (5 * g - 6) ** 3
+    rpt, col, val = C.to_host()
+    del C
+    rrpt, rcol, rval, rabs = oracle.spgemm(A, A, threads=_threads())
+    assert np.array_equal(rpt, rrpt) and np.array_equal(col, rcol)
+    k = np.repeat(np.diff(A.rpt), np.diff(rrpt)).astype(np.float64)
+    err = np.abs(val.astype(np.float64) - rval)
+    assert np.all(err <= (k + 1.0) * 2.0 ** -24 * rabs)
+    _say("st27_100 fp32 max |d|/S", float(np.max(err / np.maximum(rabs, 1e-300))))
+
+
 def _full_rpt_and_bins(ops, A, rows_abs, C, cfg, tag, extra_rows=()):
     """Whole row pointer of C (rows `rows_abs` of A) against the oracle's
     symbolic counts, then >= 32 rows of every bin compared entry by entry."""
