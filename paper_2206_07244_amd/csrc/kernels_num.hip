@@ -877,7 +877,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
     const V *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const V *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
-    const int2 *__restrict__ rng, int *stage_keys, V *stage_vals, int64_t stage_cap,
+    const int2 *__restrict__ rng, unsigned short *stage_keys, V *stage_vals, int64_t stage_cap,
     Counters *__restrict__ ctr, Learn L) {
     // dense accumulator of one chunk; while the products are counted and
     // scattered (before any chunk is accumulated) its first BK_NB / 2 words
@@ -893,7 +893,8 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
     src.resolve();
     const int t = threadIdx.x, wv = t >> 6, l = t & 63;
     unsigned int *cc = reinterpret_cast<unsigned int *>(dense);
-    int *sk = stage_keys + (int64_t)blockIdx.x * stage_cap;
+    // a staged product is its column's offset in its chunk (2 bytes) and its value
+    unsigned short *sk = stage_keys + (int64_t)blockIdx.x * stage_cap;
     V *sv = stage_vals + (int64_t)blockIdx.x * stage_cap;
     for (int i = t; i < BK_CW; i += BK_T) dense[i] = 0.0;
     for (int i = t; i < BK_CW / 32; i += BK_T) bits[i] = 0u;
@@ -1002,7 +1003,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                                        b = (unsigned int)__builtin_amdgcn_ds_bpermute(h << 2, (int)b);
                                        const unsigned int p = in ? b + (unsigned int)(l - h)
                                                                  : (unsigned int)(stage_cap - 1);
-                                       sk[p] = key;
+                                       sk[p] = (unsigned short)(o & (BK_CW - 1));
                                        sv[p] = v;
                                    },
                                    [] { return false; });
@@ -1027,12 +1028,12 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
 #pragma unroll
                     for (int u = 0; u < BK_U; ++u) {
                         const unsigned int q = p + (unsigned int)BK_T * u;
-                        kk[u] = q < p1 ? sk[q] : -1;
+                        kk[u] = q < p1 ? (int)sk[q] : -1;
                     }
 #pragma unroll
                     for (int u = 0; u < BK_U; ++u) {
                         if (kk[u] < 0) continue;
-                        const uint32_t o = (uint32_t)(kk[u] - c0);
+                        const uint32_t o = (uint32_t)kk[u];
                         atomicOr(&bits[o >> 5], 1u << (o & 31));
                     }
                 }
@@ -1071,7 +1072,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
 #pragma unroll
             for (int u = 0; u < BK_U; ++u) {
                 const unsigned int q = q0 + t + (unsigned int)BK_T * u;
-                kk[u] = q < q1 ? sk[q] : -1;
+                kk[u] = q < q1 ? (int)sk[q] : -1;
                 vv[u] = q < q1 ? sv[q] : 0.0;
             }
         };
@@ -1086,7 +1087,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
 #pragma unroll
                 for (int u = 0; u < BK_U; ++u) {
                     if (kk[u] < 0) continue;
-                    const uint32_t o = (uint32_t)(kk[u] - c0);
+                    const uint32_t o = (uint32_t)kk[u];
                     atomicAdd(&dense[bk_swz(o)], (double)vv[u]);
                     atomicOr(&bits[o >> 5], 1u << (o & 31));
                 }
@@ -1096,7 +1097,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
 #pragma unroll
                 for (int u = 0; u < BK_U; ++u) {
                     const unsigned int q = p + t + (unsigned int)BK_T * u;
-                    kk[u] = q < p1 ? sk[q] : -1;
+                    kk[u] = q < p1 ? (int)sk[q] : -1;
                     vv[u] = q < p1 ? sv[q] : 0.0;
                 }
                 accumulate();
@@ -1163,11 +1164,11 @@ static hipError_t go_bucket(const NumArgs &a, hipStream_t s) {
     if (a.lrn.mode > 0)
         hipLaunchKernelGGL((k_num_bucket<true, V>), dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
                            a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval, a.rng,
-                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+                           (unsigned short *)a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
     else
         hipLaunchKernelGGL((k_num_bucket<false, V>), dim3((unsigned)a.grid), dim3(BK_T), 0, s, a.src, a.A.rpt,
                            a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol, v.cval, a.rng,
-                           a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
+                           (unsigned short *)a.slab_keys, v.slab_vals, a.slab_entries, a.ctr, a.lrn);
     return hipGetLastError();
 }
 
