@@ -164,7 +164,9 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
         if (f_bmax) f_bmax[i] = (int32_t)bmx[w][l];
         if (range) rng[i] = make_int2(clo[w][l], chi[w][l]);
     }
-    const int b = valid ? bin_of((int64_t)v, bd) : -1;
+    const int b = valid ? (range ? bin_of_row((int64_t)v, bd, make_int2(clo[w][l], chi[w][l]))
+                                 : bin_of((int64_t)v, bd))
+                        : -1;
     for (int j = 0; j < bd.nslots; ++j) {
         const unsigned long long m = __ballot(b == j);
         if (l == 0 && m) atomicAdd(&hist[j], (unsigned)__popcll(m));
@@ -337,7 +339,8 @@ template <bool SCAN>
 __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds bd,
                                                  const Counters *__restrict__ ctr,
                                                  int32_t *__restrict__ bins, BlockParts parts,
-                                                 int64_t *vout, int skip_full) {
+                                                 int64_t *vout, int skip_full,
+                                                 const int2 *__restrict__ rng) {
     __shared__ unsigned int wcnt[4][BIN_SLOTS];
     __shared__ unsigned long long base[BIN_SLOTS];
     __shared__ unsigned long long wsum[4];
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t M, int64_t *v, Bounds b
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = i < M;
     const int64_t x = valid ? v[i] : 0;
-    const int b = valid ? bin_of(x, bd) : -1;
+    const int b = valid ? (rng ? bin_of_row(x, bd, rng[i]) : bin_of(x, bd)) : -1;
     int rank = 0;
     if (bins) {
         for (int j = 0; j < bd.nslots; ++j) {
@@ -436,16 +439,16 @@ hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Count
 
 hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
                           int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
-                          int64_t *vout, bool device_identity) {
+                          int64_t *vout, bool device_identity, const int2 *rng) {
     if (M == 0) return hipSuccess;
     const int64_t grid = (M + 255) / 256;
     if (!vout) vout = v;
     if (scan)
         hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, parts, vout, 0);
+                           bins, parts, vout, 0, nullptr);
     else
         hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)grid), dim3(256), 0, s, M, v, bd, ctr,
-                           bins, parts, vout, device_identity ? 1 : 0);
+                           bins, parts, vout, device_identity ? 1 : 0, rng);
     return hipGetLastError();
 }
 

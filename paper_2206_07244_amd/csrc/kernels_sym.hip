@@ -141,8 +141,10 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                     while (32ll * nw < sp) nw <<= 1;
                     // the largest bin counts by bitmap whenever it fits (no
                     // abandoned rows); the others when the bitmap is small
-                    // against the row's products
-                    if ((ABORT ? nw <= 2 * np : 2 * nw <= np) || sp <= 0) {
+                    // against the row's products, and always for rows with
+                    // more products than the table has slots (routed here by
+                    // their range, bin_of_row)
+                    if ((ABORT ? nw <= 2 * np : (2 * nw <= np || np > T)) || sp <= 0) {
                         bm = true;
                         nwords = sp > 0 ? nw : 0;
                         span = sp > 0 ? (uint32_t)sp : 0u;

@@ -31,14 +31,29 @@ struct Bounds {
     int32_t nb;       // natural bins
     int32_t force;    // -1 = off
     int32_t nslots;   // histogram slots (>= nb, > force)
-    int32_t pad;
+    int32_t span_bin; // symbolic step: bin of rows routed by their column range (-1 = off)
     int64_t ub[16];
+    int64_t span_max;        // ... whose output column range is at most this wide
+    int64_t span_nprod_max;  // ... and whose n_prod is at most this
 };
 
 __device__ __forceinline__ int bin_of(int64_t v, const Bounds &b) {
     int j = 0;
     while (j < b.nb - 1 && v > b.ub[j]) ++j;
     if (b.force >= 0 && (b.force >= b.nb - 1 || v <= b.ub[b.force])) j = b.force;
+    return j;
+}
+
+// Symbolic bin of a row from its n_prod and output column range: a row whose
+// range is narrow enough for the one-wave kernel's bitmap is counted there
+// whatever its n_prod (up to a cap), instead of in a table sized for n_prod
+// distinct columns (rows of high compression ratio: thousands of products,
+// a few hundred outputs).  No effect without ranges or with a forced bin.
+__device__ __forceinline__ int bin_of_row(int64_t v, const Bounds &b, int2 rg) {
+    int j = bin_of(v, b);
+    if (b.span_bin >= 0 && b.force < 0 && j > b.span_bin && rg.y >= rg.x &&
+        (int64_t)rg.y - rg.x + 1 <= b.span_max && v <= b.span_nprod_max)
+        j = b.span_bin;
     return j;
 }
 

@@ -261,8 +261,15 @@ int gv_of(const opsp_config *c) {
 Bounds make_bounds(int step, double ratio, int force, int gv) {
     Bounds b;
     memset(&b, 0, sizeof(b));
+    b.span_bin = -1;
     if (step == 0) {
         b.nb = SYM_NLDS;                    // bins 0..7 natural; 8 only by force
+        // rows whose output range fits the one-wave kernel's bitmap (32 bits
+        // per table word) go to bin 1 up to 2^13 products (one wave walks
+        // them in at most 128 windows of 64)
+        b.span_bin = 1;
+        b.span_max = 32ll * SYM_T[1];
+        b.span_nprod_max = 1ll << 13;
         for (int j = 0; j < SYM_NLDS - 1; ++j) b.ub[j] = bound_for(0, j ? SYM_T[j] : SYM_T0[gv], ratio);
         b.nslots = SYM_NLDS + 1;
     } else {
@@ -427,7 +434,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 
     // 2 second pass; the all-rows-in-one-bin case (Alg. 3) is decided on the
     //   device: no list is written and the bin kernel reads rows in order
-    CHK(launch_scatter(M, crpt, bs, ctrS, bins, parts, false, s, nullptr, true));
+    CHK(launch_scatter(M, crpt, bs, ctrS, bins, parts, false, s, nullptr, true, rng));
     tm.mark();
 
     // 3 symbolic, biggest bins first.  The bin sizes stay on the device:

@@ -61,10 +61,13 @@ hipError_t launch_finalize(int64_t M, int nslots, const BlockParts &parts, Count
 // bins are needed); with `scan`, also write the exclusive offsets of v[] to
 // vout[] (NULL = in place).  With `device_identity` (no scan), nothing is
 // written when one bin holds every row: readers given RowSrc::all take the
-// rows in order then.
+// rows in order then.  `rng` (symbolic step, no scan): the rows' output
+// column ranges, for the range rule of bin_of_row (the setup kernel must
+// have binned with the same ranges).
 hipError_t launch_scatter(int64_t M, int64_t *v, const Bounds &bd, const Counters *ctr,
                           int32_t *bins, const BlockParts &parts, bool scan, hipStream_t s,
-                          int64_t *vout = nullptr, bool device_identity = false);
+                          int64_t *vout = nullptr, bool device_identity = false,
+                          const int2 *rng = nullptr);
 
 // ---- input check of the validation mode (kernels_check.hip) ----------------
 // Sets bits of *flags (zeroed before): 1 = rpt not monotone, rpt[0] < 0 or

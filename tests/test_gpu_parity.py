@@ -390,3 +390,50 @@ def test_group_lanes_variants(lanes):
             if forced == 0 and i == 0:   # rows of about 12 products: all fit bin 0
                 assert st.sym_bin_rows[0] > 0 and st.num_bin_rows[0] > 0
 
+
+
+def _narrow_range_rows(widths, ms, L=64, G=1100, seed=21):
+    """A, B whose product rows have exactly the given column range widths and
+    numbers of products: B holds, per width w, G rows of L entries in
+    [base, base + w) that all include base and base + w - 1; A row (w, m)
+    references m distinct B rows of width w's group (m * L products, range
+    exactly w)."""
+    rng = np.random.default_rng(seed)
+    uw = sorted(set(widths))
+    n_cols = sum(uw) + 17
+    brpt, bcol, base, group = [0], [], 0, {}
+    for gi, w in enumerate(uw):
+        group[w] = gi * G
+        for _ in range(G):
+            mid = rng.choice(np.arange(1, w - 1), L - 2, replace=False)
+            bcol.append(np.sort(np.concatenate([[0, w - 1], mid])) + base)
+            brpt.append(brpt[-1] + L)
+        base += w
+    B = syn.CSR(len(uw) * G, n_cols, np.array(brpt, np.int64),
+                np.concatenate(bcol).astype(np.int32), rng.uniform(-1, 1, brpt[-1]))
+    arpt, acol = [0], []
+    for w, m in zip(widths, ms):
+        acol.append(np.sort(rng.choice(G, m, replace=False)) + group[w])
+        arpt.append(arpt[-1] + m)
+    A = syn.CSR(len(widths), B.rows, np.array(arpt, np.int64),
+                np.concatenate(acol).astype(np.int32), rng.uniform(-1, 1, arpt[-1]))
+    return A, B
+
+
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_symbolic_rows_routed_by_range(hash_all):
+    """Rows of thousands of products whose output range fits the one-wave
+    kernel's bitmap (32 * 1024 columns) are counted there up to 2^13
+    products; a column more, or a B row more, keeps them in the bin of their
+    n_prod.  Without ranges (every row hashed) nothing is routed."""
+    ops = _ops()
+    widths, ms, routed = [], [], 0
+    for w in (1000, 20000, 32768, 32769):
+        for m in (31, 128, 129, 1024):
+            widths.append(w)
+            ms.append(m)
+            routed += (w <= 32768 and m * 64 <= 8192)
+    A, B = _narrow_range_rows(widths, ms)
+    st = ops.Stats()
+    check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all), stats=st)
+    assert st.sym_bin_rows[1] == (0 if hash_all else routed)
