@@ -20,8 +20,15 @@ namespace opsp {
 // (Section 5.3 reuses C.rpt for n_prod), fused with the first symbolic
 // binning pass (Alg. 1).  Each wave owns 64 consecutive rows and walks the
 // flat range of their A entries with coalesced loads, so one long row does
-// not serialise a single lane.
+// not serialise a single lane.  Rows of more than SETUP_TILE entries are
+// listed instead, with their tiles, and left out of the block's record:
+// k_setup_long walks the tiles on many workgroups and k_setup_fin bins each
+// listed row into its block's record.
 // ---------------------------------------------------------------------------
+__global__ void k_setup_init(LongHead *lh) {
+    if (threadIdx.x == 0) lh->packed = 0;
+}
+
 __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restrict__ arpt,
                                                const int32_t *__restrict__ acol,
                                                const int64_t *__restrict__ brpt,
@@ -35,6 +42,7 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     __shared__ unsigned long long acc[4][64];
     __shared__ unsigned int bmx[4][64];
     __shared__ int clo[4][64], chi[4][64];
+    __shared__ int lng[4][64];   // row handed to k_setup_long
     __shared__ unsigned int hist[BIN_SLOTS];
     __shared__ unsigned long long s_tot, s_max;
 
@@ -60,6 +68,40 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     // entries, so that one long row does not serialise a single lane.
     const int64_t my_len = (nrows > 0 && l < nrows) ? rs[w][l + 1] - rs[w][l] : 0;
     const bool lane_rows = nrows > 0 && wave_max(my_len) <= 64;
+    {
+        // long rows go to the tile list: one reservation per wave (a 64-bit
+        // add of its rows and tiles).  If the list is full, which only an A
+        // whose rows span more entries than its nnz can cause, the wave walks
+        // those rows itself and blanks the slots it reserved.
+        const bool lr = my_len > SETUP_TILE;
+        const int n = lr ? (int)((my_len + SETUP_TILE - 1) / SETUP_TILE) : 0;
+        const unsigned long long m = __ballot(lr);
+        bool handed = false;
+        if (m) {   // uniform over the wave
+            const int incl = wave_incl_scan(n);
+            const int tot = __shfl(incl, 63);
+            const int nr = (int)__popcll(m), rk = mbcnt(m);
+            unsigned long long base = 0;
+            if (l == 0)
+                base = atomicAdd(&parts.lh->packed,
+                                 ((unsigned long long)nr << 32) | (unsigned long long)(unsigned)tot);
+            base = __shfl(base, 0);
+            const uint32_t s0 = (uint32_t)(base >> 32), i0 = (uint32_t)base;
+            const bool fits = (uint64_t)s0 + nr <= parts.cap_rows && (uint64_t)i0 + tot <= parts.cap_items;
+            const uint32_t slot = s0 + (uint32_t)rk, it0 = i0 + (uint32_t)(incl - n);
+            if (lr && fits) {
+                parts.lrows[slot] = LongRow{(int32_t)(r0 + l), n, (int32_t)it0, 0};
+                for (int j = 0; j < n; ++j) parts.litems[it0 + j] = make_int2((int)slot, j);
+                handed = true;
+            } else if (lr) {
+                if (slot < parts.cap_rows) parts.lrows[slot] = LongRow{-1, 0, 0, 0};
+                for (int j = 0; j < n; ++j)
+                    if (it0 + (uint32_t)j < parts.cap_items) parts.litems[it0 + j] = make_int2(-1, 0);
+            }
+        }
+        lng[w][l] = handed ? 1 : 0;
+    }
+    __syncthreads();
     if (lane_rows) {
         unsigned long long a = 0;
         unsigned int bm = 0;
@@ -97,8 +139,20 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
         // four entries per lane per step so that their gathers overlap; the
         // loop is uniform over the wave (lanes past the end hold no entry),
         // as the wave reductions below need every lane
-        for (int64_t eb0 = e0; eb0 < e1; eb0 += 256) {
+        for (int64_t eb0 = e0; eb0 < e1;) {
+            {   // jump over a row handed to the tiles (uniform)
+                int lo = 0, hi = nrows - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (rs[w][mid] <= eb0) lo = mid; else hi = mid - 1;
+                }
+                if (lng[w][lo]) {
+                    eb0 = rs[w][lo + 1];
+                    continue;
+                }
+            }
             const int64_t eb = eb0 + l;
+            eb0 += 256;
             int64_t len[4];
             int2 fl[4];
 #pragma unroll
@@ -116,13 +170,14 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t e = eb + 64 * u;
-                const bool ok = len[u] >= 0;
+                const bool ok0 = len[u] >= 0;
                 // largest r in [0, nrows) with rs[r] <= e (rows may be empty)
                 int lo = 0, hi = nrows - 1;
-                while (ok && lo < hi) {
+                while (ok0 && lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (rs[w][mid] <= e) lo = mid; else hi = mid - 1;
                 }
+                const bool ok = ok0 && !lng[w][lo];
                 const unsigned lc = ok ? (unsigned)(len[u] > 0xffffffffll ? 0xffffffffll : len[u]) : 0u;
                 const bool fr = range && ok && len[u] > 0;
                 // lanes hold consecutive entries, so lane 0 has the lowest
@@ -158,15 +213,18 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     const bool valid = l < nrows;
     const int64_t i = r0 + l;
     const unsigned long long v = valid ? acc[w][l] : 0ull;
+    // a handed row starts from n_prod 0, no range and b_max 0 here; the
+    // tiles add to them and bin it
     if (valid) {
         nprod[i] = (int64_t)v;
         if (f_alen) f_alen[i] = (int32_t)(rs[w][l + 1] - rs[w][l]);
         if (f_bmax) f_bmax[i] = (int32_t)bmx[w][l];
         if (range) rng[i] = make_int2(clo[w][l], chi[w][l]);
     }
-    const int b = valid ? (range ? bin_of_row((int64_t)v, bd, make_int2(clo[w][l], chi[w][l]))
-                                 : bin_of((int64_t)v, bd))
-                        : -1;
+    const int b = valid && !lng[w][l]
+                      ? (range ? bin_of_row((int64_t)v, bd, make_int2(clo[w][l], chi[w][l]))
+                               : bin_of((int64_t)v, bd))
+                      : -1;
     for (int j = 0; j < bd.nslots; ++j) {
         const unsigned long long m = __ballot(b == j);
         if (l == 0 && m) atomicAdd(&hist[j], (unsigned)__popcll(m));
@@ -181,6 +239,108 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     if (threadIdx.x == 0) {
         parts.tot[blockIdx.x] = s_tot;
         parts.mx[blockIdx.x] = s_max;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Long rows listed by k_setup.  k_setup_long: persistent waves over the
+// tiles, each tile's sum of B row lengths, largest B row and column range
+// into its slot.  k_setup_fin: one wave per long row combines its tiles,
+// writes the row's n_prod / b_max / range and counts the row in its 256-row
+// block's record (bin, total, maximum), as k_setup does for the other rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_setup_long(const int64_t *__restrict__ arpt,
+                                                    const int32_t *__restrict__ acol,
+                                                    const int64_t *__restrict__ brpt,
+                                                    BlockParts parts,
+                                                    const int4 *__restrict__ brec) {
+    constexpr int EPL = SETUP_TILE / 64;   // entries per lane, EPL / 4 rounds of four gathers
+    static_assert(EPL % 4 == 0, "whole rounds");
+    const int l = threadIdx.x & 63;
+    const bool range = brec != nullptr;
+    const uint32_t req = (uint32_t)parts.lh->packed;
+    const uint32_t nit = req < parts.cap_items ? req : parts.cap_items;
+    const uint32_t nw = gridDim.x * 4;
+    for (uint32_t it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nit; it += nw) {
+        const int2 item = parts.litems[it];
+        if (item.x < 0) continue;   // uniform over the wave
+        const int64_t row = parts.lrows[item.x].row;
+        const int64_t a0 = arpt[row] + (int64_t)item.y * SETUP_TILE;
+        const int64_t a1r = arpt[row + 1];
+        const int64_t a1 = a0 + SETUP_TILE < a1r ? a0 + SETUP_TILE : a1r;
+        unsigned long long sum = 0;
+        unsigned bm = 0;
+        int mn = INT_MAX, mx = -1;
+#pragma unroll
+        for (int q = 0; q < EPL; q += 4) {
+            int k[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t e = a0 + l + 64 * (q + u);
+                k[u] = e < a1 ? acol[e] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k[u] < 0) continue;
+                int64_t len;
+                if (range) {
+                    const int4 r = brec[k[u]];
+                    len = r.x;
+                    if (len > 0) {
+                        mn = r.y < mn ? r.y : mn;
+                        mx = r.z > mx ? r.z : mx;
+                    }
+                } else {
+                    len = brpt[k[u] + 1] - brpt[k[u]];
+                }
+                sum += (unsigned long long)len;
+                const unsigned lc = (unsigned)(len > 0xffffffffll ? 0xffffffffll : len);
+                bm = lc > bm ? lc : bm;
+            }
+        }
+        sum = wave_sum(sum);
+        bm = wave_max(bm);
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        if (l == 0) parts.lpart[it] = LongPart{sum, bm, mn, mx, 0};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_setup_fin(int64_t *__restrict__ nprod, Bounds bd,
+                                                   BlockParts parts, int32_t *__restrict__ f_bmax,
+                                                   int2 *__restrict__ rng) {
+    const int l = threadIdx.x & 63;
+    const uint32_t req = (uint32_t)(parts.lh->packed >> 32);
+    const uint32_t nr = req < parts.cap_rows ? req : parts.cap_rows;
+    const uint32_t nw = gridDim.x * 4;
+    for (uint32_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nr; r += nw) {
+        const LongRow lr = parts.lrows[r];
+        if (lr.row < 0) continue;   // uniform over the wave
+        unsigned long long sum = 0;
+        unsigned bm = 0;
+        int mn = INT_MAX, mx = -1;
+        for (int j = l; j < lr.ntiles; j += 64) {
+            const LongPart p = parts.lpart[lr.it0 + j];
+            sum += p.sum;
+            bm = p.bmax > bm ? p.bmax : bm;
+            mn = p.lo < mn ? p.lo : mn;
+            mx = p.hi > mx ? p.hi : mx;
+        }
+        sum = wave_sum(sum);
+        bm = wave_max(bm);
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        if (l == 0) {
+            const int64_t i = lr.row;
+            nprod[i] = (int64_t)sum;
+            if (f_bmax) f_bmax[i] = (int32_t)(bm > 0x7fffffffu ? 0x7fffffffu : bm);
+            if (rng) rng[i] = make_int2(mn, mx);
+            const int b = rng ? bin_of_row((int64_t)sum, bd, make_int2(mn, mx)) : bin_of((int64_t)sum, bd);
+            const int64_t blk = i >> 8;
+            atomicAdd(&parts.hist[blk * BIN_SLOTS + b], 1u);
+            atomicAdd(&parts.tot[blk], sum);
+            atomicMax(&parts.mx[blk], sum);
+        }
     }
 }
 
@@ -392,8 +552,14 @@ hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const 
                         const int4 *brec, int2 *rng) {
     if (A.rows == 0) return hipSuccess;
     const int64_t grid = (A.rows + 255) / 256;
+    hipLaunchKernelGGL(k_setup_init, dim3(1), dim3(64), 0, s, parts.lh);
     hipLaunchKernelGGL(k_setup, dim3((unsigned)grid), dim3(256), 0, s, A.rows, A.rpt, A.col, B.rpt,
                        nprod, bd, parts, f_alen, f_bmax, brec, brec ? rng : nullptr);
+    // long rows: fixed grids of two workgroups per CU of gfx950 (R-MAT
+    // scale 20 lists ~6,200 rows in ~17,600 tiles)
+    hipLaunchKernelGGL(k_setup_long, dim3(512), dim3(256), 0, s, A.rpt, A.col, B.rpt, parts, brec);
+    hipLaunchKernelGGL(k_setup_fin, dim3(512), dim3(256), 0, s, nprod, bd, parts, f_bmax,
+                       brec ? rng : nullptr);
     return hipGetLastError();
 }
 

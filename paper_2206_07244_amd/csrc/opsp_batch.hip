@@ -431,12 +431,9 @@ opsp_status opsp_batch_create(int32_t count, const opsp_csr *A, const opsp_csr *
     BA(b->ctr, Counters, 2);
     BA(b->d_bounds, int64_t, count + 1);
     {
-        hipError_t e_ = balloc(b, &p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) *
-                                          (size_t)(nblk > 0 ? nblk : 1), s);
+        hipError_t e_ = balloc(b, &p, block_parts_bytes(b->M, annz), s);
         if (e_ != hipSuccess) return fail(status_of_hip(e_));
-        b->parts.tot = (unsigned long long *)p;
-        b->parts.mx = b->parts.tot + nblk;
-        b->parts.hist = (unsigned int *)(b->parts.mx + nblk);
+        b->parts = block_parts_at(p, b->M, annz);
     }
     // symbolic global tables: a row reaches them only if it has more than
     // the abort threshold of distinct columns, i.e. if N_p > 0.8 * t7

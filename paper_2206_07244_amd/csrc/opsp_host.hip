@@ -413,11 +413,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
         CHK(ar.alloc(&p, sizeof(int4) * (size_t)(B->rows > 0 ? B->rows : 1)));
         bfl = (int4 *)p;
     }
-    CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
-    BlockParts parts;
-    parts.tot = (unsigned long long *)p;
-    parts.mx = parts.tot + nblk;
-    parts.hist = (unsigned int *)(parts.mx + nblk);
+    CHK(ar.alloc(&p, block_parts_bytes(M, A->nnz)));
+    const BlockParts parts = block_parts_at(p, M, A->nnz);
 
     const int gv = gv_of(cfg);
     plan->gv = gv;

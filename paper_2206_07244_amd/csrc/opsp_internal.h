@@ -31,18 +31,67 @@ struct DevCSR {
 // Histogram slots per 256-row block (>= the bins of either step).
 constexpr int BIN_SLOTS = 16;
 
-// Per-block records of the first binning pass (256 rows per block).
+// Rows of more than SETUP_TILE entries of A are walked by the setup step in
+// tiles of SETUP_TILE entries, one wave per tile, instead of by the wave
+// that owns them (R-MAT's heaviest rows are adjacent: one wave's 64 rows can
+// hold a quarter of a million entries).
+constexpr int SETUP_TILE = 512;
+struct LongHead { unsigned long long packed; unsigned long long pad; };   // rows << 32 | tiles
+struct LongRow { int32_t row, ntiles, it0, pad; };                       // row < 0: unused slot
+struct LongPart { unsigned long long sum; uint32_t bmax; int32_t lo, hi, pad; };
+
+// Per-block records of the first binning pass (256 rows per block), and the
+// setup step's list of long rows and their tiles.
 struct BlockParts {
     unsigned int *hist;          // [nblk][BIN_SLOTS] rows per bin; exclusive over blocks after finalize
     unsigned long long *tot;     // [nblk] sum of row values; exclusive scan after a scanning finalize
     unsigned long long *mx;      // [nblk] max row value
+    LongHead *lh;                // counts of lrows / litems (setup step only)
+    LongRow *lrows;              // [cap_rows]
+    int2 *litems;                // [cap_items] (slot in lrows or -1, tile of the row)
+    LongPart *lpart;             // [cap_items] per-tile sums
+    uint32_t cap_rows, cap_items;
 };
+
+// Bytes of the records of M rows whose A holds nnzA entries (the long-row
+// list is sized so that any A whose rows span at most nnzA entries fits:
+// at most nnzA / SETUP_TILE rows and 2 nnzA / SETUP_TILE + 1 tiles).
+inline void block_parts_caps(int64_t nnzA, uint32_t *cr, uint32_t *ci) {
+    const int64_t r = nnzA / SETUP_TILE + 1, t = 2 * r;
+    const int64_t lim = (int64_t)1 << 30;
+    *cr = (uint32_t)(r < lim ? r : lim);
+    *ci = (uint32_t)(t < lim ? t : lim);
+}
+inline size_t block_parts_bytes(int64_t M, int64_t nnzA) {
+    const int64_t nblk = M > 0 ? (M + 255) / 256 : 1;
+    uint32_t cr, ci;
+    block_parts_caps(nnzA, &cr, &ci);
+    size_t b = (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk;
+    b = (b + 15) & ~(size_t)15;
+    return b + sizeof(LongHead) + sizeof(LongRow) * cr + (sizeof(int2) + sizeof(LongPart)) * ci;
+}
+inline BlockParts block_parts_at(void *p, int64_t M, int64_t nnzA) {
+    const int64_t nblk = M > 0 ? (M + 255) / 256 : 1;
+    BlockParts q;
+    q.tot = (unsigned long long *)p;
+    q.mx = q.tot + nblk;
+    q.hist = (unsigned int *)(q.mx + nblk);
+    size_t b = (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk;
+    b = (b + 15) & ~(size_t)15;
+    block_parts_caps(nnzA, &q.cap_rows, &q.cap_items);
+    q.lh = (LongHead *)((char *)p + b);
+    q.lrows = (LongRow *)((char *)p + b + sizeof(LongHead));
+    q.lpart = (LongPart *)(q.lrows + q.cap_rows);
+    q.litems = (int2 *)(q.lpart + q.cap_items);
+    return q;
+}
 
 // Length, first and last column of every row of B (0, INT_MAX, -1 for
 // empty rows) as int4 records.
 hipError_t launch_brange(const DevCSR &B, int4 *brec, hipStream_t s);
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
-// per-block bin counts / totals / maxima into `parts`; optional features
+// per-block bin counts / totals / maxima into `parts` (which must come from
+// block_parts_at with A's nnz); optional features
 // (a_len, b_max) and, given B's row records `brec`, the column range
 // (lo, hi) of each row's output (the smallest first and largest last column
 // of the B rows it references; INT_MAX / -1 for rows without products).

@@ -133,11 +133,8 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
         CHK(ar.alloc(&p, sizeof(int4) * (size_t)(B->rows > 0 ? B->rows : 1)));
         bfl = (int4 *)p;
     }
-    CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
-    BlockParts parts;
-    parts.tot = (unsigned long long *)p;
-    parts.mx = parts.tot + nblk;
-    parts.hist = (unsigned int *)(parts.mx + nblk);
+    CHK(ar.alloc(&p, block_parts_bytes(M, A->nnz)));
+    const BlockParts parts = block_parts_at(p, M, A->nnz);
     CHK(ar.alloc(&p, sizeof(LearnedCounters)));
     LearnedCounters *dc = (LearnedCounters *)p;
     LearnedCounters hc;
@@ -394,11 +391,8 @@ opsp_status opsp_row_features(const opsp_csr *A, const opsp_csr *B, int32_t *a_l
     Arena ar(s);
     void *p = nullptr;
     const int64_t nblk = (M + 255) / 256;
-    CHK(ar.alloc(&p, (sizeof(unsigned int) * BIN_SLOTS + 2 * sizeof(unsigned long long)) * (size_t)nblk));
-    BlockParts parts;
-    parts.tot = (unsigned long long *)p;
-    parts.mx = parts.tot + nblk;
-    parts.hist = (unsigned int *)(parts.mx + nblk);
+    CHK(ar.alloc(&p, block_parts_bytes(M, A->nnz)));
+    const BlockParts parts = block_parts_at(p, M, A->nnz);
     int64_t *np = n_prod;
     if (!np) {
         CHK(ar.alloc(&p, sizeof(int64_t) * (size_t)M));

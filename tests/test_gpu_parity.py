@@ -437,3 +437,48 @@ def test_symbolic_rows_routed_by_range(hash_all):
     st = ops.Stats()
     check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all), stats=st)
     assert st.sym_bin_rows[1] == (0 if hash_all else routed)
+
+
+def _rows_of_lengths(lengths, K, seed):
+    """A with rows of the given entry counts over K columns (distinct sorted
+    columns, U(-1, 1) values)."""
+    rng = np.random.default_rng(seed)
+    rpt, cols = [0], []
+    for L in lengths:
+        cols.append(np.sort(rng.choice(K, L, replace=False)))
+        rpt.append(rpt[-1] + L)
+    return syn.CSR(len(lengths), K, np.array(rpt, np.int64),
+                   np.concatenate(cols).astype(np.int32), rng.uniform(-1, 1, rpt[-1]))
+
+
+LONG_ROW_LENGTHS = ([0, 1, 512, 513, 1023, 1024, 1025, 2049, 0, 5000, 70000, 3, 1500] + [7] * 200 +
+                    [600] * 70 + [0] * 30 + [3000])
+
+
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_setup_long_rows_in_tiles(hash_all):
+    """Rows of more than 512 A entries are walked by the setup step in tiles
+    of 512 entries on many waves: lengths on both sides of one and two
+    tiles, one row of 70,000 entries, a wave of 64 rows that are all long,
+    long rows next to empty ones; n_prod is compared through the product and
+    the per-row features."""
+    import torch
+    ops = _ops()
+    A = _rows_of_lengths(LONG_ROW_LENGTHS, 80000, seed=31)
+    B = syn.random_csr(80000, 5000, 0.0006, seed=32)
+    st = ops.Stats()
+    check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all), stats=st)
+    nprod, alen, bmax, _ = oracle.row_stats(A, B)
+    assert st.nprod == int(nprod.sum())
+    dA, dB = ops.DeviceCSR.from_host(A), ops.DeviceCSR.from_host(B)
+    al, npd, bm = ops.row_features(dA, dB)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(npd.cpu().numpy(), nprod)
+    np.testing.assert_array_equal(al.cpu().numpy(), alen)
+    np.testing.assert_array_equal(bm.cpu().numpy(), bmax)
+    # a view of rows 5..300 (rpt[0] != 0, the long rows cut at both ends)
+    lo, hi = 5, 300
+    view = ops.DeviceCSR(hi - lo, A.cols, dA.rpt[lo:hi + 1], dA.col, dA.val)
+    C = ops.spgemm(view, dB, config=ops.Config(validate=1, hash_all_rows=hash_all))
+    torch.cuda.synchronize()
+    oracle.compare(*C.to_host(), oracle.spgemm(A, B, rows=np.arange(lo, hi)), tol=TOL)
