@@ -92,9 +92,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // bins 1-7: one team (a wave for W == 64, else the workgroup) per row
 // ---------------------------------------------------------------------------
 template <int W, int T, bool ABORT, bool PERSIST>
-// wave teams: eight waves per SIMD requested (scalar registers would
-// otherwise cap the occupancy at seven)
-__global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu(W == 64 ? 8 : 1))) void k_sym_row(
+// Eight waves per SIMD requested where the LDS allows them: wave teams
+// (scalar registers would otherwise cap the occupancy at seven), and the
+// 512- and 1024-thread teams whose tables let two or four workgroups share a
+// CU (at more than 64 vector registers only one would fit: rmat 2^20
+// symbolic 46.8 -> 42.9 ms).
+__global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu((W == 64 || (W >= 512 && T <= 20448)) ? 8 : 1))) void k_sym_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list,
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 const uint32_t o = (uint32_t)(key - lo);
                 if (ok && o < span) atomicOr((unsigned int *)&tb[o & wmask], 1u << (o >> lgw));
             };
-            row_products<false, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, set,
+            row_products<false, (W >= 512 ? (ABORT ? SYM_ABORT_D : WIDE_D) : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, set,
                                 [] { return false; });
         } else if (active) {
             auto ins = [&](bool ok, int key) {
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
                 else return false;
             };
-            row_products<false, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, ins, stop);
+            row_products<false, (W >= 512 ? (ABORT ? SYM_ABORT_D : WIDE_D) : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, ins, stop);
         }
         if (bm) {   // uniform over the team
             team_sync<WT>();

@@ -61,6 +61,9 @@ constexpr int SW_LG = 20;
 // kernels that give a row 512 or more threads (long rows: few waves per CU
 // to hide the load latency).
 constexpr int WIDE_D = 2;
+// ... and in the symbolic bin-7 kernel, which has the CU to itself (all of
+// the LDS; four waves per SIMD leave it 128 vector registers)
+constexpr int SYM_ABORT_D = 6;
 constexpr int SW_MAXPASS = 8;
 constexpr int NUM_GLOBAL_WG_PER_CU = 1;
 
