@@ -1015,25 +1015,35 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         for (int i = t; i < BK_NB / 2; i += BK_T) dense[i] = 0.0;
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if constexpr (LRN) {
-            // the row's size decides where it goes: count the distinct
-            // columns chunk by chunk first
-            unsigned int tot_n = 0;
-            for (int b = 0; b < nb; ++b) {
+        // One-phase step: the row goes to its slot while it fits.  Its size
+        // is only counted (distinct columns of the chunks not yet emitted)
+        // once the next chunk's products could overflow the slot; if the
+        // exact size does not fit, the row moves to the arena (the entries
+        // already emitted are copied there) or, when the arena is full, to
+        // the recompute list.
+        int64_t cap = n;
+        bool known = !LRN;
+        if constexpr (LRN) {   // no slots in the recompute pass: straight to the arena
+            base = L.off ? L.off[row] : 0;
+            cap = L.off ? L.off[row + 1] - base : 0;
+        }
+        // distinct columns of chunks [b0, nb) (bits is clear before and after)
+        auto count_from = [&](int b0) -> int64_t {
+            int64_t tot_n = 0;
+            for (int b = b0; b < nb; ++b) {
                 const unsigned int p0 = off[b], p1 = off[b + 1];
                 if (p0 == p1) continue;   // uniform
-                const int c0 = lo + (b << BK_LG);
                 for (unsigned int p = p0 + t; p < p1; p += BK_T * BK_U) {
-                    int kk[BK_U];
+                    int ck[BK_U];
 #pragma unroll
                     for (int u = 0; u < BK_U; ++u) {
                         const unsigned int q = p + (unsigned int)BK_T * u;
-                        kk[u] = q < p1 ? (int)sk[q] : -1;
+                        ck[u] = q < p1 ? (int)sk[q] : -1;
                     }
 #pragma unroll
                     for (int u = 0; u < BK_U; ++u) {
-                        if (kk[u] < 0) continue;
-                        const uint32_t o = (uint32_t)kk[u];
+                        if (ck[u] < 0) continue;
+                        const uint32_t o = (uint32_t)ck[u];
                         atomicOr(&bits[o >> 5], 1u << (o & 31));
                     }
                 }
@@ -1046,17 +1056,8 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                 for (int i = 0; i < BK_NW; ++i) tot_n += red[i];
                 __syncthreads();
             }
-            n = tot_n;
-            if (t == 0) {
-                const int64_t bb = lrn_place(L, row, n);
-                if (bb < 0) lrn_retry(L, row, false);
-                else lrn_done(L, row, n, bb);
-                s_base = bb;
-            }
-            __syncthreads();
-            base = (int64_t)s_base;
-            if (base < 0) continue;   // uniform; no barrier pending
-        }
+            return tot_n;
+        };
         // 4. per chunk: dense accumulation, then emission.  Thread t owns
         //    the 16 columns [16 t, 16 t + 16) of the chunk: a wave scan (DPP)
         //    and one exchange over the waves give its first rank, and it
@@ -1080,9 +1081,46 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
         int b = 0;
         while (b < nb && off[b] == off[b + 1]) ++b;   // uniform
         if (b < nb) preload(b);
+        bool dropped = false;
         while (b < nb) {
             const unsigned int p0 = off[b], p1 = off[b + 1];
             const int c0 = lo + (b << BK_LG);
+            if constexpr (LRN) {
+                if (!known && run + (int64_t)(p1 - p0) > cap) {   // uniform
+                    const int64_t ex = run + count_from(b);
+                    known = true;
+                    if (ex > cap) {
+                        if (t == 0) {
+                            int64_t nb2 = -1;
+                            const unsigned long long a =
+                                atomicAdd(&L.lc->arena_used, (unsigned long long)ex);
+                            if ((int64_t)a + ex <= L.arena_cap) {
+                                atomicAdd(&L.lc->slot_overflow, 1u);
+                                nb2 = L.arena_base + (int64_t)a;
+                            } else {
+                                lrn_retry(L, row, false);
+                            }
+                            s_base = nb2;
+                        }
+                        // the entries emitted so far are visible to every
+                        // thread of the workgroup before they are moved
+                        __threadfence();
+                        __syncthreads();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        const int64_t nbase = (int64_t)s_base;
+                        if (nbase < 0) {   // uniform
+                            dropped = true;
+                            break;
+                        }
+                        for (int64_t i = t; i < run; i += BK_T) {
+                            ccol[nbase + i] = ld_coherent(&ccol[base + i]);
+                            cval[nbase + i] = ld_coherent(&cval[base + i]);
+                        }
+                        base = nbase;
+                    }
+                    cap = ex;
+                }
+            }
             auto accumulate = [&]() {
 #pragma unroll
                 for (int u = 0; u < BK_U; ++u) {
@@ -1141,7 +1179,7 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
                     const V v = (V)dense[q];
                     dense[q] = 0.0;
                     const int64_t kr = run + r0 + k;
-                    if (kr < n) {   // C is not read again here: keep it out of the caches
+                    if (kr < cap) {   // C is not read again here: keep it out of the caches
                         __builtin_nontemporal_store(c0 + (int)o, &ccol[base + kr]);
                         __builtin_nontemporal_store(v, &cval[base + kr]);
                     }
@@ -1153,7 +1191,14 @@ __global__ __launch_bounds__(BK_T) void k_num_bucket(
             __syncthreads();
             b = bn;
         }
-        if (t == 0 && run != n) atomicAdd(&ctr->error, 1u);
+        if constexpr (LRN) {
+            if (!dropped && t == 0) {
+                if (run > cap) atomicAdd(&ctr->error, 1u);
+                lrn_done(L, row, run, base);
+            }
+        } else {
+            if (t == 0 && run != n) atomicAdd(&ctr->error, 1u);
+        }
         __syncthreads();
     }
 }
