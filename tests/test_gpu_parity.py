@@ -135,7 +135,7 @@ def test_every_big_row_recomputed_globally():
     assert st.sym_bin_rows[7] > 0 and st.sym_bin_rows[8] >= st.sym_bin_rows[7]
 
 
-@pytest.mark.parametrize("rowlen", [1, 3, 8, 20, 40, 70, 300])
+@pytest.mark.parametrize("rowlen", [1, 3, 8, 20, 40, 70, 100, 300])
 def test_b_row_lengths(rowlen):
     """Uniform B rows of many lengths drive both product mappings (grouped
     lanes for B rows up to 64 entries, flat windows beyond)."""
@@ -485,3 +485,36 @@ def test_setup_long_rows_in_tiles(hash_all):
     C = ops.spgemm(view, dB, config=ops.Config(validate=1, hash_all_rows=hash_all))
     torch.cuda.synchronize()
     oracle.compare(*C.to_host(), oracle.spgemm(A, B, rows=np.arange(lo, hi)), tol=TOL)
+
+
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_b_rows_of_65_to_128_entries(hash_all):
+    """B rows of exactly 63-65, 100, 127-129 entries, around the limit of
+    the grouped product mapping (B rows of at most 64 entries) and beyond
+    it (flat windows).  A's rows mix the lengths, one row per length alone,
+    in several symbolic and numeric bin kernels (forced) and in the binned
+    default."""
+    ops = _ops()
+    rng = np.random.default_rng(65)
+    lens = [63, 64, 65, 100, 127, 128, 129]
+    K, N = 700, 6000
+    brpt, bcol = [0], []
+    for k in range(K):
+        L = lens[k % len(lens)]
+        bcol.append(np.sort(rng.choice(N, L, replace=False)))
+        brpt.append(brpt[-1] + L)
+    B = syn.CSR(K, N, np.array(brpt, np.int64), np.concatenate(bcol).astype(np.int32),
+                rng.uniform(-1, 1, brpt[-1]))
+    arpt, acol = [0], []
+    for i in range(300):
+        if i < len(lens):   # one row per length alone
+            cols = np.arange(i, K, len(lens))[:5 + i]
+        else:
+            cols = np.sort(rng.choice(K, 1 + i % 90, replace=False))
+        acol.append(cols)
+        arpt.append(arpt[-1] + len(cols))
+    A = syn.CSR(300, K, np.array(arpt, np.int64), np.concatenate(acol).astype(np.int32),
+                rng.uniform(-1, 1, arpt[-1]))
+    check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all))
+    for b in (1, 4, 7):
+        check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all, force_sym_bin=b, force_num_bin=b))
