@@ -613,6 +613,9 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
         return;
     }
 
+    // pairs per lane in use (uniform): the loops below stop there instead of
+    // running all EMAX steps with the lanes masked off
+    const int jn = __builtin_amdgcn_readfirstlane((n + W - 1) / W);
     int ek[EMAX], es[EMAX];
 #pragma unroll
     for (int j = 0; j < EMAX; ++j) {
@@ -632,6 +635,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     int eb[EMAX];
 #pragma unroll
     for (int j = 0; j < EMAX; ++j) {
+        if (j >= jn) break;
         eb[j] = (ek[j] - kmin) >> 5;
         if (ek[j] >= 0) atomicOr(&L1[eb[j] >> 5], 1u << (eb[j] & 31));
     }
@@ -652,6 +656,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     team_sync<WT>();
 #pragma unroll
     for (int j = 0; j < EMAX; ++j) {
+        if (j >= jn) break;
         if (ek[j] >= 0) {
             const int b = eb[j];
             eb[j] = P1[b >> 5] + __popc(L1[b >> 5] & ((1u << (b & 31)) - 1u));
@@ -676,6 +681,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     if (active) {
 #pragma unroll
         for (int j = 0; j < EMAX; ++j) {
+            if (j >= jn) break;
             if (ek[j] >= 0) {
                 const int bit = (ek[j] - kmin) & 31;
                 const int rank = P0[eb[j]] + __popc(L0[eb[j]] & ((1u << bit) - 1u));
