@@ -335,6 +335,9 @@ def main():
                          "batch vs 512 plain calls; learned: one-phase product with the trained "
                          "predictor vs the plain two-phase product and the upper-bound rule")
     ap.add_argument("--count", type=int, default=512, help="problems in the batched mode")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batched mode: time the tuned batch alone (no built-in configuration, "
+                         "no separate plain calls), e.g. under a kernel trace")
     ap.add_argument("--workloads", default="st27_100,bst27_40,band21,rmat20",
                     help="ablation mode: workloads of the tables")
     ap.add_argument("--out", default="", help="ablation mode: also write the tables (markdown) here")
@@ -804,10 +807,12 @@ def bench_batched(args, dev):
         log(f"batched ({'tuned batch class' if tuned is not None else 'built-in'}): {ms:.3f} ms per "
             f"batch, nprod={nprod}, nnz={nnzC}")
         ms_builtin = None
-        if tuned is not None:
+        if tuned is not None and not args.batch_only:
             ms_builtin, _ = time_batch(None)
             log(f"batched (built-in configuration): {ms_builtin:.3f} ms per batch")
-        # the same products as separate plain calls
+
+    def time_plain_calls():
+        """ms for the same products as `count` separate plain calls."""
         Ac = [a._c_fast(a.nnz) for a in dA]
         Bc = [b._c_fast(b.nnz) for b in dB]
         for a, b in zip(Ac[:8], Bc[:8]):
@@ -819,9 +824,13 @@ def bench_batched(args, dev):
             for a, b in zip(Ac, Bc):
                 ops.free_raw(ops.spgemm_raw(a, b, sh), sh)
         torch.cuda.synchronize()
-        t4 = time.perf_counter()
-        ms_plain = (t4 - t3) * 1e3 / reps
-    log(f"{args.count} plain calls: {ms_plain:.3f} ms")
+        return (time.perf_counter() - t3) * 1e3 / reps
+
+    ms_plain = None
+    if not args.batch_only:
+        with torch.cuda.stream(stream):
+            ms_plain = time_plain_calls()
+        log(f"{args.count} plain calls: {ms_plain:.3f} ms")
     gflops = 2.0 * nprod / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -841,9 +850,10 @@ def bench_batched(args, dev):
                                   "rows, N(0,1) values, seed 4",
                    "nprod": nprod, "nnzC": nnzC, "path": "batched (two replayed graphs)",
                    "bins": "autotuned (batch)" if tuned is not None else "built-in"},
-        "plain_calls_ms": round(ms_plain, 3),
-        "speedup_vs_plain_calls": round(ms_plain / ms, 3),
     }
+    if ms_plain is not None:
+        out["plain_calls_ms"] = round(ms_plain, 3)
+        out["speedup_vs_plain_calls"] = round(ms_plain / ms, 3)
     if ms_builtin is not None:
         out["builtin_config"] = {"ms_per_step": round(ms_builtin, 4),
                                  "value": round(2.0 * nprod / (ms_builtin * 1e-3) / 1e9, 3),
