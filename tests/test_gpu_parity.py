@@ -518,3 +518,33 @@ def test_b_rows_of_65_to_128_entries(hash_all):
     check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all))
     for b in (1, 4, 7):
         check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all, force_sym_bin=b, force_num_bin=b))
+
+
+@pytest.mark.parametrize("declared_nnz", [3000, 42000])
+def test_setup_long_row_list_full(declared_nnz):
+    """The setup step's list of long rows is sized from A's declared entry
+    count.  An A that declares fewer entries than its rows span (the arrays
+    themselves are whole) fills the list: with 3,000 no wave's reservation
+    fits, with 42,000 the first wave's long rows are listed and the later
+    waves' are not; waves whose reservation does not fit walk their long
+    rows themselves.  The product is unchanged (validation off: it would
+    reject the declared count)."""
+    import ctypes
+    import torch
+    ops = _ops()
+    A = _rows_of_lengths(LONG_ROW_LENGTHS, 80000, seed=31)
+    B = syn.random_csr(80000, 5000, 0.0006, seed=32)
+    dA, dB = ops.DeviceCSR.from_host(A), ops.DeviceCSR.from_host(B)
+    Ac, Bc, Cc = dA._c(), dB._c(), ops.opsp_csr()
+    assert Ac.nnz > declared_nnz
+    Ac.nnz = declared_nnz
+    s = torch.cuda.current_stream().cuda_stream
+    st = ops.Stats()
+    code = ops.lib().opsp_spgemm_ex(ctypes.byref(Ac), ctypes.byref(Bc), ctypes.byref(Cc), None,
+                                    ctypes.byref(st), s)
+    assert code == 0, code
+    C = ops._adopt(Cc, s, dA.rpt.device)
+    torch.cuda.synchronize()
+    nprod, _, _, _ = oracle.row_stats(A, B)
+    assert st.nprod == int(nprod.sum())
+    oracle.compare(*C.to_host(), oracle.spgemm(A, B), tol=TOL)
