@@ -437,6 +437,25 @@ def main():
             torch.cuda.synchronize()
             out["learned"] = {"skipped": f"one-phase product does not fit in device memory ({e})"}
             log(f"learned one-phase: skipped, {e}")
+            # such products run the one-phase form by row panels: compare
+            # the first of LEARNED_PANELS panels of equal n_prod (a zero-copy
+            # view of A's rows) in both forms, with the built-in bins
+            release()
+            _, npd, _ = ops.row_features(dA, dA)
+            cum = np.cumsum(npd.cpu().numpy())
+            r1 = int(np.searchsorted(cum, int(cum[-1]) / LEARNED_PANELS, side="right"))
+            view = ops.DeviceCSR(r1, dA.cols, dA.rpt[:r1 + 1], dA.col, dA.val)
+            steps_p = min(args.steps, 5)
+            ms_p, stp = time_plain(ops, torch, view, dA, steps_p, 1)
+            release()
+            rlp = time_learned(ops, torch, view, dA, pred, steps_p, 1)
+            del view
+            out["learned"]["panel"] = {
+                "panel": f"0/{LEARNED_PANELS}", "rows": [0, r1], "nprod": stp.nprod, "steps": steps_p,
+                "plain_ms": round(ms_p, 4), "learned_ms": round(rlp["ms"], 4),
+                "speedup_vs_plain": round(ms_p / rlp["ms"], 4), **rlp["stats"]}
+            log(f"learned one-phase on row panel 0/{LEARNED_PANELS} (rows [0, {r1})): {rlp['ms']:.3f} ms "
+                f"against {ms_p:.3f} ms plain ({ms_p / rlp['ms']:.3f}x)")
         else:
             out["learned"] = {"value": round(2.0 * nprod / (rl["ms"] * 1e-3) / 1e9, 3),
                               "ms_per_step": round(rl["ms"], 4),
@@ -638,6 +657,11 @@ def bench_copy(args, dev):
     print(json.dumps({"mode": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
                       "copies": args.steps, "ms_per_copy": round(ms, 4),
                       "GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
+# Row panels of equal n_prod for the one-phase comparison of a product that
+# does not fit one GPU in one piece.
+LEARNED_PANELS = 8
 
 
 def time_learned(ops, torch, dA, dB, pred, steps, warmup):
