@@ -101,7 +101,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list,
-    const int2 *__restrict__ rng) {
+    const int2 *__restrict__ rng, const int4 *__restrict__ brec) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;  // waves per team
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 if (ok && o < span) atomicOr((unsigned int *)&tb[o & wmask], 1u << (o >> lgw));
             };
             row_products<false, (W >= 512 ? (ABORT ? SYM_ABORT_D : WIDE_D) : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, set,
-                                [] { return false; });
+                                [] { return false; }, brec);
         } else if (active) {
             auto ins = [&](bool ok, int key) {
                 const int nw = sym_insert_wave(tb, (uint32_t)T, ok, key, &ctr->error);
@@ -200,7 +200,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                 if constexpr (ABORT) return *(volatile int *)&s_abort[team] != 0;
                 else return false;
             };
-            row_products<false, (W >= 512 ? (ABORT ? SYM_ABORT_D : WIDE_D) : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, ins, stop);
+            row_products<false, (W >= 512 ? (ABORT ? SYM_ABORT_D : WIDE_D) : 1)>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, t >> 6, NW, ins, stop,
+                brec);
         }
         if (bm) {   // uniform over the team
             team_sync<WT>();
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(1024) void k_sym_global(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int64_t ncols, int *slabs, int64_t slab_entries, const int2 *__restrict__ rng,
-    unsigned long long *sched, Counters *__restrict__ ctr) {
+    unsigned long long *sched, Counters *__restrict__ ctr, const int4 *__restrict__ brec) {
     __shared__ unsigned int bm[SW_WORDS];
     __shared__ int red[16];
     __shared__ long long s_r;
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(1024) void k_sym_global(
                                         const uint32_t o = (uint32_t)key - base;
                                         if (ok && o < wlen) atomicOr(&bm[o >> 5], 1u << (o & 31));
                                     },
-                                    [] { return false; });
+                                    [] { return false; }, brec);
                 __syncthreads();
                 unsigned int c = 0;
                 for (uint32_t i = t; i < words; i += 1024) c += __popc(bm[i]);
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(1024) void k_sym_global(
             int cnt = 0;
             auto ins = [&](bool ok, int key) { cnt += sym_insert_wave(tb, T, ok, key, &ctr->error); };
             row_products<false, WIDE_D>(a0, a1, acol, (const double *)nullptr, brpt, bcol, (const double *)nullptr, wv, 16, ins,
-                                [] { return false; });
+                                [] { return false; }, brec);
             cnt = wave_sum(cnt);
             if (l == 0) red[wv] = cnt;
             __syncthreads();
@@ -345,11 +346,11 @@ static hipError_t go_row(const SymArgs &a, hipStream_t s) {
     if (a.grid > 0)
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, true>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list, a.rng);
+                           a.fail_list, a.rng, a.brec);
     else
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, false>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list, a.rng);
+                           a.fail_list, a.rng, a.brec);
     return hipGetLastError();
 }
 
@@ -385,7 +386,7 @@ hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s) {
             if (a.grid <= 0) return hipSuccess;
             hipLaunchKernelGGL(k_sym_global, dim3((unsigned)a.grid), dim3(1024), 0, s, a.src, a.A.rpt,
                                a.A.col, a.B.rpt, a.B.col, a.nnz, a.B.cols, a.slab, a.slab_entries,
-                               a.rng, a.sched, a.ctr);
+                               a.rng, a.sched, a.ctr, a.brec);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

@@ -366,15 +366,21 @@ __device__ __forceinline__ float bpermute_v(float v, int src_lane) {
 // (`f(ok, key)` for the symbolic step); every lane calls f once per window,
 // `ok` says whether it holds a product.  `stop()` is polled once per window
 // and ends the enumeration for the whole wave.
+// Symbolic step only: with `dup` (B's row records, .w = 1 when a row has the
+// same columns as the row before it), an entry whose B row repeats the
+// previous entry's row pattern (A holds k - 1 and k, B rows k - 1 and k have
+// one column set) contributes no new column and is skipped: blocks of
+// unknowns per node (finite elements) then cost one B row per node.
 template <bool NUMERIC, int D = 1, class V = double, class F, class Stop>
 __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32_t *__restrict__ acol,
                                              const V *__restrict__ aval,
                                              const int64_t *__restrict__ brpt,
                                              const int32_t *__restrict__ bcol,
                                              const V *__restrict__ bval, int wv_in, int nwaves,
-                                             F &&f, Stop &&stop) {
+                                             F &&f, Stop &&stop, const int4 *__restrict__ dup = nullptr) {
     const int l = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(wv_in);   // wave-uniform: window indices in SGPRs
+    int k_last = -2;   // symbolic with dup: the previous chunk's last B row
     for (int64_t c0 = a0; c0 < a1; c0 += 64) {
         const int64_t j = c0 + l;
         const bool v = j < a1;
@@ -385,7 +391,15 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
             if constexpr (NUMERIC) av = aval[j];
         }
         const int64_t b0 = v ? brpt[k] : 0;
-        const int len = v ? (int)(brpt[k + 1] - b0) : 0;
+        int len = v ? (int)(brpt[k + 1] - b0) : 0;
+        if constexpr (!NUMERIC) {
+            if (dup) {   // uniform: the previous entry from the next lane down
+                int kp = __shfl_up(k, 1);
+                if (l == 0) kp = k_last;
+                k_last = __builtin_amdgcn_readlane(k, 63);   // lanes past the end are not read again
+                if (v && k > 0 && kp == k - 1 && dup[k].w) len = 0;
+            }
+        }
         const int nent = (int)(a1 - c0 < 64 ? a1 - c0 : 64);
         const int lmax = wave_max(len);
         const int64_t total = (int64_t)wave_sum((long long)len);

@@ -448,6 +448,10 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.ctr = ctrS;
     sa.rng = rng;
     sa.gv = gv;
+    // rows that repeat the previous entry's B-row pattern are skipped when B
+    // looks like a matrix of node blocks (long rows: 3 unknowns of a 27-point
+    // node give 81); elsewhere the check would cost more than it finds
+    sa.brec = (bfl && B->nnz >= DUP_MIN_AVG * B->rows) ? bfl : nullptr;
     const bool need_slab = !rng || N > ((int64_t)SW_MAXPASS << SW_LG);
     int *slab = nullptr;
     int64_t slab_entries = 0;

@@ -87,7 +87,8 @@ inline BlockParts block_parts_at(void *p, int64_t M, int64_t nnzA) {
 }
 
 // Length, first and last column of every row of B (0, INT_MAX, -1 for
-// empty rows) as int4 records.
+// empty rows) as int4 records; .w = 1 when the row has the same columns as
+// the row before it (compared for rows of at most 256 entries).
 hipError_t launch_brange(const DevCSR &B, int4 *brec, hipStream_t s);
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
 // per-block bin counts / totals / maxima into `parts` (which must come from
@@ -142,7 +143,12 @@ struct SymArgs {
     unsigned long long *sched;  // bin 8: Counters::sched of the launch, zero on entry
                                 // (null: rows assigned round-robin)
     int gv;                  // bin 0 variant (GROUP_GL / SYM_T0)
+    const int4 *brec;        // optional B row records (launch_brange): rows that
+                             // repeat the previous entry's column set are skipped
 };
+// Average B row length from which the symbolic step looks for repeated
+// row patterns.
+constexpr int64_t DUP_MIN_AVG = 48;
 hipError_t launch_symbolic_bin(int bin, const SymArgs &a, hipStream_t s);
 // Workgroups per CU of a symbolic bin kernel launched persistently (its rows
 // counted on the device): several times what one CU holds, so that the

@@ -548,3 +548,62 @@ def test_setup_long_row_list_full(declared_nnz):
     nprod, _, _, _ = oracle.row_stats(A, B)
     assert st.nprod == int(nprod.sum())
     oracle.compare(*C.to_host(), oracle.spgemm(A, B), tol=TOL)
+
+
+def _repeated_pattern_rows(seed=77):
+    """B with runs of rows that share one column set (three unknowns of a
+    node), rows that match a neighbour in length and end columns but not in
+    the middle, and identical rows longer than the compared length (300
+    entries); A rows that take whole runs, parts of runs, and runs with a
+    row left out."""
+    rng = np.random.default_rng(seed)
+    N = 4000
+    brows = []
+    for g in range(120):
+        kind = g % 4
+        L = [20, 64, 100, 300][kind]
+        pat = np.sort(rng.choice(N, L, replace=False))
+        if kind == 2 and g % 8 == 2:   # same length and ends, one middle column moved
+            alt = pat.copy()
+            free = np.setdiff1d(np.arange(pat[0] + 1, pat[-1]), pat)
+            alt[L // 2] = free[0]
+            brows += [pat, np.sort(alt), pat]
+        else:
+            brows += [pat, pat, pat]
+    brpt = np.concatenate([[0], np.cumsum([len(r) for r in brows])]).astype(np.int64)
+    B = syn.CSR(len(brows), N, brpt, np.concatenate(brows).astype(np.int32),
+                rng.uniform(-1, 1, int(brpt[-1])))
+    K = len(brows)
+    arows = []
+    for i in range(400):
+        m = i % 5
+        if m == 0:      # whole runs
+            g = rng.choice(K // 3, 4, replace=False)
+            cols = np.concatenate([[3 * x, 3 * x + 1, 3 * x + 2] for x in g])
+        elif m == 1:    # the last two of a run
+            g = rng.choice(K // 3, 5, replace=False)
+            cols = np.concatenate([[3 * x + 1, 3 * x + 2] for x in g])
+        elif m == 2:    # a run with its middle row left out
+            g = rng.choice(K // 3, 5, replace=False)
+            cols = np.concatenate([[3 * x, 3 * x + 2] for x in g])
+        elif m == 3:    # random rows
+            cols = rng.choice(K, 12, replace=False)
+        else:           # one whole run alone
+            x = int(rng.integers(K // 3))
+            cols = np.array([3 * x, 3 * x + 1, 3 * x + 2])
+        arows.append(np.unique(cols))
+    arpt = np.concatenate([[0], np.cumsum([len(r) for r in arows])]).astype(np.int64)
+    A = syn.CSR(len(arows), K, arpt, np.concatenate(arows).astype(np.int32),
+                rng.uniform(-1, 1, int(arpt[-1])))
+    return A, B
+
+
+@pytest.mark.parametrize("forced", [-1, 1, 4, 7, 8])
+def test_symbolic_skips_repeated_row_patterns(forced):
+    """The symbolic step skips an A entry whose B row has the same columns as
+    the B row of the entry before it (flagged by the B row records); the
+    counts, and so the product, must equal the oracle's whatever the
+    symbolic kernel."""
+    ops = _ops()
+    A, B = _repeated_pattern_rows()
+    check(A, B, cfg=ops.Config(validate=1, force_sym_bin=forced))
