@@ -565,38 +565,38 @@ hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const 
 
 // Length, first and last column of every row of B in one 16-byte record,
 // so that the setup step reads one record per A entry (instead of two row
-// bounds) and also gets each row's output column range; the fourth field
-// flags a row with the same columns as the row before it (the symbolic step
-// skips such a row when the A row also holds the one before it).
+// bounds) and also gets each row's output column range; with `dup` the
+// fourth field flags a row with the same columns as the row before it (the
+// symbolic step skips such a row when the A row also holds the one before
+// it), else it is zero.
 constexpr int64_t DUP_MAX = 256;
 __global__ __launch_bounds__(256) void k_brange(int64_t K, const int64_t *__restrict__ brpt,
                                                 const int32_t *__restrict__ bcol,
-                                                int4 *__restrict__ brec) {
+                                                int4 *__restrict__ brec, int dup) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= K) return;
     const int64_t b0 = brpt[k], b1 = brpt[k + 1];
-    // .w: the row has the same columns as row k - 1 (rows of up to DUP_MAX
-    // entries whose length and end columns match are compared in full)
+    // rows of up to DUP_MAX entries whose length and end columns match are
+    // compared in full; the compare has no early exit so that its loads
+    // can be in flight together
     int d = 0;
-    if (k > 0 && b1 > b0) {
+    if (dup && k > 0 && b1 > b0) {
         const int64_t p0 = brpt[k - 1], L = b1 - b0;
         if (b0 - p0 == L && L <= DUP_MAX && bcol[p0] == bcol[b0] && bcol[b0 - 1] == bcol[b1 - 1]) {
-            d = 1;
-            for (int64_t e = 1; e + 1 < L; ++e)
-                if (bcol[p0 + e] != bcol[b0 + e]) {
-                    d = 0;
-                    break;
-                }
+            int diff = 0;
+#pragma unroll 8
+            for (int64_t e = 1; e + 1 < L; ++e) diff |= bcol[p0 + e] ^ bcol[b0 + e];
+            d = diff == 0;
         }
     }
     brec[k] = b1 > b0 ? make_int4((int)(b1 - b0), bcol[b0], bcol[b1 - 1], d)
                       : make_int4(0, INT_MAX, -1, 0);
 }
 
-hipError_t launch_brange(const DevCSR &B, int4 *brec, hipStream_t s) {
+hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, hipStream_t s) {
     if (B.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_brange, dim3((unsigned)((B.rows + 255) / 256)), dim3(256), 0, s, B.rows,
-                       B.rpt, B.col, brec);
+                       B.rpt, B.col, brec, dup ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -424,7 +424,11 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
 
     // 1 setup + first symbolic binning pass
     tm.mark();
-    if (bfl) CHK(launch_brange(dB, bfl, s));
+    // rows that repeat the previous entry's B-row pattern are skipped when B
+    // looks like a matrix of node blocks (long rows: 3 unknowns of a 27-point
+    // node give 81); elsewhere the check would cost more than it finds
+    const bool dup = bfl && B->nnz >= DUP_MIN_AVG * B->rows;
+    if (bfl) CHK(launch_brange(dB, bfl, dup, s));
     CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s, bfl, rng));
     tm.mark();   // setup (with the first binning pass fused in) done
     CHK(launch_finalize(M, bs.nslots, parts, ctrS, nullptr, false, s));
@@ -448,10 +452,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.ctr = ctrS;
     sa.rng = rng;
     sa.gv = gv;
-    // rows that repeat the previous entry's B-row pattern are skipped when B
-    // looks like a matrix of node blocks (long rows: 3 unknowns of a 27-point
-    // node give 81); elsewhere the check would cost more than it finds
-    sa.brec = (bfl && B->nnz >= DUP_MIN_AVG * B->rows) ? bfl : nullptr;
+    sa.brec = dup ? bfl : nullptr;
     const bool need_slab = !rng || N > ((int64_t)SW_MAXPASS << SW_LG);
     int *slab = nullptr;
     int64_t slab_entries = 0;

@@ -89,7 +89,7 @@ inline BlockParts block_parts_at(void *p, int64_t M, int64_t nnzA) {
 // Length, first and last column of every row of B (0, INT_MAX, -1 for
 // empty rows) as int4 records; .w = 1 when the row has the same columns as
 // the row before it (compared for rows of at most 256 entries).
-hipError_t launch_brange(const DevCSR &B, int4 *brec, hipStream_t s);
+hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, hipStream_t s);
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
 // per-block bin counts / totals / maxima into `parts` (which must come from
 // block_parts_at with A's nnz); optional features
