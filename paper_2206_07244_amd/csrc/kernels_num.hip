@@ -356,15 +356,23 @@ __device__ __forceinline__ int team_excl_scan(int x, int &total, int *red) {
 // network instead; with binning ratios below 1.5 pairs may not fit at all and
 // entries are ranked by counting over the table.
 // ---------------------------------------------------------------------------
-template <int W, int T, bool LRN, class V>
+template <int W, int T, bool LRN, class V, bool MRG = false>
 // wave teams: eight waves per SIMD requested (scalar registers would
-// otherwise cap the occupancy at seven)
-__global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu(W == 64 ? 8 : 1))) void k_num_row(
+// otherwise cap the occupancy at seven); merged runs hold up to NUM_RUN
+// values per window and would spill within the 64 registers of that
+// occupancy
+__global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_eu(W == 64 && !MRG ? 8 : 1))) void k_num_row(
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const V *__restrict__ aval, const int64_t *__restrict__ brpt,
     const int32_t *__restrict__ bcol, const V *__restrict__ bval,
     const int64_t *__restrict__ crpt, int32_t *__restrict__ ccol, V *__restrict__ cval,
-    Counters *__restrict__ ctr, Learn L, const int2 *__restrict__ rng) {
+    Counters *__restrict__ ctr, Learn L, const int2 *__restrict__ rng,
+    const int4 *__restrict__ dup) {
+    // MRG: entries whose B rows repeat the previous entry's column set are
+    // merged into one table update per column (row_products, `dup` = B's row
+    // records)
+    static_assert(!(MRG && LRN), "runs are merged in the two-phase step only");
+    constexpr int RN = MRG ? NUM_RUN : 1;
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;
@@ -451,15 +459,15 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     if (dn) {   // uniform over the team
         if (active) {
             unsigned int *bits = reinterpret_cast<unsigned int *>(tk);
-            auto acc = [&](bool ok, int key, V v) {
+            auto acc = [&](bool ok, int key, auto v) {
                 const uint32_t o = (uint32_t)(key - lo);
                 if (ok && o < (uint32_t)dspan) {
                     atomicOr(&bits[o >> 5], 1u << (o & 31));
                     atomicAdd(&tv[o], (double)v);
                 }
             };
-            row_products<true, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, acc,
-                                                          [] { return false; });
+            row_products<true, (W >= 512 ? WIDE_D : 1), V, RN>(a0, a1, acol, aval, brpt, bcol, bval, wv,
+                                                                NW, acc, [] { return false; }, dup);
         }
         team_sync<WT>();
         // exclusive popcount prefix per bitmap word, after the words
@@ -497,7 +505,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     // count in a scalar register; larger teams add into LDS.
     int wcnt = 0;
     if (active) {
-        auto ins = [&](bool ok, int key, V v) {
+        auto ins = [&](bool ok, int key, auto v) {
             const int nw = num_insert_wave(tk, tv, (uint32_t)T, ok, key, (double)v, &ctr->error,
                                            [](double *p, double x) { atomicAdd(p, x); });
             if constexpr (LRN) {
@@ -511,7 +519,8 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
             else if constexpr (LRN) return *(volatile int *)&s_cnt[team] > THR;
             else return false;
         };
-        row_products<true, (W >= 512 ? WIDE_D : 1)>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW, ins, stop);
+        row_products<true, (W >= 512 ? WIDE_D : 1), V, RN>(a0, a1, acol, aval, brpt, bcol, bval, wv, NW,
+                                                            ins, stop, dup);
     }
     team_sync<WT>();
     if constexpr (LRN) {
@@ -1334,11 +1343,15 @@ static hipError_t go_row_v(const NumArgs &a, hipStream_t s) {
     if (a.lrn.mode == 1)
         hipLaunchKernelGGL((k_num_row<W, T, true, V>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
                            a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol,
-                           v.cval, a.ctr, a.lrn, a.rng);
+                           v.cval, a.ctr, a.lrn, a.rng, nullptr);
+    else if (a.brec && a.lrn.mode == 0)
+        hipLaunchKernelGGL((k_num_row<W, T, false, V, true>), dim3((unsigned)grid), dim3(W * R), 0, s,
+                           a.src, a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol,
+                           v.cval, a.ctr, a.lrn, a.rng, a.brec);
     else
         hipLaunchKernelGGL((k_num_row<W, T, false, V>), dim3((unsigned)grid), dim3(W * R), 0, s, a.src,
                            a.A.rpt, a.A.col, v.aval, a.B.rpt, a.B.col, v.bval, a.crpt, a.ccol,
-                           v.cval, a.ctr, a.lrn, a.rng);
+                           v.cval, a.ctr, a.lrn, a.rng, nullptr);
     return hipGetLastError();
 }
 

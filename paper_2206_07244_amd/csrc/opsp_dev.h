@@ -345,6 +345,30 @@ __device__ __forceinline__ float bpermute_v(float v, int src_lane) {
     return __int_as_float(bpermute(__float_as_int(v), src_lane));
 }
 
+// Products of one window handed to the numeric step: a[0] * b[0], or, for an
+// entry that leads a run of up to RUN entries whose B rows share one column
+// set (see row_products), the sum of the run's products a[r] * b[r] at one
+// column.  Each product is rounded to the value type and the sum is taken in
+// FP64, as the tables add them.
+template <class V, int RUN>
+struct WinProd {
+    V a[RUN], b[RUN];
+    __device__ __forceinline__ auto value() const {
+        if constexpr (RUN == 1) {
+            return a[0] * b[0];
+        } else {
+            double s = (double)(V)(a[0] * b[0]);
+#pragma unroll
+            for (int r = 1; r < RUN; ++r) s += (double)(V)(a[r] * b[r]);
+            return s;
+        }
+    }
+};
+
+// Longest run of entries with one B-row pattern that the numeric step merges
+// (3 unknowns per node in 3-D elasticity).
+constexpr int NUM_RUN = 3;
+
 // Enumeration of the intermediate products of one row of C = A*B
 // (Eq. 2: C_i* = sum over k in A_i* of A_ik * B_k*), spread over `nwaves`
 // waves of which the caller is wave `wv`.
@@ -366,18 +390,24 @@ __device__ __forceinline__ float bpermute_v(float v, int src_lane) {
 // (`f(ok, key)` for the symbolic step); every lane calls f once per window,
 // `ok` says whether it holds a product.  `stop()` is polled once per window
 // and ends the enumeration for the whole wave.
-// Symbolic step only: with `dup` (B's row records, .w = 1 when a row has the
-// same columns as the row before it), an entry whose B row repeats the
-// previous entry's row pattern (A holds k - 1 and k, B rows k - 1 and k have
-// one column set) contributes no new column and is skipped: blocks of
-// unknowns per node (finite elements) then cost one B row per node.
-template <bool NUMERIC, int D = 1, class V = double, class F, class Stop>
+// Repeated B-row patterns (`dup`: B's row records, .w = 1 when a row has the
+// same columns as the row before it; blocks of unknowns per node in finite
+// elements): when A holds k - 1 and k and B row k repeats row k - 1, entry k
+// adds no column of its own.  The symbolic step skips such an entry.  The
+// numeric step with RUN > 1 gives a run of up to RUN such entries (within a
+// chunk) to the run's first entry, which walks its B row once and hands f
+// the run's summed products (WinProd) per column: one table update where
+// there were up to RUN.  The rows of a run are consecutive in B with one
+// length L, so product r of position p sits at p + r*L.
+template <bool NUMERIC, int D = 1, class V = double, int RUN = 1, class F, class Stop>
 __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32_t *__restrict__ acol,
                                              const V *__restrict__ aval,
                                              const int64_t *__restrict__ brpt,
                                              const int32_t *__restrict__ bcol,
                                              const V *__restrict__ bval, int wv_in, int nwaves,
                                              F &&f, Stop &&stop, const int4 *__restrict__ dup = nullptr) {
+    static_assert(RUN == 1 || NUMERIC, "runs are merged by the numeric step only");
+    using P = WinProd<V, RUN>;
     const int l = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(wv_in);   // wave-uniform: window indices in SGPRs
     int k_last = -2;   // symbolic with dup: the previous chunk's last B row
@@ -392,12 +422,38 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         }
         const int64_t b0 = v ? brpt[k] : 0;
         int len = v ? (int)(brpt[k + 1] - b0) : 0;
+        // run of the entry (RUN > 1): ar[r] the value of its r-th entry and
+        // rn the entries in the run (lanes that are not a run's first: 0)
+        V ar[RUN];
+        ar[0] = av;
+        int rn = 1;
         if constexpr (!NUMERIC) {
             if (dup) {   // uniform: the previous entry from the next lane down
                 int kp = __shfl_up(k, 1);
                 if (l == 0) kp = k_last;
                 k_last = __builtin_amdgcn_readlane(k, 63);   // lanes past the end are not read again
                 if (v && k > 0 && kp == k - 1 && dup[k].w) len = 0;
+            }
+        } else if constexpr (RUN > 1) {
+#pragma unroll
+            for (int r = 1; r < RUN; ++r) ar[r] = 0;
+            if (dup) {   // uniform
+                const int kp = __shfl_up(k, 1);
+                const bool fol = v && l > 0 && k > 0 && kp == k - 1 && dup[k].w;
+                const unsigned long long fm = __ballot(fol);
+                const unsigned long long upto = (2ull << l) - 1;   // lanes 0..l
+                // lane 0 never follows: the run's first lane is the highest
+                // lane at or below l that does not follow
+                const int top = 63 - __clzll((long long)(~fm & upto));
+                const bool lead = !fol || (l - top) % RUN == 0;
+                const unsigned long long nxt = __ballot(lead) & ~upto;
+                rn = lead ? (nxt ? __ffsll((long long)nxt) - 1 - l : 64 - l) : 0;
+#pragma unroll
+                for (int r = 1; r < RUN; ++r) {
+                    const V x = bpermute_v(av, l + r < 64 ? l + r : 63);
+                    ar[r] = r < rn ? x : V(0);
+                }
+                if (!lead) len = 0;
             }
         }
         const int nent = (int)(a1 - c0 < 64 ? a1 - c0 : 64);
@@ -411,6 +467,16 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         const int64_t win_flat = (total + 63) / 64;
         // a flat window costs about twice a grouped one (entry walk)
         const bool grouped = lg <= 6 && win_grouped <= 2 * win_flat;
+        // loads of the run's further products (RUN > 1): position ix of the
+        // first row, rows of length el, crn entries in the run
+        auto load_run = [&](P &pv, bool ok, int64_t ix, int el, int crn) {
+#pragma unroll
+            for (int r = 1; r < RUN; ++r) {
+                const bool okr = ok && r < crn;
+                const V bw = bval[okr ? ix + (int64_t)r * el : 0];
+                pv.b[r] = okr ? bw : V(0);
+            }
+        };
         // windows wv, wv + nwaves, ... of nwin with D + 1 windows of loads in
         // flight: slot d is consumed, then refilled with the window D + 1
         // places ahead.  Windows past the last hold no products (every lane
@@ -420,30 +486,53 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
         auto pipelined = [&](int64_t nwin, auto &&fetchw) -> bool {
             constexpr int S = D + 1;
             int key[S];
-            V bv[S], a[S];
+            P pv[S];
             bool ok[S];
 #pragma unroll
-            for (int d = 0; d < S; ++d) fetchw(wv + (int64_t)nwaves * d, key[d], bv[d], a[d], ok[d]);
+            for (int d = 0; d < S; ++d) fetchw(wv + (int64_t)nwaves * d, key[d], pv[d], ok[d]);
             for (int64_t w = wv; w < nwin; w += (int64_t)nwaves * S) {
 #pragma unroll
                 for (int d = 0; d < S; ++d) {
-                    if constexpr (NUMERIC) f(ok[d], key[d], a[d] * bv[d]);
+                    if constexpr (NUMERIC) f(ok[d], key[d], pv[d].value());
                     else f(ok[d], key[d]);
                     if (stop()) return true;
-                    fetchw(w + (int64_t)nwaves * (d + S), key[d], bv[d], a[d], ok[d]);
+                    fetchw(w + (int64_t)nwaves * (d + S), key[d], pv[d], ok[d]);
                 }
             }
             return false;
         };
+        // one window at a time, the next one's loads issued before the
+        // current one is consumed
+        auto paired = [&](int64_t w, int64_t step, int64_t end, auto &&fetchw) {
+            int key, key1;
+            P pv, pv1;
+            bool ok, ok1;
+            fetchw(w, key, pv, ok);
+            while (true) {
+                const int64_t wn = w + step;
+                const bool more = wn < end;
+                fetchw(wn, key1, pv1, ok1);   // past the last window: no products
+                if constexpr (NUMERIC) f(ok, key, pv.value());
+                else f(ok, key);
+                if (!more || stop()) break;
+                w = wn;
+                key = key1;
+                pv = pv1;
+                ok = ok1;
+            }
+        };
 
         if (grouped) {
             const int g = l >> lg, r = l & ((1 << lg) - 1);
-            auto fetch = [&](int64_t w, int &key, V &bv, V &a, bool &ok) {
+            auto fetch = [&](int64_t w, int &key, P &pv, bool &ok) {
                 const int e = (int)w * per + g;
                 const int src = e < 64 ? e : 63;
                 const int64_t eb0 = bpermute64(b0, src);
                 const int elen = bpermute(len, src);
-                if constexpr (NUMERIC) a = bpermute_v(av, src);
+                if constexpr (NUMERIC) {
+#pragma unroll
+                    for (int q = 0; q < RUN; ++q) pv.a[q] = bpermute_v(ar[q], src);
+                }
                 ok = e < nent && r < elen;
                 // every lane loads (index 0 when it holds no product): no
                 // divergent branch around the loads, so that the wait before
@@ -453,43 +542,37 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                 key = ok ? kv : -1;
                 if constexpr (NUMERIC) {
                     const V bw = bval[ix];
-                    bv = ok ? bw : V(0);
+                    pv.b[0] = ok ? bw : V(0);
+                    if constexpr (RUN > 1) load_run(pv, ok, ix, elen, bpermute(rn, src));
                 }
             };
-            int64_t w = wv;
-            if (w >= win_grouped) continue;
+            if (wv >= win_grouped) continue;
             if constexpr (D > 1) {
                 if (pipelined(win_grouped, fetch)) break;
                 continue;
             }
-            int key, key1;
-            V bv = 0, bv1 = 0, a = 0, a1v = 0;
-            bool ok, ok1;
-            fetch(w, key, bv, a, ok);
-            while (true) {
-                const int64_t wn = w + nwaves;
-                const bool more = wn < win_grouped;
-                fetch(wn, key1, bv1, a1v, ok1);   // past the last window: no products
-                if constexpr (NUMERIC) f(ok, key, a * bv);
-                else f(ok, key);
-                if (!more || stop()) break;
-                w = wn;
-                key = key1;
-                bv = bv1;
-                a = a1v;
-                ok = ok1;
-            }
+            paired(wv, nwaves, win_grouped, fetch);
         } else {
             const int64_t incl = wave_incl_scan((int64_t)len);
             const int64_t off = incl - len;
             const int64_t base = b0 - off;
             const bool starts = len > 0;
-            auto fetch = [&](int64_t w0, int &key, V &bv, V &a, bool &ok) {
+            auto fetch = [&](int64_t w0, int &key, P &pv, bool &ok) {
                 const unsigned long long cov = __ballot(starts && off <= w0);
                 int s = 63 - __clzll((long long)cov);
                 int64_t cb = readlane64(base, s);
-                V ca = 0;
-                if constexpr (NUMERIC) ca = readlane_v(av, s);
+                int cl = 0, crn = 1;   // RUN > 1: the entry's row length and run
+                auto take = [&](int src) {
+                    if constexpr (NUMERIC) {
+#pragma unroll
+                        for (int q = 0; q < RUN; ++q) pv.a[q] = readlane_v(ar[q], src);
+                    }
+                    if constexpr (RUN > 1) {
+                        cl = __builtin_amdgcn_readlane(len, src);
+                        crn = __builtin_amdgcn_readlane(rn, src);
+                    }
+                };
+                take(s);
                 unsigned long long in = __ballot(starts && off > w0 && off < w0 + 64);
                 const int64_t p = w0 + l;
                 while (in) {
@@ -498,7 +581,7 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                     const int64_t os = readlane64(off, s);
                     if (p >= os) {
                         cb = readlane64(base, s);
-                        if constexpr (NUMERIC) ca = readlane_v(av, s);
+                        take(s);
                     }
                 }
                 ok = p < total;
@@ -507,41 +590,24 @@ __device__ __forceinline__ void row_products(int64_t a0, int64_t a1, const int32
                 key = ok ? kv : -1;
                 if constexpr (NUMERIC) {
                     const V bw = bval[ix];
-                    bv = ok ? bw : V(0);
+                    pv.b[0] = ok ? bw : V(0);
+                    if constexpr (RUN > 1) load_run(pv, ok, ix, cl, crn);
                 }
-                a = ca;
             };
             const int64_t stride = (int64_t)nwaves * 64;
-            int64_t w0 = (int64_t)wv * 64;
+            const int64_t w0 = (int64_t)wv * 64;
             if (w0 >= total) continue;
             if constexpr (D > 1) {
-                auto fetch_w = [&](int64_t w, int &key, V &bv, V &a, bool &ok) {
-                    fetch(w * 64, key, bv, a, ok);
+                auto fetch_w = [&](int64_t w, int &key, P &pv, bool &ok) {
+                    fetch(w * 64, key, pv, ok);
                 };
                 if (pipelined(win_flat, fetch_w)) break;
                 continue;
             }
-            int key, key1;
-            V bv = 0, bv1 = 0, a = 0, a1v = 0;
-            bool ok, ok1;
-            fetch(w0, key, bv, a, ok);
-            while (true) {
-                const int64_t wn = w0 + stride;
-                const bool more = wn < total;
-                fetch(wn, key1, bv1, a1v, ok1);   // past the last window: no products
-                if constexpr (NUMERIC) f(ok, key, a * bv);
-                else f(ok, key);
-                if (!more || stop()) break;
-                w0 = wn;
-                key = key1;
-                bv = bv1;
-                a = a1v;
-                ok = ok1;
-            }
+            paired(w0, stride, total, fetch);
         }
         if (stop()) break;
     }
 }
-
 
 }  // namespace opsp

@@ -48,6 +48,8 @@ struct opsp_plan {
     bool fp32 = false;                  // FP32 values (opsp_spgemm_f32)
     Counters *ctr = nullptr;            // device counters (numeric step), owned
     int2 *range = nullptr;              // output column range (lo, hi) per row (owned)
+    int4 *brec = nullptr;               // B row records with repeated-pattern flags, when
+                                        // the numeric step merges such entries (owned)
     opsp_stats stats = {};
 };
 
@@ -557,6 +559,8 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     ar.keep(ctrS);
     if (rng) ar.keep(rng);
     plan->range = rng;
+    if (dup) ar.keep(bfl);
+    plan->brec = dup ? bfl : nullptr;
     if (identity < 0) ar.keep(bins);
     plan->identity_bin = identity;
     plan->crpt = crpt;
@@ -589,6 +593,7 @@ opsp_status run_numeric(opsp_plan *plan, const opsp_csr *A, const opsp_csr *B, i
     na.cval = cval;
     na.ctr = plan->ctr;
     na.rng = plan->range;
+    na.brec = plan->brec;
     const int gb = NUM_GLOBAL_BIN;
     bool first = true;
     void *pk = nullptr, *pv = nullptr;
@@ -670,6 +675,8 @@ void plan_release(opsp_plan *plan, hipStream_t s) {
     if (plan->bins) (void)cache_free(plan->bins, s);
     if (plan->range) (void)cache_free(plan->range, s);
     plan->range = nullptr;
+    if (plan->brec) (void)cache_free(plan->brec, s);
+    plan->brec = nullptr;
     if (plan->ctr) (void)cache_free(plan->ctr - 1, s);  // both counters share one allocation
     plan->crpt = nullptr;
     plan->bins = nullptr;

@@ -192,6 +192,9 @@ struct NumArgs {
     int gv;                  // bin 0 variant (GROUP_GL / NUM_T0); the one-phase
                              // step uses variant 0
     int fp32;                // values are float (A, B, C and the tables); two-phase only
+    const int4 *brec;        // optional B row records with repeated-pattern flags
+                             // (launch_brange with dup): bins 1-6 merge runs of
+                             // entries whose B rows share one column set
 };
 hipError_t launch_numeric_bin(int bin, const NumArgs &a, hipStream_t s);
 // Bin 7 by bucketed dense accumulation (rows with a column range in `rng`;

@@ -105,3 +105,13 @@ def test_fp32_rectangular_banded_and_variants():
 def test_fp32_empty_and_degenerate():
     check32(syn.random_csr(40, 30, 0.0, seed=1), syn.random_csr(30, 20, 0.3, seed=2))
     check32(syn.random_csr(0, 10, 0.5, seed=3), syn.random_csr(10, 7, 0.5, seed=4))
+
+
+@pytest.mark.parametrize("forced", [-1, 2])
+def test_fp32_merged_runs(forced):
+    """Runs of entries whose B rows share one column set are merged by the
+    numeric step; each product is still rounded to float32 and the run's
+    products summed in FP64, so the (k+1) u S bound holds."""
+    import test_gpu_parity as tp
+    A, B = tp._runs_of_rows(20000, seed=92)
+    check32(A, B, cfg=_ops().Config(validate=1, force_num_bin=forced))

@@ -607,3 +607,75 @@ def test_symbolic_skips_repeated_row_patterns(forced):
     ops = _ops()
     A, B = _repeated_pattern_rows()
     check(A, B, cfg=ops.Config(validate=1, force_sym_bin=forced))
+
+
+def _runs_of_rows(N, seed, integer=False):
+    """B made of groups of 1, 2, 3, 4, 5 or 7 consecutive rows with one
+    column set (rows of 40, 64 or 100 entries); A rows that take whole
+    groups, stretches of 65-140 consecutive B rows (runs cross the 64-entry
+    chunks of a row), groups with a row left out, a lone group of 7 (longer
+    than a merged run) and random rows."""
+    rng = np.random.default_rng(seed)
+    brows, groups = [], []
+    for g in range(72):
+        R = [1, 2, 3, 4, 5, 7][g % 6]
+        L = [40, 64, 100][(g // 6) % 3]
+        pat = np.sort(rng.choice(N, L, replace=False))
+        groups.append((len(brows), R))
+        brows += [pat] * R
+    K = len(brows)
+    brpt = np.concatenate([[0], np.cumsum([len(r) for r in brows])]).astype(np.int64)
+    nb = int(brpt[-1])
+    ints = np.array([-3.0, -2.0, -1.0, 1.0, 2.0, 3.0])   # nonzero: no signed zeros in the sums
+    bval = rng.choice(ints, nb) if integer else rng.uniform(-1, 1, nb)
+    B = syn.CSR(K, N, brpt, np.concatenate(brows).astype(np.int32), bval)
+    arows = []
+    for i in range(300):
+        m = i % 5
+        if m == 0:
+            gs = rng.choice(len(groups), 5, replace=False)
+            cols = np.concatenate([np.arange(groups[x][0], groups[x][0] + groups[x][1]) for x in gs])
+        elif m == 1:
+            s0 = int(rng.integers(0, K - 140))
+            cols = np.arange(s0, s0 + int(rng.integers(65, 141)))
+        elif m == 2:
+            gs = rng.choice(len(groups), 5, replace=False)
+            parts = []
+            for x in gs:
+                s, R = groups[x]
+                c = np.arange(s, s + R)
+                parts.append(np.delete(c, int(rng.integers(R))) if R > 1 else c)
+            cols = np.concatenate(parts)
+        elif m == 3:
+            s = groups[5][0]
+            cols = np.arange(s, s + 7)
+        else:
+            cols = rng.choice(K, 12, replace=False)
+        arows.append(np.unique(cols))
+    arpt = np.concatenate([[0], np.cumsum([len(r) for r in arows])]).astype(np.int64)
+    na = int(arpt[-1])
+    aval = rng.choice(ints, na) if integer else rng.uniform(-1, 1, na)
+    A = syn.CSR(len(arows), K, arpt, np.concatenate(arows).astype(np.int32), aval)
+    return A, B
+
+
+@pytest.mark.parametrize("narrow", [False, True])
+@pytest.mark.parametrize("forced", [-1, 1, 2, 3, 4, 5, 6])
+def test_numeric_merges_repeated_row_patterns(forced, narrow):
+    """The numeric step hands a run of up to three entries whose B rows share
+    one column set to the run's first entry, which adds their summed
+    products once per column: the product must equal the oracle's in every
+    table kernel, with the dense accumulator of narrow rows (420 columns)
+    and with hashing (20,000 columns)."""
+    ops = _ops()
+    A, B = _runs_of_rows(420 if narrow else 20000, seed=91 + int(narrow))
+    check(A, B, cfg=ops.Config(validate=1, force_num_bin=forced))
+
+
+@pytest.mark.parametrize("forced", [-1, 1, 4])
+def test_numeric_merged_runs_exact(forced):
+    """Integer values: every merged sum is exact, so the product matches the
+    oracle bit for bit."""
+    ops = _ops()
+    A, B = _runs_of_rows(20000, seed=93, integer=True)
+    check(A, B, cfg=ops.Config(validate=1, force_num_bin=forced), exact=True)
