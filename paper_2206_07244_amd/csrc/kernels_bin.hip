@@ -62,12 +62,16 @@ __global__ __launch_bounds__(256) void k_setup(int64_t M, const int64_t *__restr
     __syncthreads();
     const bool range = rng != nullptr;   // column range of each row's output
 
-    // Short rows (the wave's longest at most 64 entries): every lane walks
-    // its own row, accumulating in registers; no per-entry row search and no
-    // LDS atomics.  Otherwise the wave walks the flat range of its rows'
-    // entries, so that one long row does not serialise a single lane.
+    // Short rows (the wave's longest at most 64 entries), or rows of up to
+    // 256 entries whose longest is at most twice the wave's mean (finite
+    // element rows: 81 entries for 3 unknowns on a 27-point stencil): every
+    // lane walks its own row, accumulating in registers; no per-entry row
+    // search and no LDS atomics.  Otherwise the wave walks the flat range of
+    // its rows' entries, so that one long row does not serialise a single
+    // lane.
     const int64_t my_len = (nrows > 0 && l < nrows) ? rs[w][l + 1] - rs[w][l] : 0;
-    const bool lane_rows = nrows > 0 && wave_max(my_len) <= 64;
+    const int64_t wmax = wave_max(my_len), wtot = nrows > 0 ? rs[w][64] - rs[w][0] : 0;
+    const bool lane_rows = nrows > 0 && (wmax <= 64 || (wmax <= 256 && wmax * nrows <= 2 * wtot));
     {
         // long rows go to the tile list: one reservation per wave (a 64-bit
         // add of its rows and tiles).  If the list is full, which only an A
@@ -597,6 +601,61 @@ hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, hipStream_t s) {
     if (B.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_brange, dim3((unsigned)((B.rows + 255) / 256)), dim3(256), 0, s, B.rows,
                        B.rpt, B.col, brec, dup ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Rows of A with the same columns as the row before them (rows of 1 to
+// DUP_MAX entries; the compare as in k_brange).
+__global__ __launch_bounds__(256) void k_arow_same(int64_t M, const int64_t *__restrict__ arpt,
+                                                   const int32_t *__restrict__ acol,
+                                                   uint8_t *__restrict__ same) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    int d = 0;
+    if (r > 0) {
+        const int64_t a0 = arpt[r], a1 = arpt[r + 1], p0 = arpt[r - 1], L = a1 - a0;
+        if (L > 0 && a0 - p0 == L && L <= DUP_MAX && acol[p0] == acol[a0] && acol[a0 - 1] == acol[a1 - 1]) {
+            int diff = 0;
+#pragma unroll 8
+            for (int64_t e = 1; e + 1 < L; ++e) diff |= acol[p0 + e] ^ acol[a0 + e];
+            d = diff == 0;
+        }
+    }
+    same[r] = (uint8_t)d;
+}
+
+// Distance of each row to the first row of its run of identical rows; a
+// row at a multiple of ARUN_CAP starts a run, so the walk back is short.
+__global__ __launch_bounds__(256) void k_arow_run(int64_t M, const int4 *__restrict__ brec,
+                                                  const uint8_t *__restrict__ same,
+                                                  uint8_t *__restrict__ arun) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    int d = 0;
+    while (((r - d) & (ARUN_CAP - 1)) != 0 && (brec ? brec[r - d].w : (int)same[r - d]) != 0) ++d;
+    arun[r] = (uint8_t)d;
+}
+
+__global__ __launch_bounds__(256) void k_arow_copy(int64_t M, const uint8_t *__restrict__ arun,
+                                                   int64_t *__restrict__ nnz) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    const int d = arun[r];
+    if (d) nnz[r] = nnz[r - d];   // the run's first row has d = 0: not written here
+}
+
+hipError_t launch_arun(const DevCSR &A, const int4 *brec, uint8_t *same, uint8_t *arun,
+                       hipStream_t s) {
+    if (A.rows == 0) return hipSuccess;
+    const dim3 grid((unsigned)((A.rows + 255) / 256));
+    if (!brec) hipLaunchKernelGGL(k_arow_same, grid, dim3(256), 0, s, A.rows, A.rpt, A.col, same);
+    hipLaunchKernelGGL(k_arow_run, grid, dim3(256), 0, s, A.rows, brec, (const uint8_t *)same, arun);
+    return hipGetLastError();
+}
+
+hipError_t launch_arun_copy(int64_t M, const uint8_t *arun, int64_t *nnz, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_arow_copy, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, M, arun, nnz);
     return hipGetLastError();
 }
 

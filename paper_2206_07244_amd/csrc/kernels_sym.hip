@@ -101,7 +101,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     RowSrc src, const int64_t *__restrict__ arpt, const int32_t *__restrict__ acol,
     const int64_t *__restrict__ brpt, const int32_t *__restrict__ bcol, int64_t *__restrict__ nnz,
     int abort_thr, Counters *__restrict__ ctr, int32_t *__restrict__ fail_list,
-    const int2 *__restrict__ rng, const int4 *__restrict__ brec) {
+    const int2 *__restrict__ rng, const int4 *__restrict__ brec, const uint8_t *__restrict__ arun) {
     constexpr bool WT = (W == 64);
     constexpr int R = WT ? 4 : 1;
     constexpr int NW = W / 64;  // waves per team
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
     const int64_t stride = PERSIST ? (int64_t)gridDim.x * R : src.nrows + R;
     for (int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * R; b0 < src.nrows; b0 += stride) {
         const int64_t idx = b0 + team;
-        const bool active = idx < src.nrows;
+        bool active = idx < src.nrows;
         // A row whose output columns span a range that fits a bitmap of at
         // most TP words (TP = the largest power of two <= T) is counted in
         // that bitmap (an atomic OR per product, a popcount at the end)
@@ -154,6 +154,12 @@ __global__ __launch_bounds__(W == 64 ? 256 : W) __attribute__((amdgpu_waves_per_
                         lgw = 31 - __builtin_clz((unsigned)nw);
                     }
                 }
+            }
+            // a row with the columns of the row before it is counted by its
+            // run's first row (the count is copied after the symbolic step)
+            if (arun && arun[row]) {
+                active = false;
+                bm = false;
             }
         }
         team_sync<WT>();   // the previous row of this team is done with the table
@@ -346,11 +352,11 @@ static hipError_t go_row(const SymArgs &a, hipStream_t s) {
     if (a.grid > 0)
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, true>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list, a.rng, a.brec);
+                           a.fail_list, a.rng, a.brec, a.arun);
     else
         hipLaunchKernelGGL((k_sym_row<W, T, ABORT, false>), dim3((unsigned)grid), dim3(W * R), 0, s,
                            a.src, a.A.rpt, a.A.col, a.B.rpt, a.B.col, a.nnz, a.abort_thr, a.ctr,
-                           a.fail_list, a.rng, a.brec);
+                           a.fail_list, a.rng, a.brec, a.arun);
     return hipGetLastError();
 }
 

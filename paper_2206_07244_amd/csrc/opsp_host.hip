@@ -455,6 +455,22 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     sa.rng = rng;
     sa.gv = gv;
     sa.brec = dup ? bfl : nullptr;
+    // rows of A with the columns of the row before them (the rows of one
+    // node) have the same count: only the first row of each run is counted,
+    // and the others copy it after the symbolic bins
+    uint8_t *arun = nullptr;
+    if (bfl && M > 1 && A->nnz >= DUP_MIN_AVG * M) {
+        const bool one = dup && A->rpt == B->rpt && A->col == B->col && A->rows == B->rows;
+        uint8_t *same = nullptr;
+        if (!one) {
+            CHK(ar.alloc(&p, (size_t)M));
+            same = (uint8_t *)p;
+        }
+        CHK(ar.alloc(&p, (size_t)M));
+        arun = (uint8_t *)p;
+        CHK(launch_arun(dA, one ? bfl : nullptr, same, arun, s));
+    }
+    sa.arun = arun;
     const bool need_slab = !rng || N > ((int64_t)SW_MAXPASS << SW_LG);
     int *slab = nullptr;
     int64_t slab_entries = 0;
@@ -526,6 +542,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
         CHK(launch_symbolic_bin(SYM_GLOBAL_BIN, global_args(gr), s));
     }
     CHK(fk.end());
+    if (arun) CHK(launch_arun_copy(M, arun, crpt, s));
     tm.mark();
 
     // 4 numeric binning, first pass with nnz(C)

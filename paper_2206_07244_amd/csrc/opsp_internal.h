@@ -90,6 +90,16 @@ inline BlockParts block_parts_at(void *p, int64_t M, int64_t nnzA) {
 // empty rows) as int4 records; .w = 1 when the row has the same columns as
 // the row before it (compared for rows of at most 256 entries).
 hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, hipStream_t s);
+// Rows of A with the columns of the row before them: arun[i] = distance of
+// row i to the first row of its run (0: counted itself); runs are cut at
+// multiples of ARUN_CAP rows.  `brec` (B's records with repeated-pattern
+// flags) stands in for the row compare when A and B are one matrix; else
+// `same` (M bytes) holds the compare.  launch_arun_copy gives each row the
+// symbolic count of its run's first row.
+constexpr int ARUN_CAP = 32;
+hipError_t launch_arun(const DevCSR &A, const int4 *brec, uint8_t *same, uint8_t *arun,
+                       hipStream_t s);
+hipError_t launch_arun_copy(int64_t M, const uint8_t *arun, int64_t *nnz, hipStream_t s);
 // Setup step fused with the first binning pass: n_prod per row into `nprod`,
 // per-block bin counts / totals / maxima into `parts` (which must come from
 // block_parts_at with A's nnz); optional features
@@ -145,6 +155,8 @@ struct SymArgs {
     int gv;                  // bin 0 variant (GROUP_GL / SYM_T0)
     const int4 *brec;        // optional B row records (launch_brange): rows that
                              // repeat the previous entry's column set are skipped
+    const uint8_t *arun;     // optional (launch_arun): rows of A counted by the
+                             // first row of their run are skipped (bins 1-7)
 };
 // Average B row length from which the symbolic step looks for repeated
 // row patterns.

@@ -487,6 +487,51 @@ def test_setup_long_rows_in_tiles(hash_all):
     oracle.compare(*C.to_host(), oracle.spgemm(A, B, rows=np.arange(lo, hi)), tol=TOL)
 
 
+def _setup_wave_lengths(seed=41):
+    """Row lengths per 64-row wave of the setup step: all 81; uniform in
+    65..256; one row of 256 among rows of 3 (longest above twice the mean);
+    one of 257 among rows of 200; 64 and 65 mixed; rows of 128 beside empty
+    ones (longest exactly twice the mean); a last partial wave of 10 rows of
+    200."""
+    rng = np.random.default_rng(seed)
+    waves = [[81] * 64,
+             list(rng.integers(65, 257, 64)),
+             [256] + [3] * 63,
+             [257] + [200] * 63,
+             [64, 65] * 32,
+             [128, 0] * 32,
+             [200] * 10]
+    return [int(x) for w in waves for x in w]
+
+
+@pytest.mark.parametrize("hash_all", [0, 1])
+def test_setup_rows_of_65_to_256_entries(hash_all):
+    """The setup step lets every lane walk its own row when the wave's rows
+    have at most 256 entries and the longest at most twice their mean, and
+    walks the flat entry range otherwise: n_prod, a_len and b_max per row
+    and the product must match the oracle on both sides of those limits."""
+    import torch
+    ops = _ops()
+    A = _rows_of_lengths(_setup_wave_lengths(), 3000, seed=42)
+    B = syn.random_csr(3000, 4000, 0.01, seed=43)
+    st = ops.Stats()
+    check(A, B, cfg=ops.Config(validate=1, hash_all_rows=hash_all), stats=st)
+    nprod, alen, bmax, _ = oracle.row_stats(A, B)
+    assert st.nprod == int(nprod.sum())
+    dA, dB = ops.DeviceCSR.from_host(A), ops.DeviceCSR.from_host(B)
+    al, npd, bm = ops.row_features(dA, dB)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(npd.cpu().numpy(), nprod)
+    np.testing.assert_array_equal(al.cpu().numpy(), alen)
+    np.testing.assert_array_equal(bm.cpu().numpy(), bmax)
+    # a view starting at row 7 shifts every wave's rows
+    lo, hi = 7, A.rows
+    view = ops.DeviceCSR(hi - lo, A.cols, dA.rpt[lo:hi + 1], dA.col, dA.val)
+    C = ops.spgemm(view, dB, config=ops.Config(validate=1, hash_all_rows=hash_all))
+    torch.cuda.synchronize()
+    oracle.compare(*C.to_host(), oracle.spgemm(A, B, rows=np.arange(lo, hi)), tol=TOL)
+
+
 @pytest.mark.parametrize("hash_all", [0, 1])
 def test_b_rows_of_65_to_128_entries(hash_all):
     """B rows of exactly 63-65, 100, 127-129 entries, around the limit of
@@ -679,3 +724,46 @@ def test_numeric_merged_runs_exact(forced):
     ops = _ops()
     A, B = _runs_of_rows(20000, seed=93, integer=True)
     check(A, B, cfg=ops.Config(validate=1, force_num_bin=forced), exact=True)
+
+
+def _runs_of_identical_rows(seed=51):
+    """A whose rows come in runs of identical column sets: runs of 1 to 70
+    rows (longer than the 32-row cut, and across it), rows of 50 to 300
+    entries (those above 256 are not compared), empty rows between runs;
+    B random with rows of 0 to 60 entries."""
+    rng = np.random.default_rng(seed)
+    K = 3000
+    rows = []
+    while len(rows) < 1500:
+        R = int(rng.choice([1, 2, 3, 5, 31, 33, 70]))
+        L = int(rng.choice([50, 81, 256, 257, 300]))
+        pat = np.sort(rng.choice(K, L, replace=False))
+        rows += [pat] * R
+        if rng.random() < 0.2:
+            rows.append(np.zeros(0, np.int64))
+    rpt = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    A = syn.CSR(len(rows), K, rpt, np.concatenate(rows).astype(np.int32),
+                rng.uniform(-1, 1, int(rpt[-1])))
+    blen = rng.integers(0, 61, K)
+    brows = [np.sort(rng.choice(5000, int(n), replace=False)) for n in blen]
+    brpt = np.concatenate([[0], np.cumsum(blen)]).astype(np.int64)
+    B = syn.CSR(K, 5000, brpt, np.concatenate(brows).astype(np.int32),
+                rng.uniform(-1, 1, int(brpt[-1])))
+    return A, B
+
+
+@pytest.mark.parametrize("forced", [-1, 1, 3, 7, 8])
+def test_symbolic_counts_runs_of_identical_rows(forced):
+    """Rows of A with the columns of the row before them are counted once
+    per run (runs cut every 32 rows) and the count copied: every row's
+    count must equal the oracle's whatever the symbolic kernel."""
+    ops = _ops()
+    A, B = _runs_of_identical_rows()
+    check(A, B, cfg=ops.Config(validate=1, force_sym_bin=forced))
+
+
+@pytest.mark.parametrize("g", [5, 8])
+def test_block_stencil_square_runs_of_identical_rows(g):
+    """C = A^2 for the 3x3-block stencil: A's rows of a node are identical,
+    flagged by the B row records of the same matrix."""
+    check(syn.block_stencil27(g, seed=g))
