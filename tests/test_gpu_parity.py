@@ -767,3 +767,16 @@ def test_block_stencil_square_runs_of_identical_rows(g):
     """C = A^2 for the 3x3-block stencil: A's rows of a node are identical,
     flagged by the B row records of the same matrix."""
     check(syn.block_stencil27(g, seed=g))
+
+
+@pytest.mark.parametrize("n,L", [(2000, 64), (700, 300)])
+def test_all_rows_identical(n, L):
+    """Every row of A = B has the same L columns: every B row repeats the
+    one before it (entries merged three at a time, rows of more than 256
+    entries not compared), and every A row after the first of its 32-row
+    block copies that row's count."""
+    rng = np.random.default_rng(n + L)
+    pat = np.sort(rng.choice(n, L, replace=False)).astype(np.int32)
+    rpt = np.arange(n + 1, dtype=np.int64) * L
+    A = syn.CSR(n, n, rpt, np.tile(pat, n), rng.uniform(-1, 1, n * L))
+    check(A)
