@@ -574,33 +574,51 @@ hipError_t launch_setup(const DevCSR &A, const DevCSR &B, int64_t *nprod, const 
 // symbolic step skips such a row when the A row also holds the one before
 // it), else it is zero.
 constexpr int64_t DUP_MAX = 256;
-__global__ __launch_bounds__(256) void k_brange(int64_t K, const int64_t *__restrict__ brpt,
-                                                const int32_t *__restrict__ bcol,
-                                                int4 *__restrict__ brec, int dup) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= K) return;
-    const int64_t b0 = brpt[k], b1 = brpt[k + 1];
-    // rows of up to DUP_MAX entries whose length and end columns match are
-    // compared in full; the compare has no early exit so that its loads
-    // can be in flight together
-    int d = 0;
-    if (dup && k > 0 && b1 > b0) {
-        const int64_t p0 = brpt[k - 1], L = b1 - b0;
-        if (b0 - p0 == L && L <= DUP_MAX && bcol[p0] == bcol[b0] && bcol[b0 - 1] == bcol[b1 - 1]) {
-            int diff = 0;
-#pragma unroll 8
-            for (int64_t e = 1; e + 1 < L; ++e) diff |= bcol[p0 + e] ^ bcol[b0 + e];
-            d = diff == 0;
-        }
-    }
-    brec[k] = b1 > b0 ? make_int4((int)(b1 - b0), bcol[b0], bcol[b1 - 1], d)
-                      : make_int4(0, INT_MAX, -1, 0);
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (threadIdx.x == 0) *p = 0ull;
 }
 
-hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_brange(int64_t K, const int64_t *__restrict__ brpt,
+                                                const int32_t *__restrict__ bcol,
+                                                int4 *__restrict__ brec, int dup,
+                                                unsigned long long *__restrict__ ndup) {
+    __shared__ unsigned int s_dup;   // flagged rows of the workgroup (with ndup)
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (ndup && threadIdx.x == 0) s_dup = 0u;
+    int d = 0;
+    if (k < K) {
+        const int64_t b0 = brpt[k], b1 = brpt[k + 1];
+        // rows of up to DUP_MAX entries whose length and end columns match
+        // are compared in full; the compare has no early exit so that its
+        // loads can be in flight together
+        if (dup && k > 0 && b1 > b0) {
+            const int64_t p0 = brpt[k - 1], L = b1 - b0;
+            if (b0 - p0 == L && L <= DUP_MAX && bcol[p0] == bcol[b0] && bcol[b0 - 1] == bcol[b1 - 1]) {
+                int diff = 0;
+#pragma unroll 8
+                for (int64_t e = 1; e + 1 < L; ++e) diff |= bcol[p0 + e] ^ bcol[b0 + e];
+                d = diff == 0;
+            }
+        }
+        brec[k] = b1 > b0 ? make_int4((int)(b1 - b0), bcol[b0], bcol[b1 - 1], d)
+                          : make_int4(0, INT_MAX, -1, 0);
+    }
+    if (ndup) {   // uniform: per-wave counts into LDS, one global atomic per workgroup
+        __syncthreads();
+        const unsigned long long m = __ballot(d != 0);
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(&s_dup, (unsigned int)__popcll(m));
+        __syncthreads();
+        if (threadIdx.x == 0 && s_dup) atomicAdd(ndup, (unsigned long long)s_dup);
+    }
+}
+
+hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, unsigned long long *ndup,
+                         hipStream_t s) {
+    if (!dup) ndup = nullptr;
+    if (ndup) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ndup);
     if (B.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_brange, dim3((unsigned)((B.rows + 255) / 256)), dim3(256), 0, s, B.rows,
-                       B.rpt, B.col, brec, dup ? 1 : 0);
+                       B.rpt, B.col, brec, dup ? 1 : 0, ndup);
     return hipGetLastError();
 }
 

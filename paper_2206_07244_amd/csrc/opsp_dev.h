@@ -66,7 +66,8 @@ struct Counters {
     unsigned int fail;              // rows abandoned by the LDS table (symbolic)
     unsigned int error;             // internal consistency failures
     unsigned long long sched[2];    // row counter, finished workgroups (take_row)
-    unsigned long long pad[4];
+    unsigned long long dups;        // B rows that repeat the row before them (k_brange)
+    unsigned long long pad[3];
 };
 
 // Counters of the one-phase (predicted-capacity) numeric step, zeroed

@@ -430,7 +430,7 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     // looks like a matrix of node blocks (long rows: 3 unknowns of a 27-point
     // node give 81); elsewhere the check would cost more than it finds
     const bool dup = bfl && B->nnz >= DUP_MIN_AVG * B->rows;
-    if (bfl) CHK(launch_brange(dB, bfl, dup, s));
+    if (bfl) CHK(launch_brange(dB, bfl, dup, &ctrS->dups, s));
     CHK(launch_setup(dA, dB, crpt, bs, parts, nullptr, nullptr, s, bfl, rng));
     tm.mark();   // setup (with the first binning pass fused in) done
     CHK(launch_finalize(M, bs.nslots, parts, ctrS, nullptr, false, s));
@@ -576,8 +576,14 @@ opsp_status run_symbolic(const opsp_csr *A, const opsp_csr *B, const opsp_config
     ar.keep(ctrS);
     if (rng) ar.keep(rng);
     plan->range = rng;
-    if (dup) ar.keep(bfl);
-    plan->brec = dup ? bfl : nullptr;
+    // the numeric bins merge runs of repeated B rows only when at least a
+    // third of B's rows repeat the row before them: the merged kernels cost
+    // more registers and lane permutes per window (wide rows without
+    // repeats: numeric 3.3 -> 5.1 ms), and pay off on node blocks (two
+    // thirds repeated: 4.5 -> 2.3 ms)
+    const bool merge = dup && hc[0].dups * 3 >= (unsigned long long)B->rows;
+    if (merge) ar.keep(bfl);
+    plan->brec = merge ? bfl : nullptr;
     if (identity < 0) ar.keep(bins);
     plan->identity_bin = identity;
     plan->crpt = crpt;

@@ -89,7 +89,10 @@ inline BlockParts block_parts_at(void *p, int64_t M, int64_t nnzA) {
 // Length, first and last column of every row of B (0, INT_MAX, -1 for
 // empty rows) as int4 records; .w = 1 when the row has the same columns as
 // the row before it (compared for rows of at most 256 entries).
-hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, hipStream_t s);
+// With `dup`, the fourth field flags a row that repeats the row before it,
+// and `ndup` (optional; zeroed first) receives the number of flagged rows.
+hipError_t launch_brange(const DevCSR &B, int4 *brec, bool dup, unsigned long long *ndup,
+                         hipStream_t s);
 // Rows of A with the columns of the row before them: arun[i] = distance of
 // row i to the first row of its run (0: counted itself); runs are cut at
 // multiples of ARUN_CAP rows.  `brec` (B's records with repeated-pattern

@@ -146,7 +146,7 @@ opsp_status run_learned(const opsp_csr *A, const opsp_csr *B, opsp_csr *C, const
     // 1-2 setup, capacities, numeric bins by capacity, slot offsets
     tm.mark();
     CHK(hipMemsetAsync(&dc->lc, 0, sizeof(LearnedCounters) - offsetof(LearnedCounters, lc), s));
-    if (bfl) CHK(launch_brange(dB, bfl, false, s));
+    if (bfl) CHK(launch_brange(dB, bfl, false, nullptr, s));
     CHK(launch_setup(dA, dB, np, bs, parts, alen, bmax, s, bfl, rng));
     CapArgs ca;
     memset(&ca, 0, sizeof(ca));

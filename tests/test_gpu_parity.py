@@ -780,3 +780,30 @@ def test_all_rows_identical(n, L):
     rpt = np.arange(n + 1, dtype=np.int64) * L
     A = syn.CSR(n, n, rpt, np.tile(pat, n), rng.uniform(-1, 1, n * L))
     check(A)
+
+
+@pytest.mark.parametrize("share", [0.0, 0.2, 0.4])
+def test_repeated_rows_below_and_above_merge_share(share):
+    """B rows of 64 entries of which a given share repeat the row before
+    them: the numeric step merges runs only from a third of B's rows up,
+    the symbolic step skips repeats at any share; the product must match
+    the oracle either way."""
+    rng = np.random.default_rng(int(share * 10) + 61)
+    N, K = 6000, 900
+    rows = []
+    while len(rows) < K:
+        pat = np.sort(rng.choice(N, 64, replace=False))
+        rows.append(pat)
+        if rng.random() < share / (1 - share) and len(rows) < K:
+            rows.append(pat)
+    rows = rows[:K]
+    brpt = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    B = syn.CSR(K, N, brpt, np.concatenate(rows).astype(np.int32), rng.uniform(-1, 1, int(brpt[-1])))
+    arows = []
+    for i in range(500):
+        s0 = int(rng.integers(0, K - 12))
+        arows.append(np.arange(s0, s0 + int(rng.integers(4, 12))))
+    arpt = np.concatenate([[0], np.cumsum([len(r) for r in arows])]).astype(np.int64)
+    A = syn.CSR(len(arows), K, arpt, np.concatenate(arows).astype(np.int32),
+                rng.uniform(-1, 1, int(arpt[-1])))
+    check(A, B)
