@@ -807,3 +807,17 @@ def test_repeated_rows_below_and_above_merge_share(share):
     A = syn.CSR(len(arows), K, arpt, np.concatenate(arows).astype(np.int32),
                 rng.uniform(-1, 1, int(arpt[-1])))
     check(A, B)
+
+
+def test_runs_of_identical_rows_in_a_view():
+    """A view of A's rows 5.. (row pointer not starting at zero): the runs of
+    identical rows are found from the view's own rows."""
+    import torch
+    ops = _ops()
+    A, B = _runs_of_identical_rows(seed=52)
+    dA, dB = ops.DeviceCSR.from_host(A), ops.DeviceCSR.from_host(B)
+    lo, hi = 5, A.rows
+    view = ops.DeviceCSR(hi - lo, A.cols, dA.rpt[lo:hi + 1], dA.col, dA.val)
+    C = ops.spgemm(view, dB, config=ops.Config(validate=1))
+    torch.cuda.synchronize()
+    oracle.compare(*C.to_host(), oracle.spgemm(A, B, rows=np.arange(lo, hi)), tol=TOL)
